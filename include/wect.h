@@ -1,0 +1,228 @@
+/*
+ * wect.h -- C ABI of the MI355X (gfx950) weighted Euler characteristic
+ * transform library (libwect.so).
+ *
+ * What is computed (paper: "Tensor Computation of Euler Characteristic
+ * Functions and Transforms"):
+ *
+ *   out[b][p][q] = sum over cells c of complex b with  f_p^max(c) <= thr[q]
+ *                  of (-1)^dim(c) * w(c)
+ *
+ * i.e. the weighted Euler characteristic (Definition "Weighted Euler
+ * Characteristic") of the lower-star filtration (Definition "Lower-Star
+ * Filtrations", test <=) of the height function h_p(v) = l(v) . s_p
+ * (Definition "Vertex Height Functions and Directional Filtrations"),
+ * sampled at the stored thresholds: the WECT of Definition "Weighted Euler
+ * Characteristic Transform", computed as in Algorithm 1 / Example "WECT as a
+ * special case" (filter values = coordinates times directions).
+ *
+ * Numerics fixed by this library:
+ *   - heights are float32, round to nearest even, no fused multiply-add,
+ *     evaluated as ((x*sx) + (y*sy)) + (z*sz);
+ *   - a cell's value is the maximum of its vertices' heights and it enters at
+ *     the first stored threshold at or above that value; a value above
+ *     thr[T-1] enters at no threshold;
+ *   - integer weights accumulate in int32 with wrap-around (exact whenever
+ *     every result fits in int32); float32 weights accumulate in float32
+ *     per block and are combined in float64.
+ *
+ * Memory: every data pointer is a DEVICE pointer owned by the caller; the
+ * library keeps no pointer after a call returns.  Sizes and counts in the
+ * structs are HOST values.  All arrays are dense, row-major, naturally
+ * aligned.
+ *
+ * Asynchrony: wect_forward / wect_backward / wect_batched only check the
+ * host-side metadata, then enqueue kernels on `hip_stream` (a hipStream_t,
+ * NULL = the null stream) and return.  They never allocate, synchronise or
+ * read device memory, so they may be captured into a HIP graph.  Data
+ * errors (vertex ids out of range, unsorted thresholds, NaN) are detected
+ * only by wect_validate.  On any error status nothing is enqueued and the
+ * outputs are untouched.  Outputs are overwritten, never accumulated.
+ *
+ * Thread safety: the entry points may be called concurrently from several
+ * host threads on different streams with different workspaces.
+ */
+#ifndef WECT_H
+#define WECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WECT_OK = 0,
+  WECT_ERR_ARG = 1,          /* invalid metadata: null pointer, bad size, bad enum value */
+  WECT_ERR_INDEX = 2,        /* wect_validate: vertex id out of range, or inconsistent offsets/shapes */
+  WECT_ERR_THRESHOLDS = 3,   /* wect_validate: thresholds not non-decreasing, or an axis not strictly increasing */
+  WECT_ERR_NONFINITE = 4,    /* wect_validate: NaN or Inf in coordinates, directions, thresholds or weights */
+  WECT_ERR_WORKSPACE = 5,    /* workspace pointer missing or smaller than wect_workspace_bytes() */
+  WECT_ERR_UNSUPPORTED = 6,  /* valid request outside what the kernels implement (e.g. T too large) */
+  WECT_ERR_DEVICE = 7        /* a HIP runtime call failed (no device, launch failure, ...) */
+} wect_status;
+
+typedef enum {
+  WECT_W_ONES = 0,        /* w(c) = 1 for every cell: the Euler characteristic transform */
+  WECT_W_EXPLICIT = 1,    /* simplicial: one weight per simplex, weights[i] has count[i] entries */
+  WECT_W_VERTEX_MAX = 2   /* w(c) = max of its vertices' weights (caption of Figure 1);
+                             simplicial: weights[0] = float32 [count[0]] vertex weights;
+                             cubical: the vertex weight is the voxel intensity */
+} wect_wmode;
+
+typedef enum { WECT_I32 = 0, WECT_F32 = 1 } wect_dtype;   /* dtype of the weights == dtype of out */
+typedef enum { WECT_SIMPLICIAL = 0, WECT_CUBICAL = 1 } wect_kind;
+
+/*
+ * One complex (B == 1) or a batch of B complexes stored back to back with
+ * CSR offsets (the paper's input structure "Complex", Section "Computation of
+ * WECFs": vertex filter data and weights, then per dimension i a list of
+ * i-simplices as rows of i+1 vertex ids and their weights).
+ */
+typedef struct {
+  int32_t kind;     /* wect_kind */
+  int32_t n;        /* ambient dimension: simplicial 1..3, cubical 2 or 3 */
+  int32_t B;        /* number of complexes, >= 1 */
+  int32_t top_dim;  /* simplicial: highest dimension present, 0..3 */
+  int32_t wmode;    /* wect_wmode */
+  int32_t dtype;    /* wect_dtype; WECT_F32 requires wmode EXPLICIT or VERTEX_MAX (simplicial) */
+
+  /* ---- simplicial ---- */
+  const float* coords;              /* [count[0], n] vertex coordinates l(v) */
+  const int64_t* vert_off;          /* [B+1] vertex offsets (vert_off[0] = 0); NULL allowed iff B == 1 */
+  int64_t count[4];                 /* totals over the batch: vertices, edges, triangles, tetrahedra;
+                                       count[i] = 0 for i > top_dim */
+  const int32_t* simplices[4];      /* simplices[i]: [count[i], i+1] vertex ids, numbered locally
+                                       within their complex (0 .. V_b-1); simplices[0] unused */
+  const int64_t* simp_off[4];       /* simp_off[i]: [B+1] offsets of complex b's i-simplices;
+                                       NULL allowed iff B == 1; simp_off[0] unused (vert_off) */
+  const void* weights[4];           /* EXPLICIT: weights[i] = [count[i]] of dtype (weights[0] = vertices);
+                                       VERTEX_MAX: weights[0] = float32 [count[0]]; ONES: unused */
+
+  /* ---- cubical (implicit grid; vertex = voxel with intensity > include_above,
+          every axis-aligned edge/square/cube whose corners are all vertices is
+          a cell, sign (-1)^dim; VERTEX_MAX weight = max corner intensity) ---- */
+  const int32_t* shape;             /* [B, 3] extents (n0, n1, n2) with axis 0 fastest; n2 = 1 when n == 2 */
+  const int64_t* grid_off;          /* [B+1] voxel offsets into `intensity`; NULL allowed iff B == 1 */
+  const uint8_t* intensity;         /* all voxels, complex after complex, axis 0 fastest */
+  const float* axis;                /* per complex n0 (+ n1 (+ n2)) coordinates: axis 0, then 1, then 2,
+                                       each strictly increasing */
+  const int64_t* axis_off;          /* [B+1] offsets into `axis`; NULL allowed iff B == 1 */
+  int64_t total_voxels;             /* sum of n0*n1*n2 over the batch */
+  int32_t include_above;            /* voxel is a vertex iff intensity > include_above (-1: all) */
+  int32_t reserved;
+} wect_complex;
+
+/* Sampling grid of the transform: d directions s_p (rows, used as stored,
+ * not renormalised) and T thresholds thr[0] <= ... <= thr[T-1]. */
+typedef struct {
+  const float* dirs;   /* [d, n] */
+  int32_t d;
+  int32_t T;
+  const float* thr;    /* [T] */
+} wect_grid;
+
+/*
+ * Size in bytes of the device workspace that wect_forward (with_backward = 0),
+ * wect_backward or wect_batched (with_backward = 1) need for this request on
+ * the current device.  Returns 0 when the request is invalid (the call itself
+ * would then return its error status) or when no workspace is needed.
+ */
+size_t wect_workspace_bytes(const wect_complex* c, const wect_grid* g, int with_backward);
+
+/*
+ * Forward transform (Algorithm 1 specialised to height filters, Example
+ * "WECT as a special case").
+ *   out: [B, d, T] int32 (dtype I32) or float32 (dtype F32), overwritten.
+ *   ws:  device workspace of at least wect_workspace_bytes(c, g, 0) bytes.
+ * Errors: WECT_ERR_ARG (metadata), WECT_ERR_WORKSPACE, WECT_ERR_UNSUPPORTED,
+ * WECT_ERR_DEVICE (launch failed).
+ */
+wect_status wect_forward(const wect_complex* c, const wect_grid* g, void* out,
+                         void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Adjoint of the forward with respect to the weights (simplicial, float32
+ * weights).  The forward is linear in the cell weights, so for
+ * L = sum_{b,p,q} grad_out[b][p][q] * out[b][p][q]:
+ *   dL/dw(c) = (-1)^dim(c) * sum_p sum_{q : f_p^max(c) <= thr[q]} grad_out[b][p][q]
+ * (a reverse scan of grad_out along the thresholds, read at each cell's
+ * threshold index).  The paper lists differentiable transforms as future work
+ * (Section "Discussion"); this is the derivative of its Algorithm 1 output.
+ *   grad_out:    [B, d, T] float32.
+ *   grad_w:      EXPLICIT: array of 4 pointers, grad_w[i] = [count[i]] float32 or NULL (skipped).
+ *   grad_vertex: VERTEX_MAX: [count[0]] float32; each cell's gradient goes to the
+ *                lowest-numbered vertex attaining the maximum vertex weight.
+ * Gradients with respect to coordinates, directions and thresholds are zero
+ * almost everywhere (the output is piecewise constant in them) and are not
+ * produced.  Outputs are overwritten.  Float32 accumulation order is not fixed.
+ */
+wect_status wect_backward(const wect_complex* c, const wect_grid* g, const float* grad_out,
+                          float* const grad_w[4], float* grad_vertex,
+                          void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Forward and, when grad_out != NULL, backward for a batch of complexes of
+ * uneven size, each a single persistent launch over the whole batch; the call
+ * sequence is capture-safe, so the pair can be replayed from one HIP graph.
+ * Same arguments as wect_forward / wect_backward; ws must hold
+ * wect_workspace_bytes(c, g, grad_out != NULL) bytes.
+ */
+wect_status wect_batched(const wect_complex* c, const wect_grid* g, void* out,
+                         const float* grad_out, float* const grad_w[4], float* grad_vertex,
+                         void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Synchronous data check on `hip_stream`: CSR offsets and shapes consistent
+ * with the counts, vertex ids in range, thresholds non-decreasing, axes
+ * strictly increasing, no NaN/Inf in coordinates, directions, thresholds or
+ * float weights.  Returns the first failing class (INDEX, THRESHOLDS,
+ * NONFINITE) or WECT_OK.  Allocates and synchronises: not for graph capture.
+ */
+wect_status wect_validate(const wect_complex* c, const wect_grid* g, void* hip_stream);
+
+/* Static, NUL-terminated description of a status code. */
+const char* wect_status_string(wect_status s);
+
+/*
+ * Launch shape used by the following calls of this process (for tuning).
+ * block: threads per block of the main kernels (256, 512 or 1024; 0 = default);
+ * blocks_per_cu: main-kernel blocks per compute unit (0 = default);
+ * min_items_per_block: lower bound of stream items per block (0 = default).
+ * Changing it changes wect_workspace_bytes().  Not to be called while other
+ * threads are inside wect_* calls.
+ */
+typedef struct {
+  int32_t block;
+  int32_t blocks_per_cu;
+  int32_t min_items_per_block;
+  int32_t reserved;
+} wect_launch;
+
+wect_status wect_set_launch(const wect_launch* l);
+wect_status wect_get_launch(wect_launch* l);
+
+/*
+ * Kernel timing for measurement.  When enabled, every following call records
+ * HIP events on its own stream around its main kernel (the histogram kernel
+ * of the forward, the adjoint kernel of the backward); wect_profile_read
+ * synchronises those events and returns the summed durations and launch
+ * counts since the last reset.  Event recording is not capture-safe: leave
+ * it disabled while capturing.
+ */
+wect_status wect_profile_enable(int on);
+wect_status wect_profile_read(double* fwd_ms, int64_t* fwd_launches,
+                              double* bwd_ms, int64_t* bwd_launches, int reset);
+
+/* Library version string, e.g. "wect 0.1 gfx950". */
+const char* wect_version(void);
+
+/* Description of the last HIP failure behind a WECT_ERR_DEVICE returned on
+ * the calling thread ("" if none).  Valid until the next call on the thread. */
+const char* wect_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WECT_H */

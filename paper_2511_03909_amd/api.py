@@ -1,0 +1,353 @@
+"""Python binding of libwect.so: argument marshalling only.
+
+Every step of the transform runs in the HIP kernels behind the C ABI
+(include/wect.h).  PyTorch provides device memory and the current stream;
+nothing here computes any part of the transform.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = [
+    "Grid", "SimplicialBatch", "CubicalBatch", "wect_workspace_bytes", "wect_forward", "wect_backward",
+    "wect_batched", "wect_validate", "set_launch", "get_launch", "profile_enable", "profile_read",
+    "WECTFunction", "wect", "WECT",
+]
+
+_WMODES = {"ones": L.WECT_W_ONES, "explicit": L.WECT_W_EXPLICIT, "vertex_max": L.WECT_W_VERTEX_MAX}
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr() if t.numel() > 0 else None
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Grid:
+    """Directions [d, n] and thresholds [T] (float32, device)."""
+
+    def __init__(self, dirs, thr, device="cuda"):
+        self.dirs = torch.as_tensor(np.ascontiguousarray(dirs, dtype=np.float32) if isinstance(dirs, np.ndarray)
+                                    else dirs).to(device=device, dtype=torch.float32).contiguous()
+        self.thr = torch.as_tensor(np.ascontiguousarray(thr, dtype=np.float32) if isinstance(thr, np.ndarray)
+                                   else thr).to(device=device, dtype=torch.float32).contiguous()
+        self.d = int(self.dirs.shape[0])
+        self.T = int(self.thr.shape[0])
+
+    def struct(self) -> L.WectGrid:
+        return L.WectGrid(_ptr(self.dirs), self.d, self.T, _ptr(self.thr))
+
+
+class SimplicialBatch:
+    """B simplicial complexes packed back to back on the device (CSR offsets).
+
+    coords [sum V, n] float32; simplices[i] [sum k_i, i+1] int32 with vertex ids
+    local to their complex; weights per ``wmode``: 'ones' (none), 'explicit'
+    (list per dimension, int32 or float32), 'vertex_max' ([w] float32 [sum V]).
+    """
+
+    def __init__(self, coords, simplices, wmode, weights, vert_off=None, simp_off=None, B=1):
+        self.coords = coords
+        self.simplices = list(simplices)
+        self.top_dim = len(self.simplices) - 1
+        self.wmode = wmode
+        self.weights = list(weights)
+        self.vert_off = vert_off
+        self.simp_off = simp_off or [None] * 4
+        self.B = int(B)
+        self.n = int(coords.shape[1])
+        self.device = coords.device
+        if wmode == "ones":
+            self.dtype = L.WECT_I32
+        elif wmode == "vertex_max":
+            self.dtype = L.WECT_F32
+        else:
+            self.dtype = L.WECT_F32 if self.weights[0].dtype == torch.float32 else L.WECT_I32
+
+    @property
+    def counts(self) -> List[int]:
+        c = [int(self.coords.shape[0])]
+        for i in range(1, self.top_dim + 1):
+            c.append(int(self.simplices[i].shape[0]))
+        return c
+
+    def with_weights(self, weights) -> "SimplicialBatch":
+        s = SimplicialBatch(self.coords, self.simplices, self.wmode, list(weights), self.vert_off,
+                            self.simp_off, self.B)
+        return s
+
+    @classmethod
+    def from_host(cls, complexes: Sequence, device="cuda") -> "SimplicialBatch":
+        """Pack host complexes (objects with coords, simplices, wmode, weights)."""
+        complexes = list(complexes)
+        B = len(complexes)
+        top = max(len(K.simplices) - 1 for K in complexes)
+        n = complexes[0].coords.shape[1]
+        wmode = complexes[0].wmode
+        coords = np.concatenate([np.asarray(K.coords, np.float32) for K in complexes])
+        vcount = [K.coords.shape[0] for K in complexes]
+        simp = [None]
+        offs: list = [None]
+        for i in range(1, top + 1):
+            parts = [np.asarray(K.simplices[i], np.int32).reshape(-1, i + 1) if i < len(K.simplices)
+                     and K.simplices[i] is not None else np.zeros((0, i + 1), np.int32) for K in complexes]
+            simp.append(np.concatenate(parts))
+            offs.append(np.concatenate([[0], np.cumsum([p.shape[0] for p in parts])]).astype(np.int64))
+        weights = []
+        if wmode == "explicit":
+            for i in range(top + 1):
+                weights.append(np.concatenate([np.asarray(K.weights[i]) for K in complexes]))
+        elif wmode == "vertex_max":
+            weights.append(np.concatenate([np.asarray(K.weights[0], np.float32) for K in complexes]))
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        vert_off = T(np.concatenate([[0], np.cumsum(vcount)]).astype(np.int64)) if B > 1 else None
+        simp_off = [None] + [T(o) for o in offs[1:]] if B > 1 else None
+        return cls(T(coords), [None] + [T(s) for s in simp[1:]], wmode, [T(w) for w in weights],
+                   vert_off, simp_off, B)
+
+    def struct(self) -> L.WectComplex:
+        c = L.WectComplex()
+        c.kind = L.WECT_SIMPLICIAL
+        c.n = self.n
+        c.B = self.B
+        c.top_dim = self.top_dim
+        c.wmode = _WMODES[self.wmode]
+        c.dtype = self.dtype
+        c.coords = _ptr(self.coords)
+        c.vert_off = _ptr(self.vert_off)
+        cnt = self.counts
+        for i in range(4):
+            c.count[i] = cnt[i] if i < len(cnt) else 0
+            c.simplices[i] = _ptr(self.simplices[i]) if 1 <= i <= self.top_dim else None
+            c.simp_off[i] = _ptr(self.simp_off[i]) if (1 <= i <= self.top_dim and self.simp_off) else None
+            c.weights[i] = _ptr(self.weights[i]) if i < len(self.weights) else None
+        return c
+
+
+class CubicalBatch:
+    """B uint8 images (n = 2) or volumes (n = 3) on the device.
+
+    intensity: all voxels back to back, axis 0 fastest; shape [B, 3] int32
+    (n2 = 1 for images); axis: per complex n0 + n1 (+ n2) float32 coordinates."""
+
+    def __init__(self, n, intensity, shape, grid_off, axis, axis_off, include_above, weighted, B):
+        self.n = int(n)
+        self.intensity = intensity
+        self.shape = shape
+        self.grid_off = grid_off
+        self.axis = axis
+        self.axis_off = axis_off
+        self.include_above = int(include_above)
+        self.weighted = bool(weighted)
+        self.B = int(B)
+        self.total_voxels = int(intensity.numel())
+        self.device = intensity.device
+
+    @classmethod
+    def from_host(cls, images: Sequence, device="cuda") -> "CubicalBatch":
+        images = list(images)
+        B = len(images)
+        n = images[0].intensity.ndim
+        shapes, flat, axes, gv, av = [], [], [], [0], [0]
+        for C in images:
+            I = np.asarray(C.intensity, np.uint8)
+            sxyz = list(I.shape[::-1]) + [1] * (3 - I.ndim)
+            shapes.append(sxyz)
+            flat.append(np.ascontiguousarray(I).ravel())
+            ax = np.concatenate([np.asarray(a, np.float32) for a in C.axes])
+            axes.append(ax)
+            gv.append(gv[-1] + I.size)
+            av.append(av[-1] + ax.size)
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        inc = images[0].include_above
+        return cls(n, T(np.concatenate(flat)), T(np.array(shapes, np.int32)),
+                   T(np.array(gv, np.int64)) if B > 1 else None, T(np.concatenate(axes)),
+                   T(np.array(av, np.int64)) if B > 1 else None, inc, images[0].weighted, B)
+
+    def struct(self) -> L.WectComplex:
+        c = L.WectComplex()
+        c.kind = L.WECT_CUBICAL
+        c.n = self.n
+        c.B = self.B
+        c.top_dim = self.n
+        c.wmode = L.WECT_W_VERTEX_MAX if self.weighted else L.WECT_W_ONES
+        c.dtype = L.WECT_I32
+        c.shape = _ptr(self.shape)
+        c.grid_off = _ptr(self.grid_off)
+        c.intensity = _ptr(self.intensity)
+        c.axis = _ptr(self.axis)
+        c.axis_off = _ptr(self.axis_off)
+        c.total_voxels = self.total_voxels
+        c.include_above = self.include_above
+        return c
+
+    @property
+    def dtype(self):
+        return L.WECT_I32
+
+
+def _out_dtype(cx):
+    return torch.float32 if cx.dtype == L.WECT_F32 else torch.int32
+
+
+def wect_workspace_bytes(cx, grid: Grid, with_backward: bool = False) -> int:
+    c, g = cx.struct(), grid.struct()
+    return int(L.lib().wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), int(with_backward)))
+
+
+def _workspace(cx, grid, with_backward, ws):
+    need = wect_workspace_bytes(cx, grid, with_backward)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
+    return ws, max(need, int(ws.numel()))
+
+
+def wect_forward(cx, grid: Grid, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Forward transform -> out [B, d, T] (int32 or float32); see wect_forward in wect.h."""
+    if out is None:
+        out = torch.empty((cx.B, grid.d, grid.T), dtype=_out_dtype(cx), device=cx.device)
+    ws, nbytes = _workspace(cx, grid, False, ws)
+    c, g = cx.struct(), grid.struct()
+    st = L.lib().wect_forward(ctypes.byref(c), ctypes.byref(g), _ptr(out), _ptr(ws), ctypes.c_size_t(int(ws.numel())),
+                              _stream(cx.device))
+    L.check(st, "wect_forward")
+    return out
+
+
+def _grad_outputs(cx):
+    if cx.wmode == "vertex_max":
+        return None, torch.empty(cx.counts[0], dtype=torch.float32, device=cx.device)
+    gw = [torch.empty(k, dtype=torch.float32, device=cx.device) for k in cx.counts]
+    return gw, None
+
+
+def _gw_array(gw):
+    arr = (ctypes.c_void_p * 4)()
+    if gw is not None:
+        for i, t in enumerate(gw):
+            arr[i] = _ptr(t)
+    return arr
+
+
+def wect_backward(cx, grid: Grid, grad_out: torch.Tensor, ws: Optional[torch.Tensor] = None):
+    """Adjoint with respect to the weights: list per dimension (explicit) or [V] (vertex_max)."""
+    grad_out = grad_out.to(dtype=torch.float32).contiguous()
+    gw, gv = _grad_outputs(cx)
+    ws, nbytes = _workspace(cx, grid, True, ws)
+    c, g = cx.struct(), grid.struct()
+    st = L.lib().wect_backward(ctypes.byref(c), ctypes.byref(g), _ptr(grad_out), _gw_array(gw), _ptr(gv),
+                               _ptr(ws), ctypes.c_size_t(int(ws.numel())), _stream(cx.device))
+    L.check(st, "wect_backward")
+    return gv if gv is not None else gw
+
+
+def wect_batched(cx, grid: Grid, grad_out: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                 grads=None, ws: Optional[torch.Tensor] = None):
+    """Forward (+ backward when grad_out is given) for a batch in one call.
+    Returns (out, grads) with grads None when grad_out is None."""
+    if out is None:
+        out = torch.empty((cx.B, grid.d, grid.T), dtype=_out_dtype(cx), device=cx.device)
+    gw = gv = None
+    if grad_out is not None:
+        grad_out = grad_out.to(dtype=torch.float32).contiguous()
+        if grads is None:
+            gw, gv = _grad_outputs(cx)
+        elif cx.wmode == "vertex_max":
+            gv = grads
+        else:
+            gw = grads
+    ws, nbytes = _workspace(cx, grid, grad_out is not None, ws)
+    c, g = cx.struct(), grid.struct()
+    st = L.lib().wect_batched(ctypes.byref(c), ctypes.byref(g), _ptr(out), _ptr(grad_out), _gw_array(gw), _ptr(gv),
+                              _ptr(ws), ctypes.c_size_t(int(ws.numel())), _stream(cx.device))
+    L.check(st, "wect_batched")
+    if grad_out is None:
+        return out, None
+    return out, (gv if gv is not None else gw)
+
+
+def wect_validate(cx, grid: Grid) -> None:
+    """Synchronous data check; raises WectError on the first failing class."""
+    c, g = cx.struct(), grid.struct()
+    L.check(L.lib().wect_validate(ctypes.byref(c), ctypes.byref(g), _stream(cx.device)), "wect_validate")
+
+
+def set_launch(block: int = 0, blocks_per_cu: int = 0, min_items_per_block: int = 0) -> None:
+    L.check(L.lib().wect_set_launch(ctypes.byref(L.WectLaunch(block, blocks_per_cu, min_items_per_block, 0))),
+            "wect_set_launch")
+
+
+def get_launch() -> dict:
+    w = L.WectLaunch()
+    L.check(L.lib().wect_get_launch(ctypes.byref(w)), "wect_get_launch")
+    return {"block": w.block, "blocks_per_cu": w.blocks_per_cu, "min_items_per_block": w.min_items_per_block}
+
+
+def profile_enable(on: bool = True) -> None:
+    L.check(L.lib().wect_profile_enable(int(on)), "wect_profile_enable")
+
+
+def profile_read(reset: bool = True) -> dict:
+    fm, bm = ctypes.c_double(), ctypes.c_double()
+    fl, bl = ctypes.c_int64(), ctypes.c_int64()
+    L.check(L.lib().wect_profile_read(ctypes.byref(fm), ctypes.byref(fl), ctypes.byref(bm), ctypes.byref(bl),
+                                      int(reset)), "wect_profile_read")
+    return {"fwd_ms": fm.value, "fwd_launches": fl.value, "bwd_ms": bm.value, "bwd_launches": bl.value}
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+
+class WECTFunction(torch.autograd.Function):
+    """out = WECT(weights); gradients flow to the weights only.
+
+    The output is piecewise constant in coordinates, directions and
+    thresholds, so their gradient is zero almost everywhere and None is
+    returned for them."""
+
+    @staticmethod
+    def forward(ctx, cx, grid, *weights):
+        cxw = cx.with_weights(list(w.detach().contiguous() for w in weights))
+        out = wect_forward(cxw, grid)
+        ctx.cx = cxw
+        ctx.grid = grid
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = wect_backward(ctx.cx, ctx.grid, grad_out)
+        if isinstance(g, torch.Tensor):
+            g = [g]
+        return (None, None, *g)
+
+
+def wect(cx: SimplicialBatch, grid: Grid, *weights: torch.Tensor) -> torch.Tensor:
+    """Differentiable WECT of a simplicial batch with float32 weights
+    ('vertex_max': one tensor [V]; 'explicit': one tensor per dimension)."""
+    return WECTFunction.apply(cx, grid, *weights)
+
+
+class WECT(torch.nn.Module):
+    """Module form: directions and thresholds as buffers, complexes as input."""
+
+    def __init__(self, dirs, thr):
+        super().__init__()
+        self.register_buffer("dirs", torch.as_tensor(dirs, dtype=torch.float32))
+        self.register_buffer("thr", torch.as_tensor(thr, dtype=torch.float32))
+
+    def forward(self, cx, *weights):
+        grid = Grid(self.dirs, self.thr, device=self.dirs.device)
+        if weights:
+            return wect(cx, grid, *weights)
+        return wect_forward(cx, grid)

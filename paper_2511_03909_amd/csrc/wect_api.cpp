@@ -1,0 +1,439 @@
+// Host side of the C ABI declared in include/wect.h: metadata checks, work
+// decomposition, workspace sizing, kernel dispatch, measurement hooks.
+//
+// Every hot-path entry point checks only host-side metadata, computes the
+// decomposition from host-known totals and enqueues kernels; it never reads
+// device memory, allocates or synchronises, so it can be captured.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "wect.h"
+#include "wect_internal.h"
+
+namespace {
+
+using wect::Params;
+
+constexpr int kW = wect::kWave;
+constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // dynamic LDS per workgroup on gfx950 (160 KiB, less static use)
+
+struct DeviceInfo {
+  int cus = 0;
+  bool ok = false;
+};
+
+std::mutex g_dev_mu;
+std::vector<DeviceInfo> g_devs;
+
+bool device_info(DeviceInfo* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if ((int)g_devs.size() <= dev) g_devs.resize(dev + 1);
+  DeviceInfo& di = g_devs[dev];
+  if (!di.ok) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    di.cus = prop.multiProcessorCount;
+    di.ok = true;
+  }
+  *out = di;
+  return true;
+}
+
+// launch shape (process-wide)
+std::atomic<int> g_block{1024};
+std::atomic<int> g_bpc{1};
+std::atomic<int> g_min_items{2048};
+
+// measurement
+std::atomic<int> g_profile{0};
+struct EvPair {
+  hipEvent_t a, b;
+  int bwd;
+};
+std::mutex g_prof_mu;
+std::vector<EvPair> g_prof;
+
+bool valid_block(int b) { return b == 256 || b == 512 || b == 1024; }
+
+// Everything the host derives for one request.
+struct Plan {
+  Params p;
+  int block = 1024;
+  size_t lds_fwd = 0, lds_bwd = 0;
+  size_t partial_bytes = 0;
+  size_t ws_fwd = 0, ws_bwd = 0;
+  int64_t elems = 0;  // stream elements per direction tile / group
+  int G_fwd = 0, G_bwd = 0;
+  int64_t S_fwd = 0, S_bwd = 0;
+  int dg = 0, ngd = 0;
+};
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Check host metadata and build the plan.  need_bwd: backward requested.
+wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl) {
+  if (!c || !g) return WECT_ERR_ARG;
+  if (c->kind != WECT_SIMPLICIAL && c->kind != WECT_CUBICAL) return WECT_ERR_ARG;
+  if (c->B < 1) return WECT_ERR_ARG;
+  if (c->wmode < WECT_W_ONES || c->wmode > WECT_W_VERTEX_MAX) return WECT_ERR_ARG;
+  if (c->dtype != WECT_I32 && c->dtype != WECT_F32) return WECT_ERR_ARG;
+  if (g->d < 0 || g->T < 0) return WECT_ERR_ARG;
+  if (g->d > 0 && !g->dirs) return WECT_ERR_ARG;
+  if (g->T > 0 && !g->thr) return WECT_ERR_ARG;
+  Params& p = pl->p;
+  std::memset(&p, 0, sizeof(p));
+  p.kind = c->kind;
+  p.n = c->n;
+  p.B = c->B;
+  p.wmode = c->wmode;
+  p.dtype = c->dtype;
+  p.dirs = g->dirs;
+  p.d = g->d;
+  p.T = g->T;
+  p.thr = g->thr;
+  int64_t elems = 0;
+  if (c->kind == WECT_SIMPLICIAL) {
+    if (c->n < 1 || c->n > 3) return WECT_ERR_ARG;
+    if (c->top_dim < 0 || c->top_dim > 3) return WECT_ERR_ARG;
+    if (c->wmode == WECT_W_ONES && c->dtype != WECT_I32) return WECT_ERR_ARG;
+    if (c->wmode == WECT_W_VERTEX_MAX && c->dtype != WECT_F32) return WECT_ERR_ARG;
+    for (int i = 0; i < 4; ++i) {
+      if (c->count[i] < 0) return WECT_ERR_ARG;
+      if (i > c->top_dim && c->count[i] != 0) return WECT_ERR_ARG;
+      elems += c->count[i];
+    }
+    if (c->count[0] > 0 && !c->coords) return WECT_ERR_ARG;
+    if (c->count[0] > INT32_MAX || c->count[0] * (int64_t)c->n > INT64_MAX / 4) return WECT_ERR_ARG;
+    for (int i = 1; i <= c->top_dim; ++i)
+      if (c->count[i] > 0 && !c->simplices[i]) return WECT_ERR_ARG;
+    if (c->B > 1) {
+      if (!c->vert_off) return WECT_ERR_ARG;
+      for (int i = 1; i <= c->top_dim; ++i)
+        if (!c->simp_off[i]) return WECT_ERR_ARG;
+    }
+    // a batch given with offsets for B == 1 must give all of them
+    if (c->B == 1 && c->vert_off) {
+      for (int i = 1; i <= c->top_dim; ++i)
+        if (!c->simp_off[i]) return WECT_ERR_ARG;
+    }
+    if (c->wmode == WECT_W_EXPLICIT) {
+      for (int i = 0; i <= c->top_dim; ++i)
+        if (c->count[i] > 0 && !c->weights[i]) return WECT_ERR_ARG;
+    }
+    if (c->wmode == WECT_W_VERTEX_MAX && c->count[0] > 0 && !c->weights[0]) return WECT_ERR_ARG;
+    p.top_dim = c->top_dim;
+    p.coords = c->coords;
+    p.vert_off = c->vert_off;
+    for (int i = 0; i < 4; ++i) {
+      p.count[i] = c->count[i];
+      p.simp[i] = i >= 1 ? c->simplices[i] : nullptr;
+      p.simp_off[i] = (i >= 1 && i <= c->top_dim) ? c->simp_off[i] : nullptr;
+      p.weights[i] = c->weights[i];
+    }
+    if (c->B == 1 && !c->vert_off) {
+      for (int i = 0; i < 4; ++i) p.simp_off[i] = nullptr;
+    }
+  } else {
+    if (c->n != 2 && c->n != 3) return WECT_ERR_ARG;
+    if (c->wmode == WECT_W_EXPLICIT) return WECT_ERR_UNSUPPORTED;
+    if (c->dtype != WECT_I32) return WECT_ERR_ARG;
+    if (c->total_voxels < 0) return WECT_ERR_ARG;
+    if (!c->shape || !c->axis) return WECT_ERR_ARG;
+    if (c->total_voxels > 0 && !c->intensity) return WECT_ERR_ARG;
+    if (c->B > 1 && (!c->grid_off || !c->axis_off)) return WECT_ERR_ARG;
+    if (c->include_above < -1 || c->include_above > 255) return WECT_ERR_ARG;
+    p.shape = c->shape;
+    p.grid_off = c->grid_off;
+    p.intensity = c->intensity;
+    p.axis = c->axis;
+    p.axis_off = c->axis_off;
+    p.total_voxels = c->total_voxels;
+    p.include_above = c->include_above;
+    elems = c->total_voxels;
+  }
+  if (need_bwd) {
+    if (c->kind != WECT_SIMPLICIAL) return WECT_ERR_UNSUPPORTED;
+    if (c->dtype != WECT_F32 || c->wmode == WECT_W_ONES) return WECT_ERR_ARG;
+  }
+
+  const int block = g_block.load();
+  pl->block = block;
+  pl->elems = elems;
+  const int ntiles = (int)ceil_div(g->d, kW);
+  p.ntiles = ntiles;
+  p.stage = block;
+  DeviceInfo di;
+  const bool have_dev = device_info(&di);
+  const int cus = have_dev ? di.cus : 256;
+  const int64_t max_blocks = (int64_t)cus * std::max(1, g_bpc.load());
+  const int64_t min_items = std::max(1, g_min_items.load());
+
+  if (need_fwd && g->d > 0 && g->T > 0) {
+    // forward LDS: histogram [T+1][64] + threshold pairs + staged entries
+    int stage = block;
+    size_t lds = wect::forward_lds_bytes(g->T, stage, c->kind, c->n);
+    while (lds > kLdsLimit && stage > 256) {
+      stage /= 2;
+      lds = wect::forward_lds_bytes(g->T, stage, c->kind, c->n);
+    }
+    if (lds > kLdsLimit) return WECT_ERR_UNSUPPORTED;
+    p.stage = stage;
+    pl->lds_fwd = lds;
+    const int64_t S = (int64_t)ntiles * elems;
+    int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
+    G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
+    pl->G_fwd = (int)G;
+    pl->S_fwd = S;
+    const int64_t slots = G + (int64_t)c->B * ntiles;
+    pl->partial_bytes = (size_t)slots * (size_t)g->T * kW * 4;
+    pl->ws_fwd = pl->partial_bytes;
+  }
+  if (need_bwd && g->d > 0 && g->T > 0) {
+    int dg = std::min(ntiles, 4);
+    int stage = block;
+    while (dg > 0 && wect::backward_lds_bytes(g->T, stage, dg) > kLdsLimit) --dg;
+    if (dg == 0) {
+      dg = 1;
+      while (stage > 256 && wect::backward_lds_bytes(g->T, stage, dg) > kLdsLimit) stage /= 2;
+      if (wect::backward_lds_bytes(g->T, stage, dg) > kLdsLimit) return WECT_ERR_UNSUPPORTED;
+    }
+    pl->dg = dg;
+    pl->ngd = (int)ceil_div(ntiles, dg);
+    pl->lds_bwd = wect::backward_lds_bytes(g->T, stage, dg);
+    const int64_t S = (int64_t)pl->ngd * elems;
+    int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
+    G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
+    pl->G_bwd = (int)G;
+    pl->S_bwd = S;
+    pl->ws_bwd = 0;
+    if (stage < p.stage) p.stage = stage;  // only lowered when the backward needs it
+  }
+  return WECT_OK;
+}
+
+thread_local char g_last_error[256] = "";
+
+// Remember a failed HIP call for wect_last_error() and map it to WECT_ERR_DEVICE.
+wect_status device_error(hipError_t e, const char* where) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+  return WECT_ERR_DEVICE;
+}
+
+hipError_t record(hipEvent_t* e, hipStream_t s) {
+  hipError_t r = hipEventCreate(e);
+  if (r != hipSuccess) return r;
+  return hipEventRecord(*e, s);
+}
+
+wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, hipStream_t s) {
+  Plan pl = pl0;
+  Params& p = pl.p;
+  const int64_t nout = (int64_t)p.B * p.d * p.T;
+  if (nout == 0) return WECT_OK;
+  if (!out) return WECT_ERR_ARG;
+  if (pl.ws_fwd > 0 && (!ws || ws_bytes < pl.ws_fwd)) return WECT_ERR_WORKSPACE;
+  if (ws && (reinterpret_cast<uintptr_t>(ws) & 15)) return WECT_ERR_ARG;
+  p.out = out;
+  p.partial = ws;
+  p.G = pl.G_fwd;
+  p.S = pl.S_fwd;
+  const bool prof = g_profile.load() != 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p.S > 0) {
+    if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
+    if (hipError_t e = wect::launch_forward_main(p, pl.block, pl.lds_fwd, s); e != hipSuccess)
+      return device_error(e, "forward kernel");
+    if (prof) {
+      if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof.push_back({e0, e1, 0});
+    }
+  }
+  if (hipError_t e = wect::launch_forward_reduce(p, s); e != hipSuccess) return device_error(e, "reduce kernel");
+  return WECT_OK;
+}
+
+wect_status run_backward(const Plan& pl0, const float* grad_out, float* const grad_w[4], float* grad_vertex,
+                         hipStream_t s) {
+  Plan pl = pl0;
+  Params& p = pl.p;
+  if (!grad_out && (int64_t)p.B * p.d * p.T > 0) return WECT_ERR_ARG;
+  p.grad_out = grad_out;
+  if (p.wmode == WECT_W_VERTEX_MAX) {
+    if (!grad_vertex && p.count[0] > 0) return WECT_ERR_ARG;
+    p.grad_vertex = grad_vertex;
+  } else {
+    for (int i = 0; i < 4; ++i) p.grad_w[i] = grad_w ? grad_w[i] : nullptr;
+  }
+  p.dg = pl.dg;
+  p.ngroups_dir = pl.ngd;
+  p.G = pl.G_bwd;
+  p.S = pl.S_bwd;
+  // Outputs that are accumulated with atomics start from zero; with a single
+  // direction group every explicit-weight gradient is written exactly once.
+  const bool atomic_explicit = pl.ngd > 1;
+  p.bwd_atomic = atomic_explicit ? 1 : 0;
+  if (p.wmode == WECT_W_VERTEX_MAX) {
+    if (wect::launch_fill_zero(grad_vertex, p.count[0], s) != hipSuccess) return WECT_ERR_DEVICE;
+  } else if (atomic_explicit || p.d == 0 || p.T == 0 || p.S == 0) {
+    for (int i = 0; i <= p.top_dim; ++i)
+      if (p.grad_w[i] && wect::launch_fill_zero(p.grad_w[i], p.count[i], s) != hipSuccess) return WECT_ERR_DEVICE;
+  }
+  if (p.d == 0 || p.T == 0 || p.S == 0) return WECT_OK;
+  const bool prof = g_profile.load() != 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
+  if (hipError_t e = wect::launch_backward_main(p, pl.block, pl.lds_bwd, s); e != hipSuccess)
+    return device_error(e, "adjoint kernel");
+  if (prof) {
+    if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({e0, e1, 1});
+  }
+  return WECT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wect_status_string(wect_status s) {
+  switch (s) {
+    case WECT_OK: return "ok";
+    case WECT_ERR_ARG: return "invalid argument";
+    case WECT_ERR_INDEX: return "vertex id, offset or shape out of range";
+    case WECT_ERR_THRESHOLDS: return "thresholds not non-decreasing or axis not strictly increasing";
+    case WECT_ERR_NONFINITE: return "NaN or Inf in the input";
+    case WECT_ERR_WORKSPACE: return "workspace missing or too small";
+    case WECT_ERR_UNSUPPORTED: return "unsupported request";
+    case WECT_ERR_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* wect_version(void) { return "wect 0.1 gfx950"; }
+
+const char* wect_last_error(void) { return g_last_error; }
+
+size_t wect_workspace_bytes(const wect_complex* c, const wect_grid* g, int with_backward) {
+  Plan pl;
+  if (make_plan(c, g, true, with_backward != 0, &pl) != WECT_OK) return 0;
+  return std::max(pl.ws_fwd, pl.ws_bwd);
+}
+
+wect_status wect_forward(const wect_complex* c, const wect_grid* g, void* out, void* ws, size_t ws_bytes,
+                         void* hip_stream) {
+  Plan pl;
+  wect_status st = make_plan(c, g, true, false, &pl);
+  if (st != WECT_OK) return st;
+  return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
+wect_status wect_backward(const wect_complex* c, const wect_grid* g, const float* grad_out,
+                          float* const grad_w[4], float* grad_vertex, void* ws, size_t ws_bytes, void* hip_stream) {
+  (void)ws;
+  (void)ws_bytes;
+  Plan pl;
+  wect_status st = make_plan(c, g, false, true, &pl);
+  if (st != WECT_OK) return st;
+  return run_backward(pl, grad_out, grad_w, grad_vertex, (hipStream_t)hip_stream);
+}
+
+wect_status wect_batched(const wect_complex* c, const wect_grid* g, void* out, const float* grad_out,
+                         float* const grad_w[4], float* grad_vertex, void* ws, size_t ws_bytes, void* hip_stream) {
+  const bool bwd = grad_out != nullptr;
+  Plan pl;
+  wect_status st = make_plan(c, g, true, bwd, &pl);
+  if (st != WECT_OK) return st;
+  // all metadata checks of the backward happen before anything is enqueued
+  if (bwd) {
+    if (c->wmode == WECT_W_VERTEX_MAX && !grad_vertex && c->count[0] > 0) return WECT_ERR_ARG;
+  }
+  if ((int64_t)c->B * g->d * g->T > 0 && !out) return WECT_ERR_ARG;
+  if (pl.ws_fwd > 0 && (!ws || ws_bytes < pl.ws_fwd)) return WECT_ERR_WORKSPACE;
+  st = run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
+  if (st != WECT_OK || !bwd) return st;
+  return run_backward(pl, grad_out, grad_w, grad_vertex, (hipStream_t)hip_stream);
+}
+
+wect_status wect_validate(const wect_complex* c, const wect_grid* g, void* hip_stream) {
+  Plan pl;
+  wect_status st = make_plan(c, g, false, false, &pl);
+  if (st != WECT_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  int* dflags = nullptr;
+  if (hipMalloc(&dflags, sizeof(int)) != hipSuccess) return WECT_ERR_DEVICE;
+  int flags = 0;
+  bool ok = hipMemcpyAsync(dflags, &flags, sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && wect::launch_validate(pl.p, dflags, s) == hipSuccess;
+  ok = ok && hipMemcpyAsync(&flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s) == hipSuccess;
+  ok = ok && hipStreamSynchronize(s) == hipSuccess;
+  (void)hipFree(dflags);
+  if (!ok) return WECT_ERR_DEVICE;
+  if (flags & wect::kFlagIndex) return WECT_ERR_INDEX;
+  if (flags & wect::kFlagThr) return WECT_ERR_THRESHOLDS;
+  if (flags & wect::kFlagNonfinite) return WECT_ERR_NONFINITE;
+  return WECT_OK;
+}
+
+wect_status wect_set_launch(const wect_launch* l) {
+  if (!l) return WECT_ERR_ARG;
+  if (l->block != 0 && !valid_block(l->block)) return WECT_ERR_ARG;
+  if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64 || l->min_items_per_block < 0) return WECT_ERR_ARG;
+  g_block.store(l->block ? l->block : 1024);
+  g_bpc.store(l->blocks_per_cu ? l->blocks_per_cu : 1);
+  g_min_items.store(l->min_items_per_block ? l->min_items_per_block : 2048);
+  return WECT_OK;
+}
+
+wect_status wect_get_launch(wect_launch* l) {
+  if (!l) return WECT_ERR_ARG;
+  l->block = g_block.load();
+  l->blocks_per_cu = g_bpc.load();
+  l->min_items_per_block = g_min_items.load();
+  l->reserved = 0;
+  return WECT_OK;
+}
+
+wect_status wect_profile_enable(int on) {
+  g_profile.store(on ? 1 : 0);
+  return WECT_OK;
+}
+
+wect_status wect_profile_read(double* fwd_ms, int64_t* fwd_launches, double* bwd_ms, int64_t* bwd_launches,
+                              int reset) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
+  for (auto& e : g_prof) {
+    if (hipEventSynchronize(e.b) != hipSuccess) return WECT_ERR_DEVICE;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) return WECT_ERR_DEVICE;
+    ms[e.bwd] += t;
+    cnt[e.bwd] += 1;
+  }
+  if (fwd_ms) *fwd_ms = ms[0];
+  if (fwd_launches) *fwd_launches = cnt[0];
+  if (bwd_ms) *bwd_ms = ms[1];
+  if (bwd_launches) *bwd_launches = cnt[1];
+  if (reset) {
+    for (auto& e : g_prof) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    g_prof.clear();
+  }
+  return WECT_OK;
+}
+
+}  // extern "C"

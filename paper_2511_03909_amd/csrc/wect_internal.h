@@ -1,0 +1,64 @@
+// Internal interface between the host runtime (wect_api.cpp) and the HIP
+// kernels (wect_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wect {
+
+constexpr int kWave = 64;          // lanes per wavefront on gfx950; one lane = one direction
+constexpr int kMaxStride = 16;     // floats per staged simplicial entry (4 vertices x 3 + weight + owner)
+
+// Everything a kernel needs, passed by value.
+struct Params {
+  // complex
+  int32_t kind, n, B, top_dim, wmode, dtype;
+  const float* coords;
+  const int64_t* vert_off;
+  int64_t count[4];
+  const int32_t* simp[4];
+  const int64_t* simp_off[4];
+  const void* weights[4];
+  const int32_t* shape;
+  const int64_t* grid_off;
+  const uint8_t* intensity;
+  const float* axis;
+  const int64_t* axis_off;
+  int64_t total_voxels;
+  int32_t include_above;
+  // sampling grid
+  const float* dirs;
+  int32_t d, T;
+  const float* thr;
+  // decomposition
+  int32_t ntiles;        // direction tiles of 64 (forward) / per group (backward)
+  int32_t G;             // blocks of the main kernel
+  int64_t S;             // stream length: sum over groups of the stream elements
+  int32_t stage;         // staged entries per tile (<= blockDim.x)
+  int32_t dg;            // backward: direction tiles held in LDS at once
+  int32_t ngroups_dir;   // backward: number of direction groups ( = ceil(ntiles / dg) )
+  void* partial;         // forward: [slots][T][64] int32 / float32
+  void* out;             // forward: [B][d][T]
+  // backward
+  const float* grad_out;         // [B][d][T]
+  float* grad_w[4];
+  float* grad_vertex;
+  int32_t bwd_atomic;            // 1: accumulate with atomics (output pre-zeroed)
+};
+
+// Launchers (enqueue only, return hipError_t of the launch).
+hipError_t launch_forward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+hipError_t launch_forward_reduce(const Params& p, hipStream_t s);
+hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s);
+hipError_t launch_validate(const Params& p, int* flags, hipStream_t s);
+
+// LDS bytes the main kernels need for a given T, staged entries and stride.
+size_t forward_lds_bytes(int T, int stage, int kind, int n);
+size_t backward_lds_bytes(int T, int stage, int dg);
+
+// Validation flags (bit set = failure).
+enum : int { kFlagIndex = 1, kFlagThr = 2, kFlagNonfinite = 4 };
+
+}  // namespace wect

@@ -1,0 +1,1071 @@
+// HIP kernels (gfx950) for the weighted Euler characteristic transform.
+//
+// Work layout shared by the forward and backward kernels
+// ------------------------------------------------------
+// One lane of a 64-wide wavefront owns one direction of a 64-direction tile.
+// A wavefront walks a list of cells (simplices, or voxels of an image) whose
+// data are identical for all of its lanes, so every per-cell load is a
+// broadcast and each lane only evaluates its own direction: heights, the
+// maximum over the cell's vertices, the threshold index.  The forward adds the
+// signed weight to an LDS histogram laid out [threshold index][lane]: the 64
+// lanes of one atomic always hit 64 different words in 64 consecutive banks,
+// whatever their threshold indices are, so LDS atomics never conflict.
+//
+// The cells of all complexes of a batch and all direction tiles form one
+// stream ordered (complex, direction tile, cell).  A "group" is one
+// (complex, direction tile) pair.  Block k of G processes the contiguous
+// stream range [k*S/G, (k+1)*S/G) and writes one partial histogram per group
+// it touches into slot k + group; a second kernel sums a group's slots and
+// scans along the thresholds (the cumulative sum of Algorithm 1).
+//
+// Numerics: heights are float32 with contraction off, ((x*sx) + (y*sy)) + (z*sz);
+// a cell's threshold index is the first stored threshold at or above its
+// maximum height (identical to the maximum of its vertices' indices because
+// the index is monotone, as in the correctness proof of Algorithm 1).
+
+#include "wect_internal.h"
+
+#include <math.h>
+
+#include <atomic>
+
+#pragma clang fp contract(off)
+
+namespace wect {
+namespace {
+
+constexpr int W = kWave;
+
+enum : int { WM_ONES = 0, WM_EXPLICIT = 1, WM_VMAX = 2 };
+
+template <typename A, typename B>
+__device__ __forceinline__ A bitcast(B x) {
+  static_assert(sizeof(A) == sizeof(B), "size");
+  A r;
+  __builtin_memcpy(&r, &x, sizeof(A));
+  return r;
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t mn64(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t mx64(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// heights
+// ---------------------------------------------------------------------------
+
+template <int N>
+__device__ __forceinline__ float height(const float* c, float sx, float sy, float sz) {
+  float h = c[0] * sx;
+  if constexpr (N >= 2) h = h + c[1] * sy;
+  if constexpr (N >= 3) h = h + c[2] * sz;
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// threshold index: b = min{ q : thr[q] >= h }, in [0, T]
+// ---------------------------------------------------------------------------
+
+struct Thr {
+  const float2* P;  // LDS [T+1]: (thr[q-1], thr[q]) with -inf / +inf at the ends
+  float a, c;
+  int T, p2, fast;
+};
+
+// Monotone first guess of the index (a cheap affine map, clamped to [0, T]).
+__device__ __forceinline__ int guess(float h, float a, float c, int T) {
+  float t = (h - a) * c;
+  t = __builtin_amdgcn_fmed3f(t, 0.0f, (float)T);
+  return (int)t;
+}
+
+__device__ __forceinline__ float next_up(float x) {
+  if (!(x == x) || x == INFINITY) return x;
+  if (x == 0.0f) return __int_as_float(1);
+  int i = __float_as_int(x);
+  return __int_as_float(x > 0.0f ? i + 1 : i - 1);
+}
+
+// Exact index.  Fast path: the guess is within one of the true index for
+// every float (checked against the stored thresholds when the block starts),
+// so one comparison on each side of it settles the index.  Otherwise a
+// branch-free binary search over the stored thresholds.
+template <bool FAST>
+__device__ __forceinline__ int thr_index(float h, const Thr& th) {
+  if constexpr (FAST) {
+    int g = guess(h, th.a, th.c, th.T);
+    float2 pr = th.P[g];
+    return g + (h > pr.y ? 1 : 0) - (h <= pr.x ? 1 : 0);
+  }
+  int lo = 0;
+  for (int s = th.p2; s > 0; s >>= 1) {
+    int cand = lo + s;
+    if (cand <= th.T && th.P[cand].x < h) lo = cand;  // P[cand].x == thr[cand-1]
+  }
+  return lo;
+}
+
+// Block prologue: stage the threshold pairs in LDS and decide whether the
+// fast path is exact for this threshold array.  The guess g(h) is monotone in
+// h and the true index L(h) is constant on (thr[q], thr[q+1]], so checking
+// g at thr[q] and at the next float above thr[q] for every q bounds
+// |g - L| <= 1 everywhere (strictly increasing thresholds required).
+__device__ void setup_thresholds(const float* thr, int T, float2* P, Thr& th) {
+  for (int q = threadIdx.x; q <= T; q += blockDim.x) {
+    float lo = q > 0 ? thr[q - 1] : -INFINITY;
+    float hi = q < T ? thr[q] : INFINITY;
+    P[q] = make_float2(lo, hi);
+  }
+  int p2 = 1;
+  while (p2 * 2 <= T) p2 *= 2;
+  float a = 0.0f, c = 0.0f;
+  int ok = 0;
+  if (T >= 2) {
+    float t0 = thr[0], t1 = thr[T - 1];
+    float delta = (t1 - t0) / (float)(T - 1);
+    a = t0 - delta;
+    c = 1.0f / delta;
+    ok = (delta > 0.0f) && isfinite(a) && isfinite(c) && (c > 0.0f);
+  }
+  int bad = 0;
+  if (ok) {
+    for (int q = threadIdx.x; q < T; q += blockDim.x) {
+      float x = thr[q];
+      if (q + 1 < T && !(x < thr[q + 1])) bad = 1;
+      int g0 = guess(x, a, c, T);
+      int g1 = guess(next_up(x), a, c, T);
+      if (g0 < q - 1 || g0 > q + 1 || g1 < q || g1 > q + 2) bad = 1;
+    }
+  }
+  bad = __syncthreads_or(bad);
+  th.P = P;
+  th.a = a;
+  th.c = c;
+  th.T = T;
+  th.p2 = p2;
+  th.fast = ok && !bad;
+}
+
+// ---------------------------------------------------------------------------
+// LDS accumulation
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void lds_add(uint32_t* a, uint32_t v) {
+  __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(float* a, float v) {
+  __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Sum over the 64 lanes of a wavefront: rotate-and-add inside each row of 16
+// lanes (DPP row_ror), then add the four row sums.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += bitcast<float>(__builtin_amdgcn_update_dpp(0, bitcast<int>(v), 0x128, 0xf, 0xf, false));
+  v += bitcast<float>(__builtin_amdgcn_update_dpp(0, bitcast<int>(v), 0x124, 0xf, 0xf, false));
+  v += bitcast<float>(__builtin_amdgcn_update_dpp(0, bitcast<int>(v), 0x122, 0xf, 0xf, false));
+  v += bitcast<float>(__builtin_amdgcn_update_dpp(0, bitcast<int>(v), 0x121, 0xf, 0xf, false));
+  float r0 = bitcast<float>(__builtin_amdgcn_readlane(bitcast<int>(v), 0));
+  float r1 = bitcast<float>(__builtin_amdgcn_readlane(bitcast<int>(v), 16));
+  float r2 = bitcast<float>(__builtin_amdgcn_readlane(bitcast<int>(v), 32));
+  float r3 = bitcast<float>(__builtin_amdgcn_readlane(bitcast<int>(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+// ---------------------------------------------------------------------------
+// stream bookkeeping
+// ---------------------------------------------------------------------------
+
+// Number of stream elements (cells handled one by one) of the complexes
+// before complex b: all simplices of all dimensions, or all voxels.
+__device__ __forceinline__ int64_t cum_elems(const Params& p, int b) {
+  if (p.kind == 1) {
+    if (p.grid_off) return p.grid_off[b];
+    return b == 0 ? 0 : p.total_voxels;
+  }
+  if (p.B == 1 && !p.vert_off) {
+    if (b == 0) return 0;
+    int64_t s = 0;
+    for (int i = 0; i <= p.top_dim; ++i) s += p.count[i];
+    return s;
+  }
+  int64_t s = p.vert_off[b];
+  for (int i = 1; i <= p.top_dim; ++i) s += p.simp_off[i][b];
+  return s;
+}
+
+__device__ __forceinline__ int64_t off_or(const int64_t* off, int b, int64_t dflt) {
+  return off ? off[b] : (b == 0 ? 0 : dflt);
+}
+
+// Largest b in [0, B) with groups_per_complex * cum_elems(b) <= pos.
+__device__ int find_complex(const Params& p, int64_t pos, int gpc) {
+  int lo = 0, hi = p.B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)gpc * cum_elems(p, mid) <= pos) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t block_start(int64_t k, int64_t S, int64_t G) { return (k * S) / G; }
+
+// ---------------------------------------------------------------------------
+// simplicial staging: one thread gathers one simplex into registers
+// ---------------------------------------------------------------------------
+
+template <int N, int DIM>
+struct SimpLayout {
+  static constexpr int NV = DIM + 1;
+  static constexpr int WOFF = NV * N;          // weight slot
+  static constexpr int OOFF = NV * N + 1;      // owner slot (vertex-max backward)
+  static constexpr int STRIDE = ((NV * N + 2 + 3) / 4) * 4;
+};
+
+template <int N, int DIM, int WM, typename WT>
+struct SimpStager {
+  using L = SimpLayout<N, DIM>;
+  float e[L::OOFF + 1];
+  int idx[L::NV];
+
+  // vertex ids (local to the complex) of simplex `row` (global row index)
+  __device__ __forceinline__ void load_idx(const Params& p, int64_t row, int64_t lrow) {
+    if constexpr (DIM == 0) {
+      idx[0] = (int)lrow;
+    } else {
+      const int32_t* s = p.simp[DIM] + row * L::NV;
+#pragma unroll
+      for (int j = 0; j < L::NV; ++j) idx[j] = s[j];
+    }
+  }
+  // coordinates and weight of the simplex whose ids are in idx
+  __device__ __forceinline__ void gather(const Params& p, int64_t row, int64_t voff) {
+#pragma unroll
+    for (int j = 0; j < L::NV; ++j) {
+      const float* c = p.coords + (voff + idx[j]) * N;
+#pragma unroll
+      for (int k = 0; k < N; ++k) e[j * N + k] = c[k];
+    }
+    if constexpr (WM == WM_ONES) {
+      e[L::WOFF] = bitcast<float>(1u);
+      e[L::OOFF] = 0.0f;
+    } else if constexpr (WM == WM_EXPLICIT) {
+      e[L::WOFF] = bitcast<float>(((const WT*)p.weights[DIM])[row]);
+      e[L::OOFF] = 0.0f;
+    } else {
+      const float* w = (const float*)p.weights[0];
+      float best = w[voff + idx[0]];
+      int own = idx[0];
+#pragma unroll
+      for (int j = 1; j < L::NV; ++j) {
+        float x = w[voff + idx[j]];
+        if (x > best || (x == best && idx[j] < own)) { best = x; own = idx[j]; }
+      }
+      e[L::WOFF] = best;
+      e[L::OOFF] = bitcast<float>(own);
+    }
+  }
+  __device__ __forceinline__ void store(float* dst) const {
+#pragma unroll
+    for (int k = 0; k <= L::OOFF; ++k) dst[k] = e[k];
+  }
+  // forward entry: the weight slot holds the signed weight (-1)^DIM w
+  __device__ __forceinline__ void store_signed(float* dst) const {
+#pragma unroll
+    for (int k = 0; k <= L::OOFF; ++k) dst[k] = e[k];
+    if constexpr (DIM & 1) dst[L::WOFF] = bitcast<float>(WT(0) - bitcast<WT>(e[L::WOFF]));
+  }
+};
+
+// Maximum height of a staged simplex for the lane's direction.
+template <int N, int DIM>
+__device__ __forceinline__ float max_height(const float* E, float sx, float sy, float sz) {
+  float h = height<N>(E, sx, sy, sz);
+#pragma unroll
+  for (int j = 1; j <= DIM; ++j) h = fmaxf(h, height<N>(E + j * N, sx, sy, sz));
+  return h;
+}
+
+// Forward over the simplices [lo, hi) (local numbering) of dimension DIM of
+// one complex: stage TS simplices at a time, then every wavefront adds its
+// share of them to the LDS histogram.  Indices are prefetched one tile ahead
+// of the coordinate gather, which runs one tile ahead of the histogram.
+template <int N, int DIM, int WM, typename WT, bool FAST>
+__device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
+                               float sx, float sy, float sz, WT* hist, float* stage, const Thr& th) {
+  using L = SimpLayout<N, DIM>;
+  const int tid = threadIdx.x, lane = tid & (W - 1);
+  const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
+  const int TS = p.stage;
+  const int64_t ntile = (hi - lo + TS - 1) / TS;
+  SimpStager<N, DIM, WM, WT> st;
+  auto tile_row = [&](int64_t t) { return lo + t * TS + tid; };
+  // prologue: ids of tile 0, gather tile 0, ids of tile 1
+  if (tid < TS && tile_row(0) < hi) {
+    st.load_idx(p, soff + tile_row(0), tile_row(0));
+    st.gather(p, soff + tile_row(0), voff);
+  }
+  int nidx[L::NV];
+  bool have_next = ntile > 1 && tid < TS && tile_row(1) < hi;
+  if (have_next) {
+    SimpStager<N, DIM, WM, WT> tmp;
+    tmp.load_idx(p, soff + tile_row(1), tile_row(1));
+#pragma unroll
+    for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
+  }
+  for (int64_t t = 0; t < ntile; ++t) {
+    const int cnt = (int)mn64(TS, hi - (lo + t * TS));
+    __syncthreads();
+    if (tid < cnt) st.store_signed(stage + tid * L::STRIDE);
+    __syncthreads();
+    // gather tile t+1 (ids loaded last iteration), load ids of tile t+2
+    if (have_next) {
+#pragma unroll
+      for (int j = 0; j < L::NV; ++j) st.idx[j] = nidx[j];
+      st.gather(p, soff + tile_row(t + 1), voff);
+    }
+    have_next = (t + 2 < ntile) && tid < TS && tile_row(t + 2) < hi;
+    if (have_next) {
+      SimpStager<N, DIM, WM, WT> tmp;
+      tmp.load_idx(p, soff + tile_row(t + 2), tile_row(t + 2));
+#pragma unroll
+      for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
+    }
+    // histogram of tile t: two entries per iteration for latency overlap
+    int e = wave;
+    for (; e + nw < cnt; e += 2 * nw) {
+      const float* E0 = stage + e * L::STRIDE;
+      const float* E1 = stage + (e + nw) * L::STRIDE;
+      float h0 = max_height<N, DIM>(E0, sx, sy, sz);
+      float h1 = max_height<N, DIM>(E1, sx, sy, sz);
+      WT w0 = bitcast<WT>(E0[L::WOFF]);
+      WT w1 = bitcast<WT>(E1[L::WOFF]);
+      int b0 = thr_index<FAST>(h0, th);
+      int b1 = thr_index<FAST>(h1, th);
+      lds_add(&hist[b0 * W + lane], w0);
+      lds_add(&hist[b1 * W + lane], w1);
+    }
+    if (e < cnt) {
+      const float* E0 = stage + e * L::STRIDE;
+      float h0 = max_height<N, DIM>(E0, sx, sy, sz);
+      WT w0 = bitcast<WT>(E0[L::WOFF]);
+      int b0 = thr_index<FAST>(h0, th);
+      lds_add(&hist[b0 * W + lane], w0);
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int WM, typename WT, bool FAST>
+__device__ __forceinline__ void simp_fwd_dim(int dim, const Params& p, int64_t lo, int64_t hi, int64_t voff,
+                                             int64_t soff, float sx, float sy, float sz, WT* hist, float* stage,
+                                             const Thr& th) {
+  switch (dim) {
+    case 0: simp_fwd_range<N, 0, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
+    case 1: simp_fwd_range<N, 1, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
+    case 2: simp_fwd_range<N, 2, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
+    default: simp_fwd_range<N, 3, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
+  }
+}
+
+template <typename WT>
+__device__ void flush_hist(const Params& p, WT* hist, int64_t slot) {
+  __syncthreads();
+  const int T = p.T;
+  WT* dst = (WT*)p.partial + slot * (int64_t)T * W;
+  for (int i = threadIdx.x; i < T * W; i += blockDim.x) dst[i] = hist[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = WT(0);
+  __syncthreads();
+}
+
+__device__ __forceinline__ void load_dir(const Params& p, int gp, float& sx, float& sy, float& sz) {
+  sx = sy = sz = 0.0f;
+  if (gp < p.d) {
+    const float* s = p.dirs + (int64_t)gp * p.n;
+    sx = s[0];
+    if (p.n >= 2) sy = s[1];
+    if (p.n >= 3) sz = s[2];
+  }
+}
+
+__device__ __forceinline__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// forward, simplicial
+// ---------------------------------------------------------------------------
+
+template <int N, int WM, typename WT>
+__global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T;
+  WT* hist = (WT*)smem;
+  float2* P = (float2*)(smem + (size_t)(T + 1) * W * sizeof(WT));
+  float* stage = (float*)(smem + (size_t)(T + 1) * W * sizeof(WT) + align_up((size_t)(T + 1) * 8, 16));
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = WT(0);
+  __syncthreads();
+
+  const int k = blockIdx.x;
+  int64_t pos = block_start(k, p.S, p.G);
+  const int64_t end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return;
+  const int gpc = p.ntiles;
+  int b = find_complex(p, pos, gpc);
+  const int lane = threadIdx.x & (W - 1);
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int t = (int)((pos - base) / nb);
+    const int64_t e0 = (pos - base) - (int64_t)t * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    float sx, sy, sz;
+    load_dir(p, t * W + lane, sx, sy, sz);
+    const int64_t voff = off_or(p.vert_off, b, p.count[0]);
+    // dimension ranges within the complex's element numbering
+    int64_t dlo = 0;
+    for (int dim = 0; dim <= p.top_dim; ++dim) {
+      int64_t kd = (dim == 0) ? (off_or(p.vert_off, b + 1, p.count[0]) - voff)
+                              : (off_or(p.simp_off[dim], b + 1, p.count[dim]) - off_or(p.simp_off[dim], b, p.count[dim]));
+      const int64_t dhi = dlo + kd;
+      const int64_t lo = mx64(e0, dlo), hi = mn64(e1, dhi);
+      if (lo < hi) {
+        const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
+        if (th.fast) simp_fwd_dim<N, WM, WT, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th);
+        else simp_fwd_dim<N, WM, WT, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th);
+      }
+      dlo = dhi;
+    }
+    flush_hist<WT>(p, hist, (int64_t)k + (int64_t)b * gpc + t);
+    pos += e1 - e0;
+    if (e1 == nb && t == gpc - 1) ++b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward, cubical (implicit cells of an image / volume)
+// ---------------------------------------------------------------------------
+//
+// Heights of a grid vertex are ((x_i*sx) + (y_j*sy)) + (z_k*sz).  Rounding is
+// monotone, so for sx >= 0 the height never decreases with i (and never
+// increases for sx < 0), and the same for the other axes: the maximum height
+// of a cell is attained at its "top" corner, the corner furthest along the
+// sign pattern of the direction.  Each vertex therefore adds, per direction,
+// one combined weight: the signed weights of the 2^n cells (itself, its
+// edges, squares, cubes) that it tops for that sign pattern ("orthant").  The
+// 2^n combined weights of a vertex are computed once when it is staged; each
+// lane then reads the one for its direction's orthant.  With a zero component
+// the heights along that axis are equal, so either corner gives the same index.
+
+template <int N>
+struct CubLayout {
+  static constexpr int NO = 1 << N;                 // orthants
+  static constexpr int COFF = N == 2 ? 2 : 4;       // first combined weight
+  static constexpr int STRIDE = N == 2 ? 8 : 12;
+};
+
+template <int N, int WM>
+__device__ __forceinline__ void cub_weights(const Params& p, const uint8_t* vol, int n0, int n1, int n2,
+                                            int i0, int i1, int i2, int32_t* cw) {
+  // neighbourhood values: intensity if the voxel exists and is a vertex, else -1
+  constexpr int M = N == 2 ? 9 : 27;
+  int nb[M];
+  const int thr = p.include_above;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
+    const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
+    int v = -1;
+    if (j0 >= 0 && j0 < n0 && j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2) {
+      int x = vol[((int64_t)j2 * n1 + j1) * n0 + j0];
+      v = x > thr ? x : -1;
+    }
+    nb[m] = v;
+  }
+#pragma unroll
+  for (int o = 0; o < (1 << N); ++o) {
+    // orthant bit k set: s_k < 0, the cells topped by v extend towards +k
+    const int s0 = (o & 1) ? 1 : -1, s1 = (o & 2) ? 1 : -1, s2 = (o & 4) ? 1 : -1;
+    int32_t acc = 0;
+#pragma unroll
+    for (int S = 0; S < (1 << N); ++S) {  // axes spanned by the cell
+      int mx = -1;
+      bool inc = true;
+#pragma unroll
+      for (int eps = 0; eps < (1 << N); ++eps) {
+        if ((eps & ~S) != 0) continue;  // corner offsets only along spanned axes
+        const int d0 = (eps & 1) ? s0 : 0, d1 = (eps & 2) ? s1 : 0, d2 = (eps & 4) ? s2 : 0;
+        const int m = (d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0);
+        const int v = nb[m];
+        inc = inc && (v >= 0);
+        mx = max(mx, v);
+      }
+      const int w = WM == WM_ONES ? 1 : mx;
+      const int sgn = (__builtin_popcount(S) & 1) ? -1 : 1;
+      acc += inc ? sgn * w : 0;
+    }
+    cw[o] = acc;
+  }
+}
+
+template <int N, int WM, bool FAST>
+__device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, float sx, float sy, float sz,
+                              int orth, uint32_t* hist, float* stage, int* counter, const Thr& th) {
+  using L = CubLayout<N>;
+  const int tid = threadIdx.x, lane = tid & (W - 1);
+  const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
+  const int TS = p.stage;
+  const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = N == 3 ? p.shape[3 * b + 2] : 1;
+  const int64_t goff = off_or(p.grid_off, b, p.total_voxels);
+  const int64_t aoff = p.axis_off ? p.axis_off[b] : 0;
+  const uint8_t* vol = p.intensity + goff;
+  const float* ax0 = p.axis + aoff;
+  const float* ax1 = ax0 + n0;
+  const float* ax2 = ax1 + n1;
+  for (int64_t t0 = lo; t0 < hi; t0 += TS) {
+    const int cnt = (int)mn64(TS, hi - t0);
+    if (tid == 0) *counter = 0;
+    __syncthreads();
+    bool keep = false;
+    float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+    int32_t cw[L::NO];
+    if (tid < cnt) {
+      const int64_t v = t0 + tid;
+      const int i0 = (int)(v % n0);
+      const int64_t r = v / n0;
+      const int i1 = (int)(r % n1);
+      const int i2 = (int)(r / n1);
+      if ((int)vol[v] > p.include_above) {
+        cub_weights<N, WM>(p, vol, n0, n1, n2, i0, i1, i2, cw);
+        bool nz = false;
+#pragma unroll
+        for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
+        keep = nz;
+        cx = ax0[i0];
+        cy = ax1[i1];
+        if constexpr (N == 3) cz = ax2[i2];
+      }
+    }
+    // compact the contributing vertices
+    const uint64_t bal = __ballot(keep);
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(counter, __popcll(bal));
+    base = __shfl(base, 0);
+    if (keep) {
+      const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+      float* E = stage + slot * L::STRIDE;
+      E[0] = cx;
+      E[1] = cy;
+      if constexpr (N == 3) { E[2] = cz; E[3] = 0.0f; }
+#pragma unroll
+      for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
+    }
+    __syncthreads();
+    const int ne = uniform(*counter);
+    int e = wave;
+    for (; e + nw < ne; e += 2 * nw) {
+      const float* E0 = stage + e * L::STRIDE;
+      const float* E1 = stage + (e + nw) * L::STRIDE;
+      float h0 = height<N>(E0, sx, sy, sz);
+      float h1 = height<N>(E1, sx, sy, sz);
+      uint32_t w0 = bitcast<uint32_t>(E0[L::COFF + orth]);
+      uint32_t w1 = bitcast<uint32_t>(E1[L::COFF + orth]);
+      int b0 = thr_index<FAST>(h0, th);
+      int b1 = thr_index<FAST>(h1, th);
+      lds_add(&hist[b0 * W + lane], w0);
+      lds_add(&hist[b1 * W + lane], w1);
+    }
+    if (e < ne) {
+      const float* E0 = stage + e * L::STRIDE;
+      float h0 = height<N>(E0, sx, sy, sz);
+      uint32_t w0 = bitcast<uint32_t>(E0[L::COFF + orth]);
+      int b0 = thr_index<FAST>(h0, th);
+      lds_add(&hist[b0 * W + lane], w0);
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T;
+  uint32_t* hist = (uint32_t*)smem;
+  size_t off = (size_t)(T + 1) * W * 4;
+  float2* P = (float2*)(smem + off);
+  off += align_up((size_t)(T + 1) * 8, 16);
+  int* counter = (int*)(smem + off);
+  off += 16;
+  float* stage = (float*)(smem + off);
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = 0u;
+  __syncthreads();
+
+  const int k = blockIdx.x;
+  int64_t pos = block_start(k, p.S, p.G);
+  const int64_t end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return;
+  const int gpc = p.ntiles;
+  int b = find_complex(p, pos, gpc);
+  const int lane = threadIdx.x & (W - 1);
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int t = (int)((pos - base) / nb);
+    const int64_t e0 = (pos - base) - (int64_t)t * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    float sx, sy, sz;
+    load_dir(p, t * W + lane, sx, sy, sz);
+    const int orth = (sx < 0.0f ? 1 : 0) | (sy < 0.0f ? 2 : 0) | (sz < 0.0f ? 4 : 0);
+    if (th.fast) cub_fwd_range<N, WM, true>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    else cub_fwd_range<N, WM, false>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    flush_hist<uint32_t>(p, hist, (int64_t)k + (int64_t)b * gpc + t);
+    pos += e1 - e0;
+    if (e1 == nb && t == gpc - 1) ++b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reduce the partial histograms of a group and scan along the thresholds
+// (cumulative sum of Algorithm 1): out[b][p][q] = sum_{j <= q} D[p][j]
+// ---------------------------------------------------------------------------
+
+template <typename WT>
+struct ScanAcc;
+template <>
+struct ScanAcc<uint32_t> {
+  using T = uint32_t;
+  __device__ static uint32_t out(T x) { return x; }
+};
+template <>
+struct ScanAcc<float> {
+  using T = double;
+  __device__ static float out(T x) { return (float)x; }
+};
+
+template <typename WT>
+__global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
+  using A = typename ScanAcc<WT>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T;
+  const int LS = T + 1;                 // padded row of the transposed result
+  WT* L = (WT*)smem;                    // [64][T+1]
+  A* tot = (A*)(smem + align_up((size_t)W * LS * sizeof(WT), 16));  // [nr][64]
+  const int g = blockIdx.x;
+  const int gpc = p.ntiles;
+  const int b = g / gpc, t = g % gpc;
+  const int lane = threadIdx.x & (W - 1), r = threadIdx.x >> 6, nr = blockDim.x >> 6;
+  const int chunk = (T + nr - 1) / nr;
+  const int q0 = min(T, r * chunk), q1 = min(T, q0 + chunk);
+
+  const int64_t cb = cum_elems(p, b);
+  const int64_t nb = cum_elems(p, b + 1) - cb;
+  int64_t kfirst = 0, klast = -1;
+  if (nb > 0 && p.S > 0) {
+    const int64_t gs = (int64_t)gpc * cb + (int64_t)t * nb;
+    const int64_t ge = gs + nb;
+    kfirst = ((gs + 1) * p.G - 1) / p.S;
+    klast = (ge * p.G - 1) / p.S;
+  }
+  A run = A(0);
+  for (int q = q0; q < q1; ++q) {
+    A v = A(0);
+    for (int64_t kk = kfirst; kk <= klast; ++kk) {
+      const WT* src = (const WT*)p.partial + ((kk + g) * (int64_t)T + q) * W;
+      v += (A)src[lane];
+    }
+    run += v;
+    L[lane * LS + q] = (WT)run;
+  }
+  tot[r * W + lane] = run;
+  __syncthreads();
+  A offv = A(0);
+  for (int rr = 0; rr < r; ++rr) offv += tot[rr * W + lane];
+  if (offv != A(0)) {
+    // re-add in the wide type: local prefix + offset
+    for (int q = q0; q < q1; ++q) L[lane * LS + q] = ScanAcc<WT>::out((A)L[lane * LS + q] + offv);
+  }
+  __syncthreads();
+  const int dv = min(W, p.d - t * W);
+  WT* out = (WT*)p.out + ((int64_t)b * p.d + (int64_t)t * W) * T;
+  for (int i = threadIdx.x; i < dv * T; i += blockDim.x) {
+    const int pp = i / T, q = i - pp * T;
+    out[i] = L[pp * LS + q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward (adjoint), simplicial, float32 weights
+// ---------------------------------------------------------------------------
+//
+// For L = <grad_out, out>, dL/dw(c) = (-1)^dim(c) sum_p G[p][b_p(c)] with
+// G[p][j] = sum_{q >= j} grad_out[p][q] and G[p][T] = 0.  The block holds G for
+// up to `dg` direction tiles in LDS ([tile][T+1][64], read conflict-free by
+// lane), recomputes each staged simplex's index per direction and sums the
+// 64 x dg values with a wavefront reduction.
+
+constexpr int kMaxDG = 4;
+
+template <int N, int DIM, int WM, bool FAST>
+__device__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
+                               const float* sx, const float* sy, const float* sz, int ntl,
+                               const float* Gt, float* stage, const Thr& th) {
+  using L = SimpLayout<N, DIM>;
+  const int tid = threadIdx.x, lane = tid & (W - 1);
+  const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
+  const int TS = p.stage;
+  const int T1 = p.T + 1;
+  SimpStager<N, DIM, WM, float> st;
+  for (int64_t t0 = lo; t0 < hi; t0 += TS) {
+    const int cnt = (int)mn64(TS, hi - t0);
+    if (tid < cnt) {
+      st.load_idx(p, soff + t0 + tid, t0 + tid);
+      st.gather(p, soff + t0 + tid, voff);
+      st.store(stage + tid * L::STRIDE);
+    }
+    __syncthreads();
+    for (int e = wave; e < cnt; e += nw) {
+      const float* E = stage + e * L::STRIDE;
+      float acc = 0.0f;
+#pragma unroll
+      for (int j = 0; j < kMaxDG; ++j) {
+        if (j < ntl) {
+          const float h = max_height<N, DIM>(E, sx[j], sy[j], sz[j]);
+          const int bi = thr_index<FAST>(h, th);
+          acc += Gt[((size_t)j * T1 + bi) * W + lane];
+        }
+      }
+      float tot = wave_sum(acc);
+      if constexpr (DIM & 1) tot = -tot;
+      if (lane == 0) {
+        const int64_t row = soff + t0 + e;
+        if constexpr (WM == WM_VMAX) {
+          const int own = bitcast<int>(E[L::OOFF]);
+          atomicAdd(p.grad_vertex + voff + own, tot);
+        } else {
+          float* gw = p.grad_w[DIM];
+          if (gw) {
+            if (p.bwd_atomic) atomicAdd(gw + row, tot);
+            else gw[row] = tot;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, int WM, bool FAST>
+__device__ __forceinline__ void simp_bwd_dim(int dim, const Params& p, int b, int64_t lo, int64_t hi, int64_t voff,
+                                             int64_t soff, const float* sx, const float* sy, const float* sz, int ntl,
+                                             const float* Gt, float* stage, const Thr& th) {
+  switch (dim) {
+    case 0: simp_bwd_range<N, 0, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
+    case 1: simp_bwd_range<N, 1, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
+    case 2: simp_bwd_range<N, 2, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
+    default: simp_bwd_range<N, 3, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
+  }
+}
+
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_simp_bwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T, T1 = T + 1;
+  const int dg = p.dg;
+  float* Gt = (float*)smem;
+  size_t off = (size_t)dg * T1 * W * 4;
+  float2* P = (float2*)(smem + off);
+  off += align_up((size_t)T1 * 8, 16);
+  float* stage = (float*)(smem + off);
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  __syncthreads();
+
+  const int k = blockIdx.x;
+  int64_t pos = block_start(k, p.S, p.G);
+  const int64_t end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return;
+  const int gpc = p.ngroups_dir;
+  int b = find_complex(p, pos, gpc);
+  const int tid = threadIdx.x, lane = tid & (W - 1), wave = tid >> 6, nw = blockDim.x >> 6;
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int jg = (int)((pos - base) / nb);  // direction group
+    const int64_t e0 = (pos - base) - (int64_t)jg * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    const int tile0 = jg * dg;
+    const int ntl = min(dg, p.ntiles - tile0);
+    float sx[kMaxDG], sy[kMaxDG], sz[kMaxDG];
+#pragma unroll
+    for (int j = 0; j < kMaxDG; ++j) load_dir(p, (tile0 + j) * W + lane, sx[j], sy[j], sz[j]);
+    // reverse scan of grad_out for the group's tiles: one wavefront per tile
+    __syncthreads();
+    for (int j = wave; j < dg; j += nw) {
+      const int gp = (tile0 + j) * W + lane;
+      float* G = Gt + (size_t)j * T1 * W;
+      G[(size_t)T * W + lane] = 0.0f;
+      if (j < ntl && gp < p.d) {
+        const float* g = p.grad_out + ((int64_t)b * p.d + gp) * T;
+        double acc = 0.0;
+        for (int q = T - 1; q >= 0; --q) {
+          acc += (double)g[q];
+          G[(size_t)q * W + lane] = (float)acc;
+        }
+      } else {
+        for (int q = 0; q < T; ++q) G[(size_t)q * W + lane] = 0.0f;
+      }
+    }
+    __syncthreads();
+    const int64_t voff = off_or(p.vert_off, b, p.count[0]);
+    int64_t dlo = 0;
+    for (int dim = 0; dim <= p.top_dim; ++dim) {
+      int64_t kd = (dim == 0) ? (off_or(p.vert_off, b + 1, p.count[0]) - voff)
+                              : (off_or(p.simp_off[dim], b + 1, p.count[dim]) - off_or(p.simp_off[dim], b, p.count[dim]));
+      const int64_t dhi = dlo + kd;
+      const int64_t lo = mx64(e0, dlo), hi = mn64(e1, dhi);
+      if (lo < hi) {
+        const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
+        if (th.fast) simp_bwd_dim<N, WM, true>(dim, p, b, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, ntl, Gt, stage, th);
+        else simp_bwd_dim<N, WM, false>(dim, p, b, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, ntl, Gt, stage, th);
+      }
+      dlo = dhi;
+    }
+    pos += e1 - e0;
+    if (e1 == nb && jg == gpc - 1) ++b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_zero(float* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0f;
+}
+
+// Data checks; blockIdx.y selects the check.
+__global__ void k_validate(Params p, int* flags) {
+  const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+  int f = 0;
+  switch (blockIdx.y) {
+    case 0: {  // thresholds and directions
+      for (int64_t i = gtid; i < p.T; i += gstride) {
+        float x = p.thr[i];
+        if (!isfinite(x)) f |= kFlagNonfinite;
+        if (i + 1 < p.T && !(x <= p.thr[i + 1])) f |= kFlagThr;
+      }
+      for (int64_t i = gtid; i < (int64_t)p.d * p.n; i += gstride)
+        if (!isfinite(p.dirs[i])) f |= kFlagNonfinite;
+      break;
+    }
+    case 1: {  // simplicial coordinates and float weights
+      if (p.kind != 0) break;
+      for (int64_t i = gtid; i < p.count[0] * p.n; i += gstride)
+        if (!isfinite(p.coords[i])) f |= kFlagNonfinite;
+      if (p.dtype == 1) {
+        for (int dim = 0; dim <= p.top_dim; ++dim) {
+          if (p.wmode == 2 && dim > 0) break;
+          const float* w = (const float*)p.weights[dim];
+          if (!w) continue;
+          for (int64_t i = gtid; i < p.count[dim]; i += gstride)
+            if (!isfinite(w[i])) f |= kFlagNonfinite;
+        }
+      }
+      break;
+    }
+    case 2: {  // simplicial offsets and vertex ids
+      if (p.kind != 0) break;
+      if (p.B > 1 || p.vert_off) {
+        for (int64_t b = gtid; b <= p.B; b += gstride) {
+          if (b == 0 && p.vert_off[0] != 0) f |= kFlagIndex;
+          if (b == p.B && p.vert_off[b] != p.count[0]) f |= kFlagIndex;
+          if (b < p.B && p.vert_off[b + 1] < p.vert_off[b]) f |= kFlagIndex;
+          for (int dim = 1; dim <= p.top_dim; ++dim) {
+            const int64_t* so = p.simp_off[dim];
+            if (!so) { f |= kFlagIndex; continue; }
+            if (b == 0 && so[0] != 0) f |= kFlagIndex;
+            if (b == p.B && so[b] != p.count[dim]) f |= kFlagIndex;
+            if (b < p.B && so[b + 1] < so[b]) f |= kFlagIndex;
+          }
+        }
+      }
+      for (int dim = 1; dim <= p.top_dim; ++dim) {
+        const int64_t* so = p.simp_off[dim];
+        for (int64_t r = gtid; r < p.count[dim]; r += gstride) {
+          int64_t V = p.count[0];
+          if (so && p.vert_off) {
+            int lo = 0, hi = p.B - 1;  // complex owning row r
+            while (lo < hi) {
+              int mid = (lo + hi + 1) >> 1;
+              if (so[mid] <= r) lo = mid; else hi = mid - 1;
+            }
+            V = p.vert_off[lo + 1] - p.vert_off[lo];
+          }
+          for (int j = 0; j <= dim; ++j) {
+            int v = p.simp[dim][r * (dim + 1) + j];
+            if (v < 0 || v >= V) f |= kFlagIndex;
+          }
+        }
+      }
+      break;
+    }
+    case 3: {  // cubical shapes, offsets and axes
+      if (p.kind != 1) break;
+      for (int64_t b = gtid; b < p.B; b += gstride) {
+        const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = p.shape[3 * b + 2];
+        if (n0 < 1 || n1 < 1 || n2 < 1 || (p.n == 2 && n2 != 1)) { f |= kFlagIndex; continue; }
+        const int64_t nv = (int64_t)n0 * n1 * n2;
+        const int64_t g0 = off_or(p.grid_off, (int)b, p.total_voxels), g1 = off_or(p.grid_off, (int)b + 1, p.total_voxels);
+        if (g1 - g0 != nv) f |= kFlagIndex;
+        if (b == 0 && g0 != 0) f |= kFlagIndex;
+        if (b == p.B - 1 && g1 != p.total_voxels) f |= kFlagIndex;
+        const int64_t a0 = p.axis_off ? p.axis_off[b] : 0;
+        const int64_t na = (int64_t)n0 + n1 + (p.n == 3 ? n2 : 0);
+        if (p.axis_off && p.axis_off[b + 1] - a0 != na) f |= kFlagIndex;
+        const float* ax = p.axis + a0;
+        const int ext[3] = {n0, n1, n2};
+        int64_t o = 0;
+        for (int a = 0; a < p.n; ++a) {
+          for (int i = 0; i < ext[a]; ++i) {
+            if (!isfinite(ax[o + i])) f |= kFlagNonfinite;
+            if (i + 1 < ext[a] && !(ax[o + i] < ax[o + i + 1])) f |= kFlagThr;
+          }
+          o += ext[a];
+        }
+      }
+      break;
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
+// Opt each kernel in to the full LDS of a workgroup once per process (the
+// attribute is per function); later launches, including captured ones, only
+// enqueue.
+template <typename K>
+hipError_t set_lds_limit(K kernel, size_t bytes) {
+  static std::atomic<size_t> granted{64 * 1024};
+  if (bytes <= granted.load(std::memory_order_acquire)) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) granted.store(bytes, std::memory_order_release);
+  return e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+size_t forward_lds_bytes(int T, int stage, int kind, int n) {
+  size_t hist = (size_t)(T + 1) * W * 4;
+  size_t pairs = ((size_t)(T + 1) * 8 + 15) / 16 * 16;
+  size_t stride = kind == 1 ? (n == 2 ? 8 : 12) : kMaxStride;
+  return hist + pairs + 16 + (size_t)stage * stride * 4;
+}
+
+size_t backward_lds_bytes(int T, int stage, int dg) {
+  size_t g = (size_t)dg * (T + 1) * W * 4;
+  size_t pairs = ((size_t)(T + 1) * 8 + 15) / 16 * 16;
+  return g + pairs + (size_t)stage * kMaxStride * 4;
+}
+
+static size_t reduce_lds_bytes(int T, int dtype, int nr) {
+  size_t lsz = (size_t)W * (T + 1) * 4;
+  lsz = (lsz + 15) / 16 * 16;
+  return lsz + (size_t)nr * W * 8;
+}
+
+template <int N, int WM, typename WT>
+static hipError_t launch_simp_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_simp_fwd<N, WM, WT>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_simp_fwd<N, WM, WT>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int N, int WM>
+static hipError_t launch_cub_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cub_fwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_simp_fwd_n(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (p.wmode == WM_ONES) return launch_simp_fwd_t<N, WM_ONES, uint32_t>(p, block, lds, s);
+  if (p.wmode == WM_EXPLICIT) {
+    if (p.dtype == 0) return launch_simp_fwd_t<N, WM_EXPLICIT, uint32_t>(p, block, lds, s);
+    return launch_simp_fwd_t<N, WM_EXPLICIT, float>(p, block, lds, s);
+  }
+  return launch_simp_fwd_t<N, WM_VMAX, float>(p, block, lds, s);
+}
+
+hipError_t launch_forward_main(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (p.kind == 1) {
+    if (p.n == 2) return p.wmode == WM_ONES ? launch_cub_fwd_t<2, WM_ONES>(p, block, lds, s)
+                                            : launch_cub_fwd_t<2, WM_VMAX>(p, block, lds, s);
+    return p.wmode == WM_ONES ? launch_cub_fwd_t<3, WM_ONES>(p, block, lds, s)
+                              : launch_cub_fwd_t<3, WM_VMAX>(p, block, lds, s);
+  }
+  switch (p.n) {
+    case 1: return launch_simp_fwd_n<1>(p, block, lds, s);
+    case 2: return launch_simp_fwd_n<2>(p, block, lds, s);
+    default: return launch_simp_fwd_n<3>(p, block, lds, s);
+  }
+}
+
+hipError_t launch_forward_reduce(const Params& p, hipStream_t s) {
+  const int block = 1024, nr = block / W;
+  const size_t lds = reduce_lds_bytes(p.T, p.dtype, nr);
+  const int groups = p.B * p.ntiles;
+  if (p.dtype == 1) {
+    if (hipError_t e = set_lds_limit(k_reduce_scan<float>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_scan<float>, dim3(groups), dim3(block), lds, s, p);
+  } else {
+    if (hipError_t e = set_lds_limit(k_reduce_scan<uint32_t>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_scan<uint32_t>, dim3(groups), dim3(block), lds, s, p);
+  }
+  return hipGetLastError();
+}
+
+template <int N, int WM>
+static hipError_t launch_bwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_simp_bwd<N, WM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_simp_bwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_main(const Params& p, int block, size_t lds, hipStream_t s) {
+  const bool vm = p.wmode == WM_VMAX;
+  switch (p.n) {
+    case 1: return vm ? launch_bwd_t<1, WM_VMAX>(p, block, lds, s) : launch_bwd_t<1, WM_EXPLICIT>(p, block, lds, s);
+    case 2: return vm ? launch_bwd_t<2, WM_VMAX>(p, block, lds, s) : launch_bwd_t<2, WM_EXPLICIT>(p, block, lds, s);
+    default: return vm ? launch_bwd_t<3, WM_VMAX>(p, block, lds, s) : launch_bwd_t<3, WM_EXPLICIT>(p, block, lds, s);
+  }
+}
+
+hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, ptr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const Params& p, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(256, 4), dim3(256), 0, s, p, flags);
+  return hipGetLastError();
+}
+
+}  // namespace wect

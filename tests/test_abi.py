@@ -1,0 +1,169 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/wect.h declares, and rejects bad metadata before touching the device.
+
+Only error paths that return before any kernel launch are exercised here (the
+pointers used are never dereferenced on those paths)."""
+import ctypes
+
+import pytest
+
+from paper_2511_03909_amd import _lib as L
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = L.declared_functions()
+    assert {"wect_forward", "wect_backward", "wect_batched", "wect_validate", "wect_workspace_bytes",
+            "wect_status_string"} <= set(names)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_status_strings(lib):
+    for s in range(8):
+        assert len(L.status_string(s)) > 0
+    assert L.status_string(0) == "ok"
+    assert lib.wect_version().decode().startswith("wect")
+
+
+FAKE = 0x100000  # never dereferenced: every call below fails its metadata check first
+
+
+def _simplicial(**kw):
+    c = L.WectComplex()
+    c.kind = L.WECT_SIMPLICIAL
+    c.n = 2
+    c.B = 1
+    c.top_dim = 2
+    c.wmode = L.WECT_W_ONES
+    c.dtype = L.WECT_I32
+    c.coords = FAKE
+    c.count[0], c.count[1], c.count[2] = 3, 3, 1
+    c.simplices[1] = FAKE
+    c.simplices[2] = FAKE
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _grid(d=4, T=6):
+    return L.WectGrid(FAKE, d, T, FAKE)
+
+
+def _fwd(lib, c, g, out=FAKE, ws=None, nbytes=0):
+    return lib.wect_forward(ctypes.byref(c) if c is not None else None, ctypes.byref(g) if g is not None else None,
+                            out, ws, nbytes, None)
+
+
+def test_null_structs(lib):
+    assert _fwd(lib, None, _grid()) == L.WECT_ERR_ARG
+    assert _fwd(lib, _simplicial(), None) == L.WECT_ERR_ARG
+    assert lib.wect_workspace_bytes(None, None, 0) == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("kind", 7), ("n", 0), ("n", 4), ("B", 0), ("top_dim", 4), ("top_dim", -1), ("wmode", 3), ("dtype", 5),
+    ("coords", None),
+])
+def test_bad_metadata(lib, field, value):
+    c = _simplicial(**{field: value})
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+
+
+def test_bad_counts(lib):
+    c = _simplicial()
+    c.count[3] = 5  # count above top_dim
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+    c = _simplicial()
+    c.count[1] = -1
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+    c = _simplicial()
+    c.simplices[2] = None
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+
+
+def test_weight_mode_dtype_combinations(lib):
+    assert _fwd(lib, _simplicial(dtype=L.WECT_F32), _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+    c = _simplicial(wmode=L.WECT_W_VERTEX_MAX, dtype=L.WECT_I32)
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+    c = _simplicial(wmode=L.WECT_W_EXPLICIT, dtype=L.WECT_F32)  # weights missing
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+
+
+def test_batch_needs_offsets(lib):
+    c = _simplicial(B=2)
+    assert _fwd(lib, c, _grid(), ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG
+
+
+def test_grid_checks(lib):
+    assert _fwd(lib, _simplicial(), L.WectGrid(None, 4, 6, FAKE)) == L.WECT_ERR_ARG
+    assert _fwd(lib, _simplicial(), L.WectGrid(FAKE, 4, 6, None)) == L.WECT_ERR_ARG
+    assert _fwd(lib, _simplicial(), L.WectGrid(FAKE, -1, 6, FAKE)) == L.WECT_ERR_ARG
+    # an empty output needs no work and no workspace
+    assert _fwd(lib, _simplicial(), L.WectGrid(FAKE, 0, 6, FAKE), out=None) == L.WECT_OK
+    assert _fwd(lib, _simplicial(), L.WectGrid(FAKE, 4, 0, FAKE), out=None) == L.WECT_OK
+
+
+def test_workspace_too_small(lib):
+    c, g = _simplicial(), _grid()
+    need = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
+    assert need > 0
+    assert _fwd(lib, c, g, ws=None, nbytes=0) == L.WECT_ERR_WORKSPACE
+    assert _fwd(lib, c, g, ws=FAKE, nbytes=need - 1) == L.WECT_ERR_WORKSPACE
+    assert _fwd(lib, c, g, out=None, ws=FAKE, nbytes=need) == L.WECT_ERR_ARG
+
+
+def test_cubical_metadata(lib):
+    c = L.WectComplex()
+    c.kind = L.WECT_CUBICAL
+    c.n = 2
+    c.B = 1
+    c.wmode = L.WECT_W_ONES
+    c.dtype = L.WECT_I32
+    c.shape = FAKE
+    c.axis = FAKE
+    c.intensity = FAKE
+    c.total_voxels = 4
+    g = _grid()
+    for field, value in (("n", 1), ("n", 4), ("dtype", L.WECT_F32), ("shape", None), ("axis", None),
+                         ("intensity", None), ("include_above", 256), ("B", 2)):
+        bad = L.WectComplex.from_buffer_copy(c)
+        setattr(bad, field, value)
+        assert _fwd(lib, bad, g, ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_ARG, field
+    bad = L.WectComplex.from_buffer_copy(c)
+    bad.wmode = L.WECT_W_EXPLICIT
+    assert _fwd(lib, bad, g, ws=FAKE, nbytes=1 << 40) == L.WECT_ERR_UNSUPPORTED
+
+
+def test_backward_metadata(lib):
+    c, g = _simplicial(), _grid()
+    gw = (ctypes.c_void_p * 4)()
+    # ones weights have no gradient; cubical backward is not provided
+    assert lib.wect_backward(ctypes.byref(c), ctypes.byref(g), FAKE, gw, None, None, 0, None) == L.WECT_ERR_ARG
+    c = _simplicial(wmode=L.WECT_W_VERTEX_MAX, dtype=L.WECT_F32)
+    c.weights[0] = FAKE
+    assert lib.wect_backward(ctypes.byref(c), ctypes.byref(g), FAKE, gw, None, None, 0, None) == L.WECT_ERR_ARG
+    assert lib.wect_batched(ctypes.byref(c), ctypes.byref(g), FAKE, FAKE, gw, None, FAKE, 1 << 40,
+                            None) == L.WECT_ERR_ARG
+
+
+def test_launch_shape_roundtrip(lib):
+    before = L.WectLaunch()
+    assert lib.wect_get_launch(ctypes.byref(before)) == L.WECT_OK
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(300, 1, 0, 0))) == L.WECT_ERR_ARG
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 0))) == L.WECT_OK
+    now = L.WectLaunch()
+    lib.wect_get_launch(ctypes.byref(now))
+    assert (now.block, now.blocks_per_cu, now.min_items_per_block) == (512, 2, 1024)
+    assert lib.wect_set_launch(ctypes.byref(before)) == L.WECT_OK
+
+
+def test_workspace_grows_with_batch(lib):
+    c, g = _simplicial(), _grid(d=100, T=64)
+    a = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
+    assert a % (64 * 64 * 4) == 0  # whole [T][64] slots
+    assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(L.WectGrid(FAKE, 100, 100000, FAKE)), 0) == 0

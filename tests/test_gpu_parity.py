@@ -1,0 +1,406 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer outputs must be bit-exact.  Float32 outputs must be within
+1e-5 * sum|w| of the oracle's float64 value for every complex; every float32
+case is also re-run with unit and with integer weights, bit-exact, so that the
+tolerance cannot hide a dropped or duplicated cell."""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+F32_RTOL = 1e-5
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_03909_amd import api
+    api.set_launch()  # defaults
+    return api
+
+
+def gpu_wect(W, complexes, dirs, thr):
+    complexes = list(complexes)
+    if hasattr(complexes[0], "intensity"):
+        cx = W.CubicalBatch.from_host(complexes)
+    else:
+        cx = W.SimplicialBatch.from_host(complexes)
+    g = W.Grid(dirs, thr)
+    out = W.wect_forward(cx, g)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_match(got, ref, X, what):
+    if np.issubdtype(ref.dtype, np.integer):
+        assert got.dtype == np.int32
+        assert np.all(np.abs(ref) < 2 ** 31), "oracle value outside int32"
+        bad = np.argwhere(got.astype(np.int64) != ref)
+        assert bad.size == 0, f"{what}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+    else:
+        tol = F32_RTOL * max(oracle.total_abs_weight(X), 1e-30)
+        err = np.abs(got.astype(np.float64) - ref).max() if ref.size else 0.0
+        assert err <= tol, f"{what}: max error {err} > {tol}"
+
+
+def with_weights(K, mode, seed=0):
+    """Same complex, weights replaced: 'ones' or random 'int'."""
+    if mode == "ones":
+        return synth.Simplicial(K.coords, K.simplices, "ones", [])
+    g = np.random.default_rng(seed)
+    counts = K.counts()
+    return synth.Simplicial(K.coords, K.simplices, "explicit",
+                            [g.integers(-50, 51, size=c).astype(np.int32) for c in counts])
+
+
+# ---------------------------------------------------------------------------
+# hand examples
+# ---------------------------------------------------------------------------
+
+def test_hand_examples(W):
+    with open(os.path.join(GOLD, "hand_examples.json")) as f:
+        hand = json.load(f)
+    dirs = synth.hand_directions()
+    thr = np.array(hand["thresholds"], np.float32)
+    _say("hand triangle unweighted")
+    got = gpu_wect(W, [synth.single_triangle(False)], dirs, thr)[0]
+    assert np.array_equal(got, hand["triangle"]["unweighted"])
+    _say("hand triangle weighted")
+    got = gpu_wect(W, [synth.single_triangle(True)], dirs, thr)[0]
+    assert np.allclose(got, hand["triangle"]["weighted"], rtol=0, atol=1e-6)
+    for weighted, key in ((True, "weighted"), (False, "unweighted")):
+        _say(f"hand square {key}")
+        got = gpu_wect(W, [synth.single_square(weighted)], dirs, thr)[0]
+        assert np.array_equal(got, hand["square"][key]), key
+
+
+def test_rounding_order(W):
+    with open(os.path.join(GOLD, "rounding_order.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        _say(f"rounding {case['name']}")
+        K = synth.Simplicial(np.array([case["coord"]], np.float32), [None], "ones", [])
+        got = gpu_wect(W, [K], np.array([case["dir"]], np.float32), np.array([case["threshold"]], np.float32))
+        assert got[0, 0, 0] == case["expected_count"]
+
+
+# ---------------------------------------------------------------------------
+# random tiny complexes
+# ---------------------------------------------------------------------------
+
+TINY = [(seed, n, top, wm, wdt) for seed in range(3) for n, top in ((1, 1), (2, 2), (3, 3))
+        for wm, wdt in (("ones", np.int32), ("explicit", np.int32), ("explicit", np.float32),
+                        ("vertex_max", np.float32))]
+
+
+@pytest.mark.parametrize("seed,n,top,wm,wdt", TINY)
+def test_tiny_simplicial(W, seed, n, top, wm, wdt):
+    _say(f"tiny simplicial seed={seed} n={n} top={top} {wm} {np.dtype(wdt).name}")
+    K = synth.random_tiny_complex(seed, n=n, nv=10, top_dim=top, wmode=wm, wdtype=wdt)
+    dirs = (synth.fibonacci_directions(70) if n == 3 else synth.s1_directions(70) if n == 2
+            else np.array([[1.0], [-1.0], [0.5], [0.0]], np.float32))
+    thr = synth.uniform_thresholds(37, 1.6)
+    got = gpu_wect(W, [K], dirs, thr)[0]
+    assert_match(got, oracle.wect(K, dirs, thr), K, "tiny")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_tiny_cubical(W, seed):
+    for shape in ((7, 5), (1, 6), (5, 4, 3), (3, 1, 4)):
+        for weighted in (True, False):
+            _say(f"tiny cubical seed={seed} shape={shape} weighted={weighted}")
+            C = synth.random_tiny_cubical(seed, shape, include_above=60, weighted=weighted)
+            dirs = synth.s1_directions(66) if len(shape) == 2 else synth.fibonacci_directions(66)
+            # directions along the axes (zero components) exercise the ties of the top-corner rule
+            extra = np.eye(len(shape), dtype=np.float32)
+            dirs = np.concatenate([dirs, extra, -extra])
+            thr = synth.uniform_thresholds(19, 1.8)
+            got = gpu_wect(W, [C], dirs, thr)[0]
+            assert_match(got, oracle.wect(C, dirs, thr), C, f"cubical {shape}")
+
+
+# ---------------------------------------------------------------------------
+# threshold arrays: fallback search, duplicates, T = 1, ties
+# ---------------------------------------------------------------------------
+
+def test_threshold_variants(W):
+    K = synth.random_tiny_complex(7, n=2, nv=12, top_dim=2, wmode="explicit", wdtype=np.int32)
+    dirs = synth.s1_directions(40)
+    H = oracle.heights(K.coords, dirs)
+    g = np.random.default_rng(3)
+    variants = {
+        "uniform": synth.uniform_thresholds(50, 1.5),
+        "random_sorted": np.sort(g.uniform(-1.5, 1.5, size=45)).astype(np.float32),
+        "duplicates": np.sort(np.concatenate([synth.uniform_thresholds(20, 1.2)] * 2)).astype(np.float32),
+        "T1": np.array([0.25], np.float32),
+        "T2": np.array([-0.3, 0.4], np.float32),
+        "on_heights": np.unique(np.sort(H.ravel()))[::7].astype(np.float32),
+        "perturbed": synth.uniform_thresholds(64, 1.5),
+    }
+    variants["perturbed"][10] = np.nextafter(variants["perturbed"][10], np.float32(2))
+    for name, thr in variants.items():
+        _say(f"thresholds {name} T={thr.shape[0]}")
+        got = gpu_wect(W, [K], dirs, thr)[0]
+        assert_match(got, oracle.wect(K, dirs, thr), K, name)
+
+
+def test_direction_counts(W):
+    K = synth.random_tiny_complex(2, n=3, nv=11, top_dim=3, wmode="explicit", wdtype=np.int32)
+    thr = synth.uniform_thresholds(33, 1.8)
+    for d in (1, 63, 64, 65, 130):
+        _say(f"directions d={d}")
+        dirs = synth.fibonacci_directions(d)
+        got = gpu_wect(W, [K], dirs, thr)[0]
+        assert_match(got, oracle.wect(K, dirs, thr), K, f"d={d}")
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def test_cfg1_full(W):
+    _say("cfg1 full")
+    w = synth.cfg1()
+    got = gpu_wect(W, w.complexes, w.dirs, w.thr)[0]
+    assert_match(got, oracle.wect(w.complexes[0], w.dirs, w.thr), w.complexes[0], "cfg1")
+
+
+def test_cfg2_full_batch_sampled(W):
+    _say("cfg2 full batch")
+    w = synth.cfg2()
+    got = gpu_wect(W, w.complexes, w.dirs, w.thr)
+    assert got.shape == (256, 64, 128)
+    for b in (0, 1, 77, 255):
+        _say(f"cfg2 image {b} all directions")
+        assert_match(got[b], oracle.wect(w.complexes[b], w.dirs, w.thr), w.complexes[b], f"cfg2[{b}]")
+    for b in range(0, 256, 9):
+        assert_match(got[b, [5, 40]], oracle.wect(w.complexes[b], w.dirs, w.thr, dir_index=[5, 40]),
+                     w.complexes[b], f"cfg2[{b}] sampled")
+
+
+def test_cfg3_full_sampled_directions(W):
+    _say("cfg3 full")
+    w = synth.cfg3()
+    K = w.complexes[0]
+    got = gpu_wect(W, [K], w.dirs, w.thr)[0]
+    sample = [0, 97, 200, 255]
+    assert_match(got[sample], oracle.wect(K, w.dirs, w.thr, dir_index=sample), K, "cfg3 f32")
+    for mode in ("ones", "int"):
+        _say(f"cfg3 rerun with {mode} weights")
+        K2 = with_weights(K, mode)
+        got2 = gpu_wect(W, [K2], w.dirs, w.thr)[0]
+        assert_match(got2[sample], oracle.wect(K2, w.dirs, w.thr, dir_index=sample), K2, f"cfg3 {mode}")
+        # full-size property: at the last threshold every cell below it is counted
+        chi = oracle.euler_characteristic(K2)
+        if mode == "ones":
+            H = oracle.heights(K.coords, w.dirs)
+            ok_dirs = np.where(H.max(axis=1) <= w.thr[-1])[0]
+            assert np.all(got2[ok_dirs, -1] == chi)
+
+
+def test_cfg4_full_batch_sampled(W):
+    _say("cfg4 full batch")
+    w = synth.cfg4()
+    got = gpu_wect(W, w.complexes, w.dirs, w.thr)
+    sizes = [C.intensity.size for C in w.complexes]
+    order = np.argsort(sizes)
+    for b in (int(order[0]), int(order[-1])):
+        _say(f"cfg4 volume {b} size {w.complexes[b].intensity.shape}")
+        sample = [3, 300]
+        assert_match(got[b, sample], oracle.wect(w.complexes[b], w.dirs, w.thr, dir_index=sample),
+                     w.complexes[b], f"cfg4[{b}]")
+
+
+def test_cfg5_forward_backward(W):
+    _say("cfg5 build")
+    w = synth.cfg5()
+    Ks = w.complexes
+    cx = W.SimplicialBatch.from_host(Ks)
+    g = W.Grid(w.dirs, w.thr)
+    out = W.wect_forward(cx, g)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    sizes = [K.coords.shape[0] for K in Ks]
+    pick = [int(np.argmin(sizes)), 17]
+    targets = {}
+    for b in pick:
+        _say(f"cfg5 forward complex {b} V={sizes[b]}")
+        sample = [0, 31, 64, 127]
+        assert_match(out[b, sample], oracle.wect(Ks[b], w.dirs, w.thr, dir_index=sample), Ks[b], f"cfg5[{b}]")
+    # backward: loss = sum (out - target)^2 with target from reseeded weights
+    _say("cfg5 backward")
+    Kt = [synth.Simplicial(K.coords, K.simplices, "vertex_max", [wt]) for K, wt in
+          zip(Ks, w.extra["target_weights"])]
+    tgt = W.wect_forward(W.SimplicialBatch.from_host(Kt), g)
+    gout = 2.0 * (torch.from_numpy(out).cuda() - tgt)
+    gv = W.wect_backward(cx, g, gout)
+    torch.cuda.synchronize()
+    gv = gv.cpu().numpy()
+    voff = np.concatenate([[0], np.cumsum(sizes)])
+    b = pick[0]
+    _say(f"cfg5 oracle gradient complex {b}")
+    gb = gout[b].cpu().numpy().astype(np.float64)
+    ref = oracle.wect_backward(Ks[b], w.dirs, w.thr, gb)
+    bound = oracle.wect_backward(Ks[b], w.dirs, w.thr, gb, absolute=True)
+    mine = gv[voff[b]:voff[b + 1]]
+    assert np.all(np.abs(mine - ref) <= 1e-5 * bound + 1e-6), np.abs(mine - ref).max()
+    # float64 central differences on a few vertices away from weight ties
+    _say("cfg5 finite differences")
+    tgt_b = oracle.wect(Kt[b], w.dirs, w.thr)
+    wv = Ks[b].weights[0].astype(np.float64)
+    e = Ks[b].simplices[1]
+    gap = np.full(sizes[b], np.inf)
+    diff = np.abs(wv[e[:, 0]] - wv[e[:, 1]])
+    np.minimum.at(gap, e[:, 0], diff)
+    np.minimum.at(gap, e[:, 1], diff)
+    cand = [v for v in range(0, sizes[b], max(1, sizes[b] // 60)) if gap[v] > 2e-3][:6]
+    assert len(cand) >= 4
+    fd = oracle.fd_vertex_grad(Ks[b], w.dirs, w.thr, tgt_b, cand, eps=1e-3)
+    # the oracle's own loss gradient (float64 output) must match the differences
+    out_b = oracle.wect(Ks[b], w.dirs, w.thr)
+    g64 = 2.0 * (out_b - tgt_b)
+    ref64 = oracle.wect_backward(Ks[b], w.dirs, w.thr, g64)
+    assert np.allclose(fd, ref64[cand], rtol=1e-8, atol=1e-6)
+    assert np.allclose(mine[cand], fd, rtol=1e-4, atol=1e-3)
+    del wv
+
+
+# ---------------------------------------------------------------------------
+# batching, launch shapes, graphs
+# ---------------------------------------------------------------------------
+
+def test_batched_equals_singles(W):
+    w = synth.cfg2(n_images=12, side=40)
+    _say("cubical batch vs singles")
+    both = gpu_wect(W, w.complexes, w.dirs, w.thr)
+    for b, C in enumerate(w.complexes):
+        assert np.array_equal(both[b], gpu_wect(W, [C], w.dirs, w.thr)[0])
+    _say("simplicial uneven batch with an empty member")
+    Ks = [synth.random_tiny_complex(s, n=2, nv=6 + 2 * s, top_dim=2, wmode="explicit", wdtype=np.int32)
+          for s in range(5)]
+    empty = synth.Simplicial(np.zeros((0, 2), np.float32), [None, np.zeros((0, 2), np.int32),
+                                                            np.zeros((0, 3), np.int32)],
+                             "explicit", [np.zeros(0, np.int32)] * 3)
+    Ks.insert(2, empty)
+    dirs, thr = synth.s1_directions(70), synth.uniform_thresholds(29, 1.5)
+    both = gpu_wect(W, Ks, dirs, thr)
+    assert np.all(both[2] == 0)
+    for b, K in enumerate(Ks):
+        if b == 2:
+            continue
+        assert_match(both[b], oracle.wect(K, dirs, thr), K, f"batch member {b}")
+
+
+def test_launch_shapes_give_identical_integers(W):
+    w = synth.cfg1()
+    K = with_weights(synth.cfg3(n=12).complexes[0], "int")
+    dirs, thr = synth.fibonacci_directions(100), synth.uniform_thresholds(77, 1.8)
+    ref = None
+    try:
+        for block in (256, 512, 1024):
+            for bpc in (1, 2):
+                for mi in (64, 4096):
+                    _say(f"launch block={block} bpc={bpc} min_items={mi}")
+                    W.set_launch(block, bpc, mi)
+                    got = gpu_wect(W, [K], dirs, thr)
+                    if ref is None:
+                        ref = got
+                        assert_match(got[0], oracle.wect(K, dirs, thr), K, "launch ref")
+                    assert np.array_equal(got, ref)
+    finally:
+        W.set_launch()
+    del w
+
+
+def test_graph_capture_forward_backward(W):
+    w = synth.cfg5(n_complexes=6, vmin=500, vmax=3000)
+    cx = W.SimplicialBatch.from_host(w.complexes)
+    g = W.Grid(w.dirs, w.thr)
+    B, d, T = cx.B, g.d, g.T
+    gout = torch.randn(B, d, T, device="cuda")
+    out_e, gv_e = W.wect_batched(cx, g, gout)
+    torch.cuda.synchronize()
+    out_e, gv_e = out_e.clone(), gv_e.clone()
+    ws = torch.empty(W.wect_workspace_bytes(cx, g, True), dtype=torch.uint8, device="cuda")
+    out = torch.empty(B, d, T, device="cuda")
+    gv = torch.empty(cx.counts[0], device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        W.wect_batched(cx, g, gout, out=out, grads=gv, ws=ws)  # warm-up outside the graph
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    _say("graph capture")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        W.wect_batched(cx, g, gout, out=out, grads=gv, ws=ws)
+    for rep in range(3):
+        out.fill_(-7.0)
+        gv.fill_(123.0)
+        _ = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.allclose(out, out_e, rtol=0, atol=1e-4 * float(out_e.abs().max()) + 1e-6), rep
+        assert torch.allclose(gv, gv_e, rtol=1e-5, atol=1e-4 * float(gv_e.abs().max()) + 1e-6), rep
+
+
+def test_autograd_function(W):
+    w = synth.cfg5(n_complexes=3, vmin=300, vmax=900)
+    cx = W.SimplicialBatch.from_host(w.complexes)
+    g = W.Grid(w.dirs, w.thr)
+    wv = cx.weights[0].clone().requires_grad_(True)
+    out = W.wect(cx, g, wv)
+    loss = (out ** 2).sum()
+    loss.backward()
+    ref = W.wect_backward(cx.with_weights([wv.detach()]), g, 2 * out.detach())
+    torch.cuda.synchronize()
+    # float atomics accumulate the per-vertex sums in no fixed order
+    scale = float(ref.abs().max())
+    assert torch.allclose(wv.grad, ref, rtol=1e-5, atol=1e-5 * scale)
+
+
+def test_validate_detects_bad_data(W):
+    from paper_2511_03909_amd import _lib as L
+    K = synth.random_tiny_complex(1, n=2, nv=8, top_dim=2, wmode="explicit", wdtype=np.float32)
+    dirs, thr = synth.s1_directions(8), synth.uniform_thresholds(9, 1.5)
+    cx = W.SimplicialBatch.from_host([K])
+    W.wect_validate(cx, W.Grid(dirs, thr))
+    bad = cx.simplices[1].clone()
+    bad[0, 0] = 99
+    cxb = W.SimplicialBatch(cx.coords, [None, bad, cx.simplices[2]], cx.wmode, cx.weights)
+    with pytest.raises(L.WectError) as e:
+        W.wect_validate(cxb, W.Grid(dirs, thr))
+    assert e.value.status == L.WECT_ERR_INDEX
+    with pytest.raises(L.WectError) as e:
+        W.wect_validate(cx, W.Grid(dirs, thr[::-1].copy()))
+    assert e.value.status == L.WECT_ERR_THRESHOLDS
+    nanc = cx.coords.clone()
+    nanc[1, 0] = float("nan")
+    with pytest.raises(L.WectError) as e:
+        W.wect_validate(W.SimplicialBatch(nanc, cx.simplices, cx.wmode, cx.weights), W.Grid(dirs, thr))
+    assert e.value.status == L.WECT_ERR_NONFINITE
+    C = synth.random_tiny_cubical(0, (5, 4))
+    cc = W.CubicalBatch.from_host([C])
+    W.wect_validate(cc, W.Grid(dirs, thr))
+    cc.axis[1] = cc.axis[0]
+    with pytest.raises(L.WectError) as e:
+        W.wect_validate(cc, W.Grid(dirs, thr))
+    assert e.value.status == L.WECT_ERR_THRESHOLDS

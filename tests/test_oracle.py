@@ -351,3 +351,17 @@ def test_generator_counts():
     T = synth.grid_torus(6, 5)
     assert T.counts() == [30, 90, 60]
     assert synth.octahedron().counts() == [6, 12, 8]
+
+
+def test_cubical_views_match_explicit_cells():
+    """The shifted-view evaluation of image/volume cells equals the explicit
+    cell enumeration (which the brute force and the closed forms pin)."""
+    for seed in range(4):
+        for shape in ((6, 5), (5, 4, 3)):
+            for weighted in (True, False):
+                C = synth.random_tiny_cubical(seed, shape, include_above=70, weighted=weighted)
+                dirs = synth.s1_directions(9) if len(shape) == 2 else synth.fibonacci_directions(9)
+                thr = synth.uniform_thresholds(11, 1.8)
+                a = oracle.wect(C, dirs, thr)
+                b = oracle.wect(oracle.cubical_cells(C), dirs, thr)
+                assert np.array_equal(a, b)
