@@ -220,14 +220,73 @@ def wecf_sorted(fvals: np.ndarray, cells: Cells, thr: np.ndarray):
     return out
 
 
+def _cubical_values(C, hgrid: np.ndarray):
+    """(cell values, signed weights) of every cell of an image/volume for one
+    height grid, by shifted views: a cell spanning the axis set S has as value
+    the maximum height over its 2^|S| corners, is present iff all corners are
+    vertices, and weighs (-1)^|S| * max corner intensity (or (-1)^|S|)."""
+    I = np.asarray(C.intensity)
+    n = I.ndim
+    inc = I.astype(np.int64) > int(C.include_above)
+    Iv = I.astype(np.int64)
+    vals, sws = [], []
+    for r in range(n + 1):
+        for S in itertools.combinations(range(n), r):
+            mh = mi = ok = None
+            for eps in itertools.product((0, 1), repeat=r):
+                sl = [slice(None)] * n
+                for k, e in zip(S, eps):
+                    a = n - 1 - k            # complex axis k is numpy axis n-1-k
+                    sl[a] = slice(e, e + I.shape[a] - 1)
+                sl = tuple(sl)
+                h, iv, ic = hgrid[sl], Iv[sl], inc[sl]
+                mh = h if mh is None else np.maximum(mh, h)
+                mi = iv if mi is None else np.maximum(mi, iv)
+                ok = ic if ok is None else (ok & ic)
+            w = mi[ok] if C.weighted else np.ones(int(ok.sum()), dtype=np.int64)
+            vals.append(mh[ok])
+            sws.append(w if r % 2 == 0 else -w)
+    return np.concatenate(vals), np.concatenate(sws)
+
+
+def _sorted_sums(vals: np.ndarray, sw: np.ndarray, thr: np.ndarray):
+    """sum of sw over {value <= thr[q]} for every q, via one sort."""
+    T = thr.shape[0]
+    if vals.shape[0] == 0:
+        return np.zeros(T, dtype=sw.dtype)
+    order = np.argsort(vals, kind="stable")
+    csum = np.cumsum(sw[order])
+    cnt = np.searchsorted(vals[order], thr, side="right")
+    out = np.zeros(T, dtype=sw.dtype)
+    m = cnt > 0
+    out[m] = csum[cnt[m] - 1]
+    return out
+
+
 def wect(X, dirs: np.ndarray, thr: np.ndarray, dir_index: Optional[Sequence[int]] = None):
     """Sampled WECT [d, T] (Definition "Weighted Euler Characteristic
     Transform"): int64 for integer weights, float64 otherwise.  With
     ``dir_index`` only those directions are evaluated (rows in that order)."""
-    cells = cells_of(X)
     thr = np.asarray(thr, dtype=np.float32)
     dirs = np.asarray(dirs, dtype=np.float32)
     idx = range(dirs.shape[0]) if dir_index is None else list(dir_index)
+    if hasattr(X, "intensity"):
+        # heights on the grid: ((x*sx) + (y*sy)) + (z*sz) with x along numpy's last axis
+        axes = [np.asarray(a, np.float32) for a in X.axes]
+        n = len(axes)
+        rows = []
+        for p in idx:
+            h = None
+            for k in range(n):
+                shp = [1] * n
+                shp[n - 1 - k] = axes[k].shape[0]
+                term = (axes[k] * dirs[p, k]).astype(np.float32).reshape(shp)
+                h = term if h is None else (h + term).astype(np.float32)
+            h = np.broadcast_to(h, np.asarray(X.intensity).shape).astype(np.float32)
+            vals, sw = _cubical_values(X, h)
+            rows.append(_sorted_sums(vals, sw, thr))
+        return np.stack(rows).astype(np.int64) if rows else np.zeros((0, thr.shape[0]), np.int64)
+    cells = cells_of(X)
     rows = []
     for p in idx:
         h = heights(cells.coords, dirs[p:p + 1])[0]
