@@ -1,0 +1,286 @@
+"""Benchmark: WECT simplex*directions per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+
+Headline workload: 256 uint8 images of 128x128 (Gaussian random fields, sigma
+4 px), pixels with intensity > 64 are vertices, cells induced, cell weight =
+max vertex intensity, 64 directions on S^1, 128 thresholds on [-sqrt2, sqrt2],
+int32 output [256, 64, 128], all images in one batched call.  One step = one
+batched forward over the whole batch, inputs resident in HBM.
+
+Items = directions x (cells of every dimension, vertices included), whatever
+shortcut the kernel takes.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WECT simplex·directions/sec fwd & fwd+bwd, batched vs 1-per-launch; HBM GB/s"
+UNIT = "simplex·directions/s"
+HBM_PEAK_GBPS = 8000.0
+# VALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz (non-packed, non-fused)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def cubical_cell_count(C) -> int:
+    """Number of cells (vertices, edges, squares, cubes) of an image/volume
+    under the inclusion rule: a cell exists iff all of its corners exceed the
+    inclusion level.  Bookkeeping for the item count only."""
+    import itertools
+    import numpy as np
+    m = np.asarray(C.intensity) > C.include_above
+    n = m.ndim
+    total = 0
+    for r in range(n + 1):
+        for S in itertools.combinations(range(n), r):
+            ok = None
+            for eps in itertools.product((0, 1), repeat=r):
+                sl = [slice(None)] * n
+                for k, e in zip(S, eps):
+                    a = n - 1 - k
+                    sl[a] = slice(e, e + m.shape[a] - 1)
+                v = m[tuple(sl)]
+                ok = v if ok is None else (ok & v)
+            total += int(ok.sum())
+    return total
+
+
+def included_vertices(C) -> int:
+    import numpy as np
+    return int((np.asarray(C.intensity) > C.include_above).sum())
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("wect_kernels.hip", "wect_api.cpp", "wect_internal.h"):
+        with open(os.path.join(ROOT, "paper_2511_03909_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name: str):
+    """HBM traffic per launch measured with rocprofv3 counters for the current
+    kernel sources (profiles/<name>.json), or None."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration for profiling runs)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2511_03909_amd import api as W
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    if a.copy_calibration:
+        src_t = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)   # 512 MiB
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src_t.numel() * 4, "launches": 3}), flush=True)
+        del src_t, dst_t
+
+    # ---------------- headline: cubical 2D batch, batched forward ----------------
+    w = synth.cfg2()
+    cx = W.CubicalBatch.from_host(w.complexes, device=dev)
+    grid = W.Grid(w.dirs, w.thr, device=dev)
+    d, T, B = grid.d, grid.T, cx.B
+    cells = sum(cubical_cell_count(C) for C in w.complexes)
+    nverts = sum(included_vertices(C) for C in w.complexes)
+    items = d * cells
+    out = torch.empty((B, d, T), dtype=torch.int32, device=dev)
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, grid)), dtype=torch.uint8, device=dev)
+
+    def step():
+        W.wect_forward(cx, grid, out=out, ws=ws)
+
+    sec = timed(step, a.steps, a.warmup)
+    # live kernel timing of the dominant (histogram) kernel with HIP events on its stream
+    W.profile_enable(True)
+    W.profile_read(reset=True)
+    nprof = max(10, a.steps)
+    for _ in range(nprof):
+        step()
+    torch.cuda.synchronize()
+    prof = W.profile_read(reset=True)
+    W.profile_enable(False)
+    k_ms = prof["fwd_ms"] / max(1, prof["fwd_launches"])
+
+    # algorithmic work of the histogram kernel (per launch)
+    # VALU lane-ops per included vertex x direction (top-corner rule, n = 2):
+    #   (n-1) add + ceil(log2(T+1)) search + 1 select + 1 add
+    ops_per_vd = (2 - 1) + math.ceil(math.log2(T + 1)) + 1 + 1
+    alg_ops = ops_per_vd * nverts * d
+    # algorithmic HBM bytes: read every voxel once (uint8) + the axes, write the int32 output once
+    alg_bytes = cx.total_voxels * 1 + int(cx.axis.numel()) * 4 + B * d * T * 4
+    traffic = load_traffic("cubical_fwd_2d_256x128x128_d64_T128")
+    roofline = {
+        "bound": "alu",
+        "achieved": alg_ops / (k_ms * 1e-3) / 1e12,
+        "peak": VALU_PEAK_TOPS,
+        "unit": "TOP/s",
+        "frac": (alg_ops / (k_ms * 1e-3) / 1e12) / VALU_PEAK_TOPS,
+        "traffic": traffic,
+        "kernel": "k_cub_fwd<2, vertex-max>",
+        "kernel_ms": k_ms,
+        "alg_ops_per_launch": alg_ops,
+        "hbm_alg_bytes_per_launch": alg_bytes,
+        "hbm_frac": (alg_bytes / (k_ms * 1e-3) / 1e9) / HBM_PEAK_GBPS,
+        "hbm_achieved_GBps": alg_bytes / (k_ms * 1e-3) / 1e9,
+    }
+    result = {
+        "metric": METRIC,
+        "value": items / sec,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "images": B, "side": 128, "directions": d, "thresholds": T,
+                   "cells": cells, "included_vertices": nverts, "items_per_step": items,
+                   "mode": "batched forward, one call for all images"},
+        "roofline": roofline,
+    }
+
+    # ---------------- one complex per launch (same images) ----------------
+    singles = [W.CubicalBatch.from_host([C], device=dev) for C in w.complexes]
+    outs = [torch.empty((1, d, T), dtype=torch.int32, device=dev) for _ in singles]
+    ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(s, grid) for s in singles)), dtype=torch.uint8,
+                      device=dev)
+
+    def step_single():
+        for s, o in zip(singles, outs):
+            W.wect_forward(s, grid, out=o, ws=ws1)
+
+    sec1 = timed(step_single, max(3, a.steps // 5), 2)
+    result["one_per_launch"] = {"value": items / sec1, "ms_per_step": sec1 * 1e3,
+                                "batched_speedup": sec1 / sec}
+
+    if not a.no_extras:
+        extras = {}
+        # differentiation workload: batched forward + adjoint to vertex weights
+        w5 = synth.cfg5()
+        cx5 = W.SimplicialBatch.from_host(w5.complexes, device=dev)
+        g5 = W.Grid(w5.dirs, w5.thr, device=dev)
+        n5 = sum(cx5.counts)
+        it5 = g5.d * n5
+        gout = torch.randn((cx5.B, g5.d, g5.T), device=dev)
+        o5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device=dev)
+        gv5 = torch.empty(cx5.counts[0], dtype=torch.float32, device=dev)
+        ws5 = torch.empty(max(1, W.wect_workspace_bytes(cx5, g5, True)), dtype=torch.uint8, device=dev)
+        t_fb = timed(lambda: W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5), 10, 2)
+        t_f = timed(lambda: W.wect_batched(cx5, g5, None, out=o5, ws=ws5), 10, 2)
+        # graph-captured forward + backward
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5)
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(graph):
+            W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5)
+        t_g = timed(graph.replay, 10, 2)
+        extras["differentiation_batch64"] = {
+            "workload": w5.name, "items": it5, "fwd_items_per_s": it5 / t_f, "fwd_bwd_items_per_s": it5 / t_fb,
+            "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_graph_ms": t_g * 1e3}
+        del cx5, o5, gv5, ws5, gout
+        # 3D simplicial, float32 weights
+        w3 = synth.cfg3()
+        cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)
+        g3 = W.Grid(w3.dirs, w3.thr, device=dev)
+        it3 = g3.d * sum(cx3.counts)
+        o3 = torch.empty((1, g3.d, g3.T), dtype=torch.float32, device=dev)
+        ws3 = torch.empty(max(1, W.wect_workspace_bytes(cx3, g3)), dtype=torch.uint8, device=dev)
+        t3 = timed(lambda: W.wect_forward(cx3, g3, out=o3, ws=ws3), 5, 1)
+        extras["simplicial_3d_kuhn64"] = {"workload": w3.name, "items": it3, "items_per_s": it3 / t3,
+                                          "ms": t3 * 1e3}
+        del cx3, o3, ws3
+        # 2D simplicial, small: launch-latency bound
+        w1 = synth.cfg1()
+        cx1 = W.SimplicialBatch.from_host(w1.complexes, device=dev)
+        g1 = W.Grid(w1.dirs, w1.thr, device=dev)
+        it1 = g1.d * sum(cx1.counts)
+        o1 = torch.empty((1, g1.d, g1.T), dtype=torch.int32, device=dev)
+        ws1b = torch.empty(max(1, W.wect_workspace_bytes(cx1, g1)), dtype=torch.uint8, device=dev)
+        t1 = timed(lambda: W.wect_forward(cx1, g1, out=o1, ws=ws1b), 50, 5)
+        extras["simplicial_2d_32x32"] = {"workload": w1.name, "items": it1, "items_per_s": it1 / t1,
+                                         "us_per_call": t1 * 1e6}
+        # 3D cubical, 16 volumes of uneven size, one call
+        w4 = synth.cfg4()
+        cx4 = W.CubicalBatch.from_host(w4.complexes, device=dev)
+        g4 = W.Grid(w4.dirs, w4.thr, device=dev)
+        cells4 = sum(cubical_cell_count(C) for C in w4.complexes)
+        it4 = g4.d * cells4
+        o4 = torch.empty((cx4.B, g4.d, g4.T), dtype=torch.int32, device=dev)
+        ws4 = torch.empty(max(1, W.wect_workspace_bytes(cx4, g4)), dtype=torch.uint8, device=dev)
+        t4 = timed(lambda: W.wect_forward(cx4, g4, out=o4, ws=ws4), 3, 1)
+        extras["cubical_3d_16vol"] = {"workload": w4.name, "items": it4, "items_per_s": it4 / t4, "ms": t4 * 1e3}
+        del cx4, o4, ws4
+        result["extras"] = extras
+
+    # ---------------- CPU oracle on a bounded sample of the headline workload ----------------
+    if not a.no_cpu:
+        import oracle
+        sample = list(range(0, B, 8))  # 32 of the 256 images, all 64 directions
+        t0 = time.perf_counter()
+        for b in sample:
+            oracle.wect(w.complexes[b], w.dirs, w.thr)
+        tc = time.perf_counter() - t0
+        it_cpu = d * sum(cubical_cell_count(w.complexes[b]) for b in sample)
+        result["cpu_baseline"] = {"value": it_cpu / tc, "unit": UNIT, "cores": 1, "kind": "oracle",
+                                  "sample": f"{len(sample)} of {B} images (every 8th), all {d} directions, "
+                                            f"{tc:.1f} s, numpy single thread"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

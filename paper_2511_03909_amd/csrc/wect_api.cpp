@@ -70,7 +70,8 @@ struct Plan {
   Params p;
   int block = 1024;
   size_t lds_fwd = 0, lds_bwd = 0;
-  size_t partial_bytes = 0;
+  size_t partial_bytes = 0, dsum_bytes = 0, absmax_bytes = 0;
+  bool split = false;
   size_t ws_fwd = 0, ws_bwd = 0;
   int64_t elems = 0;  // stream elements per direction tile / group
   int G_fwd = 0, G_bwd = 0;
@@ -79,6 +80,7 @@ struct Plan {
 };
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Check host metadata and build the plan.  need_bwd: backward requested.
 wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl) {
@@ -180,23 +182,31 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
 
   if (need_fwd && g->d > 0 && g->T > 0) {
     // forward LDS: histogram [T+1][64] + threshold pairs + staged entries
-    int stage = block;
-    size_t lds = wect::forward_lds_bytes(g->T, stage, c->kind, c->n);
-    while (lds > kLdsLimit && stage > 256) {
-      stage /= 2;
-      lds = wect::forward_lds_bytes(g->T, stage, c->kind, c->n);
-    }
-    if (lds > kLdsLimit) return WECT_ERR_UNSUPPORTED;
+    const int acc_bytes = (c->kind == WECT_SIMPLICIAL && c->dtype == WECT_F32) ? 8 : 4;
+    const size_t fixed = wect::forward_lds_fixed(g->T, c->kind, acc_bytes);
+    const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
+    if (fixed + 64 * entry > kLdsLimit) return WECT_ERR_UNSUPPORTED;
+    int stage = (int)std::min<size_t>(block, (kLdsLimit - fixed) / entry);
+    stage = stage / 64 * 64;
     p.stage = stage;
-    pl->lds_fwd = lds;
+    pl->lds_fwd = fixed + (size_t)stage * entry;
     const int64_t S = (int64_t)ntiles * elems;
     int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
     G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
     pl->G_fwd = (int)G;
     pl->S_fwd = S;
-    const int64_t slots = G + (int64_t)c->B * ntiles;
-    pl->partial_bytes = (size_t)slots * (size_t)g->T * kW * 4;
-    pl->ws_fwd = pl->partial_bytes;
+    const int64_t groups = (int64_t)c->B * ntiles;
+    const int64_t slots = G + groups;
+    const size_t slot_bytes = (size_t)g->T * kW * acc_bytes;
+    // slots a group may have: blocks meeting its stream range
+    const int64_t spg = c->B == 1 ? ceil_div(G, ntiles) + 1 : G;
+    pl->split = spg > 8;
+    pl->partial_bytes = align256((size_t)slots * slot_bytes);
+    pl->dsum_bytes = pl->split ? align256((size_t)groups * slot_bytes) : 0;
+    pl->absmax_bytes = acc_bytes == 8 ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
+    pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes;
+    p.nabsmax = acc_bytes == 8 ? wect::kAbsmaxSlots : 0;
+    p.cells_total = (double)std::max<int64_t>(elems, 1);
   }
   if (need_bwd && g->d > 0 && g->T > 0) {
     int dg = std::min(ntiles, 4);
@@ -244,11 +254,18 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   if (pl.ws_fwd > 0 && (!ws || ws_bytes < pl.ws_fwd)) return WECT_ERR_WORKSPACE;
   if (ws && (reinterpret_cast<uintptr_t>(ws) & 15)) return WECT_ERR_ARG;
   p.out = out;
-  p.partial = ws;
+  unsigned char* w8 = static_cast<unsigned char*>(ws);
+  p.partial = w8;
+  p.dsum = pl.dsum_bytes ? w8 + pl.partial_bytes : nullptr;
+  p.split = pl.split ? 1 : 0;
+  p.absmax = pl.absmax_bytes ? reinterpret_cast<float*>(w8 + pl.partial_bytes + pl.dsum_bytes) : nullptr;
   p.G = pl.G_fwd;
   p.S = pl.S_fwd;
   const bool prof = g_profile.load() != 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p.nabsmax > 0) {
+    if (hipError_t e = wect::launch_absmax(p, s); e != hipSuccess) return device_error(e, "abs-max kernel");
+  }
   if (p.S > 0) {
     if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
     if (hipError_t e = wect::launch_forward_main(p, pl.block, pl.lds_fwd, s); e != hipSuccess)

@@ -38,7 +38,12 @@ struct Params {
   int32_t stage;         // staged entries per tile (<= blockDim.x)
   int32_t dg;            // backward: direction tiles held in LDS at once
   int32_t ngroups_dir;   // backward: number of direction groups ( = ceil(ntiles / dg) )
-  void* partial;         // forward: [slots][T][64] int32 / float32
+  void* partial;         // forward: [slots][T][64] uint32 (integer weights) / uint64 (fixed point)
+  void* dsum;            // forward, split reduction: [groups][T][64] slot sums
+  int32_t split;         // 1: k_slot_sum first, then the scan reads dsum
+  float* absmax;         // float32 weights: per-block max |w| ([nabsmax])
+  int32_t nabsmax;
+  double cells_total;    // bound on the cells of any complex (fixed-point scale)
   void* out;             // forward: [B][d][T]
   // backward
   const float* grad_out;         // [B][d][T]
@@ -54,9 +59,15 @@ hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hi
 hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s);
 hipError_t launch_validate(const Params& p, int* flags, hipStream_t s);
 
-// LDS bytes the main kernels need for a given T, staged entries and stride.
-size_t forward_lds_bytes(int T, int stage, int kind, int n);
+hipError_t launch_absmax(const Params& p, hipStream_t s);
+
+// LDS bytes of the forward kernels: fixed part (histogram, thresholds) plus
+// forward_entry_bytes per staged entry; of the backward kernel in total.
+size_t forward_lds_fixed(int T, int kind, int acc_bytes);
+size_t forward_entry_bytes(int kind, int n);
 size_t backward_lds_bytes(int T, int stage, int dg);
+
+constexpr int kAbsmaxSlots = 256;  // 64 blocks x 4 weight arrays
 
 // Validation flags (bit set = failure).
 enum : int { kFlagIndex = 1, kFlagThr = 2, kFlagNonfinite = 4 };

@@ -153,7 +153,7 @@ __device__ void setup_thresholds(const float* thr, int T, float2* P, Thr& th) {
 __device__ __forceinline__ void lds_add(uint32_t* a, uint32_t v) {
   __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void lds_add(float* a, float v) {
+__device__ __forceinline__ void lds_add(uint64_t* a, uint64_t v) {
   __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -214,17 +214,52 @@ __device__ __forceinline__ int64_t block_start(int64_t k, int64_t S, int64_t G) 
 // simplicial staging: one thread gathers one simplex into registers
 // ---------------------------------------------------------------------------
 
-template <int N, int DIM>
-struct SimpLayout {
-  static constexpr int NV = DIM + 1;
-  static constexpr int WOFF = NV * N;          // weight slot
-  static constexpr int OOFF = NV * N + 1;      // owner slot (vertex-max backward)
-  static constexpr int STRIDE = ((NV * N + 2 + 3) / 4) * 4;
+// Forward accumulator: unit and int32 weights accumulate in uint32 (two's
+// complement, wraps exactly like int32); float32 weights are converted to
+// signed 64-bit fixed point (see fixed_exp) and accumulate in uint64.  Integer
+// LDS atomics run one lane per bank per pass, float ones do not, and integer
+// sums do not depend on the order of the additions.
+template <typename WT>
+struct AccOf {
+  using T = uint32_t;
+};
+template <>
+struct AccOf<float> {
+  using T = uint64_t;
 };
 
-template <int N, int DIM, int WM, typename WT>
+template <int N, int DIM, typename ACC>
+struct SimpLayout {
+  static constexpr int NV = DIM + 1;
+  static constexpr int WW = sizeof(ACC) / 4;                 // words of the staged weight
+  static constexpr int WOFF = ((NV * N + WW - 1) / WW) * WW;  // weight slot, aligned to its size
+  static constexpr int OOFF = WOFF + WW;                     // owner slot (vertex-max backward)
+  static constexpr int STRIDE = ((OOFF + 1 + 3) / 4) * 4;
+  static_assert(STRIDE <= kMaxStride, "entry too large");
+};
+
+// Exponent e of the fixed-point scale 2^e for float32 weights: with M the
+// largest |w| and C the number of cells, every sum of rounded weights stays
+// below C * (M 2^e + 1/2) < 2^63.  Computed identically by every block from
+// the per-block maxima written by k_absmax.
+__device__ __forceinline__ int fixed_exp(const Params& p) {
+  float M = 0.0f;
+  for (int i = 0; i < p.nabsmax; ++i) M = fmaxf(M, p.absmax[i]);
+  const double X = (double)M * p.cells_total;
+  if (!(X > 0.0) || !isfinite(X)) return 0;
+  int ex = 0;
+  (void)frexp(X, &ex);  // X = f 2^ex, f in [0.5, 1): floor(log2 X) = ex - 1
+  return 61 - (ex - 1);
+}
+
+__device__ __forceinline__ uint64_t to_fixed(float w, int e) {
+  return (uint64_t)(int64_t)rint(ldexp((double)w, e));
+}
+
+template <int N, int DIM, int WM, typename WT, bool FWD>
 struct SimpStager {
-  using L = SimpLayout<N, DIM>;
+  using ACC = typename AccOf<WT>::T;
+  using L = SimpLayout<N, DIM, ACC>;
   float e[L::OOFF + 1];
   int idx[L::NV];
 
@@ -238,20 +273,34 @@ struct SimpStager {
       for (int j = 0; j < L::NV; ++j) idx[j] = s[j];
     }
   }
-  // coordinates and weight of the simplex whose ids are in idx
-  __device__ __forceinline__ void gather(const Params& p, int64_t row, int64_t voff) {
+  __device__ __forceinline__ void put_weight(ACC a) {
+    if constexpr (DIM & 1) a = ACC(0) - a;  // (-1)^dim: the forward stages signed weights
+    if constexpr (sizeof(ACC) == 4) {
+      e[L::WOFF] = bitcast<float>(a);
+    } else {
+      e[L::WOFF] = bitcast<float>((uint32_t)a);
+      e[L::WOFF + 1] = bitcast<float>((uint32_t)(a >> 32));
+    }
+  }
+  // coordinates, signed weight and owner vertex of the simplex whose ids are in idx
+  __device__ __forceinline__ void gather(const Params& p, int64_t row, int64_t voff, int fexp) {
 #pragma unroll
     for (int j = 0; j < L::NV; ++j) {
       const float* c = p.coords + (voff + idx[j]) * N;
 #pragma unroll
       for (int k = 0; k < N; ++k) e[j * N + k] = c[k];
     }
+#pragma unroll
+    for (int k = L::NV * N; k < L::WOFF; ++k) e[k] = 0.0f;
+    e[L::OOFF] = 0.0f;
     if constexpr (WM == WM_ONES) {
-      e[L::WOFF] = bitcast<float>(1u);
-      e[L::OOFF] = 0.0f;
+      if constexpr (FWD) put_weight(ACC(1));
     } else if constexpr (WM == WM_EXPLICIT) {
-      e[L::WOFF] = bitcast<float>(((const WT*)p.weights[DIM])[row]);
-      e[L::OOFF] = 0.0f;
+      if constexpr (FWD) {
+        const WT w = ((const WT*)p.weights[DIM])[row];
+        if constexpr (sizeof(ACC) == 4) put_weight(bitcast<ACC>(w));
+        else put_weight(to_fixed(w, fexp));
+      }
     } else {
       const float* w = (const float*)p.weights[0];
       float best = w[voff + idx[0]];
@@ -261,7 +310,7 @@ struct SimpStager {
         float x = w[voff + idx[j]];
         if (x > best || (x == best && idx[j] < own)) { best = x; own = idx[j]; }
       }
-      e[L::WOFF] = best;
+      if constexpr (FWD) put_weight(to_fixed(best, fexp));
       e[L::OOFF] = bitcast<float>(own);
     }
   }
@@ -269,13 +318,13 @@ struct SimpStager {
 #pragma unroll
     for (int k = 0; k <= L::OOFF; ++k) dst[k] = e[k];
   }
-  // forward entry: the weight slot holds the signed weight (-1)^DIM w
-  __device__ __forceinline__ void store_signed(float* dst) const {
-#pragma unroll
-    for (int k = 0; k <= L::OOFF; ++k) dst[k] = e[k];
-    if constexpr (DIM & 1) dst[L::WOFF] = bitcast<float>(WT(0) - bitcast<WT>(e[L::WOFF]));
-  }
 };
+
+template <typename ACC>
+__device__ __forceinline__ ACC load_weight(const float* E) {
+  if constexpr (sizeof(ACC) == 4) return bitcast<ACC>(E[0]);
+  else return *(const uint64_t*)E;
+}
 
 // Maximum height of a staged simplex for the lane's direction.
 template <int N, int DIM>
@@ -292,23 +341,26 @@ __device__ __forceinline__ float max_height(const float* E, float sx, float sy, 
 // of the coordinate gather, which runs one tile ahead of the histogram.
 template <int N, int DIM, int WM, typename WT, bool FAST>
 __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
-                               float sx, float sy, float sz, WT* hist, float* stage, const Thr& th) {
-  using L = SimpLayout<N, DIM>;
+                               float sx, float sy, float sz, typename AccOf<WT>::T* hist, float* stage,
+                               const Thr& th, int fexp) {
+  using ACC = typename AccOf<WT>::T;
+  using L = SimpLayout<N, DIM, ACC>;
+  using ST = SimpStager<N, DIM, WM, WT, true>;
   const int tid = threadIdx.x, lane = tid & (W - 1);
   const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
   const int TS = p.stage;
   const int64_t ntile = (hi - lo + TS - 1) / TS;
-  SimpStager<N, DIM, WM, WT> st;
+  ST st;
   auto tile_row = [&](int64_t t) { return lo + t * TS + tid; };
   // prologue: ids of tile 0, gather tile 0, ids of tile 1
   if (tid < TS && tile_row(0) < hi) {
     st.load_idx(p, soff + tile_row(0), tile_row(0));
-    st.gather(p, soff + tile_row(0), voff);
+    st.gather(p, soff + tile_row(0), voff, fexp);
   }
   int nidx[L::NV];
   bool have_next = ntile > 1 && tid < TS && tile_row(1) < hi;
   if (have_next) {
-    SimpStager<N, DIM, WM, WT> tmp;
+    ST tmp;
     tmp.load_idx(p, soff + tile_row(1), tile_row(1));
 #pragma unroll
     for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
@@ -316,17 +368,17 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
   for (int64_t t = 0; t < ntile; ++t) {
     const int cnt = (int)mn64(TS, hi - (lo + t * TS));
     __syncthreads();
-    if (tid < cnt) st.store_signed(stage + tid * L::STRIDE);
+    if (tid < cnt) st.store(stage + tid * L::STRIDE);
     __syncthreads();
     // gather tile t+1 (ids loaded last iteration), load ids of tile t+2
     if (have_next) {
 #pragma unroll
       for (int j = 0; j < L::NV; ++j) st.idx[j] = nidx[j];
-      st.gather(p, soff + tile_row(t + 1), voff);
+      st.gather(p, soff + tile_row(t + 1), voff, fexp);
     }
     have_next = (t + 2 < ntile) && tid < TS && tile_row(t + 2) < hi;
     if (have_next) {
-      SimpStager<N, DIM, WM, WT> tmp;
+      ST tmp;
       tmp.load_idx(p, soff + tile_row(t + 2), tile_row(t + 2));
 #pragma unroll
       for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
@@ -338,8 +390,8 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
       const float* E1 = stage + (e + nw) * L::STRIDE;
       float h0 = max_height<N, DIM>(E0, sx, sy, sz);
       float h1 = max_height<N, DIM>(E1, sx, sy, sz);
-      WT w0 = bitcast<WT>(E0[L::WOFF]);
-      WT w1 = bitcast<WT>(E1[L::WOFF]);
+      ACC w0 = load_weight<ACC>(E0 + L::WOFF);
+      ACC w1 = load_weight<ACC>(E1 + L::WOFF);
       int b0 = thr_index<FAST>(h0, th);
       int b1 = thr_index<FAST>(h1, th);
       lds_add(&hist[b0 * W + lane], w0);
@@ -348,7 +400,7 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
     if (e < cnt) {
       const float* E0 = stage + e * L::STRIDE;
       float h0 = max_height<N, DIM>(E0, sx, sy, sz);
-      WT w0 = bitcast<WT>(E0[L::WOFF]);
+      ACC w0 = load_weight<ACC>(E0 + L::WOFF);
       int b0 = thr_index<FAST>(h0, th);
       lds_add(&hist[b0 * W + lane], w0);
     }
@@ -358,24 +410,24 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
 
 template <int N, int WM, typename WT, bool FAST>
 __device__ __forceinline__ void simp_fwd_dim(int dim, const Params& p, int64_t lo, int64_t hi, int64_t voff,
-                                             int64_t soff, float sx, float sy, float sz, WT* hist, float* stage,
-                                             const Thr& th) {
+                                             int64_t soff, float sx, float sy, float sz,
+                                             typename AccOf<WT>::T* hist, float* stage, const Thr& th, int fexp) {
   switch (dim) {
-    case 0: simp_fwd_range<N, 0, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
-    case 1: simp_fwd_range<N, 1, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
-    case 2: simp_fwd_range<N, 2, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
-    default: simp_fwd_range<N, 3, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th); break;
+    case 0: simp_fwd_range<N, 0, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
+    case 1: simp_fwd_range<N, 1, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
+    case 2: simp_fwd_range<N, 2, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
+    default: simp_fwd_range<N, 3, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
   }
 }
 
-template <typename WT>
-__device__ void flush_hist(const Params& p, WT* hist, int64_t slot) {
+template <typename ACC>
+__device__ void flush_hist(const Params& p, ACC* hist, int64_t slot) {
   __syncthreads();
   const int T = p.T;
-  WT* dst = (WT*)p.partial + slot * (int64_t)T * W;
+  ACC* dst = (ACC*)p.partial + slot * (int64_t)T * W;
   for (int i = threadIdx.x; i < T * W; i += blockDim.x) dst[i] = hist[i];
   __syncthreads();
-  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = WT(0);
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = ACC(0);
   __syncthreads();
 }
 
@@ -397,14 +449,17 @@ __device__ __forceinline__ size_t align_up(size_t x, size_t a) { return (x + a -
 
 template <int N, int WM, typename WT>
 __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
+  using ACC = typename AccOf<WT>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = p.T;
-  WT* hist = (WT*)smem;
-  float2* P = (float2*)(smem + (size_t)(T + 1) * W * sizeof(WT));
-  float* stage = (float*)(smem + (size_t)(T + 1) * W * sizeof(WT) + align_up((size_t)(T + 1) * 8, 16));
+  ACC* hist = (ACC*)smem;
+  float2* P = (float2*)(smem + (size_t)(T + 1) * W * sizeof(ACC));
+  float* stage = (float*)(smem + (size_t)(T + 1) * W * sizeof(ACC) + align_up((size_t)(T + 1) * 8, 16));
   Thr th;
   setup_thresholds(p.thr, T, P, th);
-  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = WT(0);
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = ACC(0);
+  int fexp = 0;
+  if constexpr (sizeof(ACC) == 8) fexp = fixed_exp(p);
   __syncthreads();
 
   const int k = blockIdx.x;
@@ -434,12 +489,14 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
       const int64_t lo = mx64(e0, dlo), hi = mn64(e1, dhi);
       if (lo < hi) {
         const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
-        if (th.fast) simp_fwd_dim<N, WM, WT, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th);
-        else simp_fwd_dim<N, WM, WT, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th);
+        if (th.fast)
+          simp_fwd_dim<N, WM, WT, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th, fexp);
+        else
+          simp_fwd_dim<N, WM, WT, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th, fexp);
       }
       dlo = dhi;
     }
-    flush_hist<WT>(p, hist, (int64_t)k + (int64_t)b * gpc + t);
+    flush_hist<ACC>(p, hist, (int64_t)k + (int64_t)b * gpc + t);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;
   }
@@ -636,68 +693,150 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
 // (cumulative sum of Algorithm 1): out[b][p][q] = sum_{j <= q} D[p][j]
 // ---------------------------------------------------------------------------
 
-template <typename WT>
-struct ScanAcc;
-template <>
-struct ScanAcc<uint32_t> {
-  using T = uint32_t;
-  __device__ static uint32_t out(T x) { return x; }
-};
-template <>
-struct ScanAcc<float> {
-  using T = double;
-  __device__ static float out(T x) { return (float)x; }
-};
-
-template <typename WT>
-__global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
-  using A = typename ScanAcc<WT>::T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int T = p.T;
-  const int LS = T + 1;                 // padded row of the transposed result
-  WT* L = (WT*)smem;                    // [64][T+1]
-  A* tot = (A*)(smem + align_up((size_t)W * LS * sizeof(WT), 16));  // [nr][64]
-  const int g = blockIdx.x;
+// Slots of the partial buffer written for group g = (complex b, tile t): the
+// blocks whose stream range meets the group's range [gs, ge) are kfirst..klast
+// (block k covers [k S / G, (k+1) S / G)), and block k wrote slot k + g.
+__device__ __forceinline__ void group_slots(const Params& p, int g, int64_t& kfirst, int64_t& klast) {
   const int gpc = p.ntiles;
   const int b = g / gpc, t = g % gpc;
-  const int lane = threadIdx.x & (W - 1), r = threadIdx.x >> 6, nr = blockDim.x >> 6;
-  const int chunk = (T + nr - 1) / nr;
-  const int q0 = min(T, r * chunk), q1 = min(T, q0 + chunk);
-
   const int64_t cb = cum_elems(p, b);
   const int64_t nb = cum_elems(p, b + 1) - cb;
-  int64_t kfirst = 0, klast = -1;
+  kfirst = 0;
+  klast = -1;
   if (nb > 0 && p.S > 0) {
     const int64_t gs = (int64_t)gpc * cb + (int64_t)t * nb;
     const int64_t ge = gs + nb;
     kfirst = ((gs + 1) * p.G - 1) / p.S;
     klast = (ge * p.G - 1) / p.S;
   }
-  A run = A(0);
-  for (int q = q0; q < q1; ++q) {
-    A v = A(0);
-    for (int64_t kk = kfirst; kk <= klast; ++kk) {
-      const WT* src = (const WT*)p.partial + ((kk + g) * (int64_t)T + q) * W;
-      v += (A)src[lane];
-    }
-    run += v;
-    L[lane * LS + q] = (WT)run;
+}
+
+// Sum of the partial histograms of every group into dsum[g][T][64] (used when
+// groups have many slots): one thread per (group, threshold, lane).
+template <typename ACC>
+__global__ __launch_bounds__(256) void k_slot_sum(Params p) {
+  const int g = blockIdx.x;
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (W - 1);
+  const int T = p.T;
+  if (q >= T) return;
+  int64_t kfirst, klast;
+  group_slots(p, g, kfirst, klast);
+  const ACC* src = (const ACC*)p.partial + (int64_t)q * W + lane;
+  const int64_t slot_stride = (int64_t)T * W;
+  ACC v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+  int64_t kk = kfirst;
+  for (; kk + 3 <= klast; kk += 4) {
+    v0 += src[(kk + g) * slot_stride];
+    v1 += src[(kk + 1 + g) * slot_stride];
+    v2 += src[(kk + 2 + g) * slot_stride];
+    v3 += src[(kk + 3 + g) * slot_stride];
   }
-  tot[r * W + lane] = run;
+  for (; kk <= klast; ++kk) v0 += src[(kk + g) * slot_stride];
+  ((ACC*)p.dsum)[((int64_t)g * T + q) * W + lane] = (v0 + v1) + (v2 + v3);
+}
+
+template <typename ACC>
+struct OutOf;
+template <>
+struct OutOf<uint32_t> {
+  using T = uint32_t;  // int32 bit pattern
+  __device__ static uint32_t conv(uint32_t x, int) { return x; }
+};
+template <>
+struct OutOf<uint64_t> {
+  using T = float;
+  __device__ static float conv(uint64_t x, int fexp) { return (float)ldexp((double)(int64_t)x, -fexp); }
+};
+
+// Per group (complex, direction tile): sum its slots (or read its dsum row),
+// scan along the thresholds (cumulative sum of Algorithm 1,
+// out[b][p][q] = sum_{j <= q} D[p][j]) and write the 64 x T block of out.
+// 16 row chunks x 64 lanes: each thread keeps its chunk in registers.
+template <typename ACC, int CH>
+__global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
+  using O = OutOf<ACC>;
+  using OT = typename O::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T;
+  const int LS = T + 1;  // padded row of the transposed result
+  OT* L = (OT*)smem;     // [64][T+1]
+  ACC* tot = (ACC*)(smem + align_up((size_t)W * LS * sizeof(OT), 16));  // [16][64]
+  const int g = blockIdx.x;
+  const int gpc = p.ntiles;
+  const int b = g / gpc, t = g % gpc;
+  const int lane = threadIdx.x & (W - 1), r = threadIdx.x >> 6;
+  const int chunk = (T + 15) / 16;
+  const int q0 = min(T, r * chunk), nq = min(T, q0 + chunk) - q0;
+  int fexp = 0;
+  if constexpr (sizeof(ACC) == 8) fexp = fixed_exp(p);
+
+  ACC acc[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) acc[j] = 0;
+  if (r < 16) {
+    const int64_t slot_stride = (int64_t)T * W;
+    if (p.split) {
+      const ACC* src = (const ACC*)p.dsum + (int64_t)g * slot_stride + (int64_t)q0 * W + lane;
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (j < nq) acc[j] = src[(int64_t)j * W];
+    } else {
+      int64_t kfirst, klast;
+      group_slots(p, g, kfirst, klast);
+      for (int64_t kk = kfirst; kk <= klast; ++kk) {
+        const ACC* src = (const ACC*)p.partial + (kk + g) * slot_stride + (int64_t)q0 * W + lane;
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+          if (j < nq) acc[j] += src[(int64_t)j * W];
+      }
+    }
+  }
+  ACC run = 0;
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    run += acc[j];
+    acc[j] = run;
+  }
+  if (r < 16) tot[r * W + lane] = run;
   __syncthreads();
-  A offv = A(0);
-  for (int rr = 0; rr < r; ++rr) offv += tot[rr * W + lane];
-  if (offv != A(0)) {
-    // re-add in the wide type: local prefix + offset
-    for (int q = q0; q < q1; ++q) L[lane * LS + q] = ScanAcc<WT>::out((A)L[lane * LS + q] + offv);
+  ACC off = 0;
+  for (int rr = 0; rr < r && rr < 16; ++rr) off += tot[rr * W + lane];
+  if (r < 16) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if (j < nq) L[lane * LS + q0 + j] = O::conv(acc[j] + off, fexp);
   }
   __syncthreads();
   const int dv = min(W, p.d - t * W);
-  WT* out = (WT*)p.out + ((int64_t)b * p.d + (int64_t)t * W) * T;
+  OT* out = (OT*)p.out + ((int64_t)b * p.d + (int64_t)t * W) * T;
   for (int i = threadIdx.x; i < dv * T; i += blockDim.x) {
     const int pp = i / T, q = i - pp * T;
     out[i] = L[pp * LS + q];
   }
+}
+
+// Largest |w| over the float32 weights, per block: absmax[dim * 64 + block].
+__global__ __launch_bounds__(256) void k_absmax(Params p) {
+  __shared__ float red[256];
+  const int dim = blockIdx.y;
+  const float* w = nullptr;
+  int64_t n = 0;
+  if (p.wmode == WM_VMAX) {
+    if (dim == 0) { w = (const float*)p.weights[0]; n = p.count[0]; }
+  } else if (dim <= p.top_dim) {
+    w = (const float*)p.weights[dim];
+    n = p.count[dim];
+  }
+  float m = 0.0f;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = fmaxf(m, fabsf(w[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) p.absmax[dim * gridDim.x + blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -716,17 +855,17 @@ template <int N, int DIM, int WM, bool FAST>
 __device__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
                                const float* sx, const float* sy, const float* sz, int ntl,
                                const float* Gt, float* stage, const Thr& th) {
-  using L = SimpLayout<N, DIM>;
+  using L = SimpLayout<N, DIM, uint64_t>;
   const int tid = threadIdx.x, lane = tid & (W - 1);
   const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
   const int TS = p.stage;
   const int T1 = p.T + 1;
-  SimpStager<N, DIM, WM, float> st;
+  SimpStager<N, DIM, WM, float, false> st;
   for (int64_t t0 = lo; t0 < hi; t0 += TS) {
     const int cnt = (int)mn64(TS, hi - t0);
     if (tid < cnt) {
       st.load_idx(p, soff + t0 + tid, t0 + tid);
-      st.gather(p, soff + t0 + tid, voff);
+      st.gather(p, soff + t0 + tid, voff, 0);
       st.store(stage + tid * L::STRIDE);
     }
     __syncthreads();
@@ -968,12 +1107,14 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
 // launchers
 // ---------------------------------------------------------------------------
 
-size_t forward_lds_bytes(int T, int stage, int kind, int n) {
-  size_t hist = (size_t)(T + 1) * W * 4;
+size_t forward_lds_fixed(int T, int kind, int acc_bytes) {
+  size_t hist = (size_t)(T + 1) * W * acc_bytes;
   size_t pairs = ((size_t)(T + 1) * 8 + 15) / 16 * 16;
-  size_t stride = kind == 1 ? (n == 2 ? 8 : 12) : kMaxStride;
-  return hist + pairs + 16 + (size_t)stage * stride * 4;
+  (void)kind;
+  return hist + pairs + 16;
 }
+
+size_t forward_entry_bytes(int kind, int n) { return (size_t)(kind == 1 ? (n == 2 ? 8 : 12) : kMaxStride) * 4; }
 
 size_t backward_lds_bytes(int T, int stage, int dg) {
   size_t g = (size_t)dg * (T + 1) * W * 4;
@@ -981,10 +1122,10 @@ size_t backward_lds_bytes(int T, int stage, int dg) {
   return g + pairs + (size_t)stage * kMaxStride * 4;
 }
 
-static size_t reduce_lds_bytes(int T, int dtype, int nr) {
+static size_t reduce_lds_bytes(int T) {
   size_t lsz = (size_t)W * (T + 1) * 4;
   lsz = (lsz + 15) / 16 * 16;
-  return lsz + (size_t)nr * W * 8;
+  return lsz + (size_t)16 * W * 8;
 }
 
 template <int N, int WM, typename WT>
@@ -1025,17 +1166,27 @@ hipError_t launch_forward_main(const Params& p, int block, size_t lds, hipStream
   }
 }
 
-hipError_t launch_forward_reduce(const Params& p, hipStream_t s) {
-  const int block = 1024, nr = block / W;
-  const size_t lds = reduce_lds_bytes(p.T, p.dtype, nr);
+template <typename ACC, int CH>
+static hipError_t launch_reduce_t(const Params& p, hipStream_t s) {
   const int groups = p.B * p.ntiles;
-  if (p.dtype == 1) {
-    if (hipError_t e = set_lds_limit(k_reduce_scan<float>, lds); e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_scan<float>, dim3(groups), dim3(block), lds, s, p);
-  } else {
-    if (hipError_t e = set_lds_limit(k_reduce_scan<uint32_t>, lds); e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_scan<uint32_t>, dim3(groups), dim3(block), lds, s, p);
+  if (p.split) {
+    hipLaunchKernelGGL(k_slot_sum<ACC>, dim3(groups, (p.T + 3) / 4), dim3(256), 0, s, p);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   }
+  const size_t lds = reduce_lds_bytes(p.T);
+  if (hipError_t e = set_lds_limit(k_reduce_scan<ACC, CH>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_reduce_scan<ACC, CH>), dim3(groups), dim3(1024), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_reduce(const Params& p, hipStream_t s) {
+  const bool wide = p.kind == 0 && p.dtype == 1;
+  if (p.T <= 256) return wide ? launch_reduce_t<uint64_t, 16>(p, s) : launch_reduce_t<uint32_t, 16>(p, s);
+  return wide ? launch_reduce_t<uint64_t, 48>(p, s) : launch_reduce_t<uint32_t, 48>(p, s);
+}
+
+hipError_t launch_absmax(const Params& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_absmax, dim3(p.nabsmax / 4, 4), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
