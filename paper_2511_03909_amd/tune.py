@@ -1,0 +1,113 @@
+"""Launch-shape autotuner.
+
+For one request (a complex batch and a sampling grid) it times the forward for a
+set of launch shapes (threads per block, blocks per compute unit, minimum stream
+items per block) and keeps the fastest.  Results are cached in a JSON file
+keyed by a signature of the request (kind, ambient dimension, batch size,
+total cells rounded to a power of two, directions, thresholds, dtype), so a
+workload of the same shape reuses the choice.
+
+The direction tile is fixed at one wavefront (64 directions, one per lane) and
+the histograms always live in LDS, so the shape knobs are the only ones.
+
+    from paper_2511_03909_amd import tune
+    shape = tune.tune(cx, grid)        # times, caches, applies
+    tune.apply(shape)                  # or later: tune.lookup(cx, grid)
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, Iterable, Optional, Tuple
+
+import torch
+
+from . import api
+
+DEFAULT_CACHE = os.environ.get("WECT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "wect_tune.json"))
+
+CANDIDATES: Tuple[Tuple[int, int, int], ...] = (
+    (1024, 0, 0), (1024, 1, 0), (1024, 2, 0),
+    (512, 0, 0), (512, 2, 0), (512, 4, 0),
+    (256, 0, 0), (256, 4, 0),
+    (512, 0, 256), (1024, 0, 256), (512, 0, 8192),
+)
+
+
+def signature(cx, grid) -> str:
+    if isinstance(cx, api.CubicalBatch):
+        cells = cx.total_voxels
+        kind = "cubical"
+    else:
+        cells = sum(cx.counts)
+        kind = "simplicial"
+    bucket = 1 << max(0, int(math.ceil(math.log2(max(cells, 1)))))
+    return f"{kind}/n{cx.n}/B{cx.B}/cells~{bucket}/d{grid.d}/T{grid.T}/dtype{cx.dtype}"
+
+
+def _load(path: str) -> Dict[str, dict]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path: str, data: Dict[str, dict]) -> None:
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply(shape: Optional[dict]) -> None:
+    if shape:
+        api.set_launch(shape["block"], shape["blocks_per_cu"], shape["min_items_per_block"])
+    else:
+        api.set_launch()
+
+
+def lookup(cx, grid, cache: str = DEFAULT_CACHE) -> Optional[dict]:
+    return _load(cache).get(signature(cx, grid))
+
+
+def _time_forward(cx, grid, reps: int) -> float:
+    out = torch.empty((cx.B, grid.d, grid.T), dtype=torch.float32 if cx.dtype == 1 else torch.int32,
+                      device=cx.device)
+    ws = torch.empty(max(1, api.wect_workspace_bytes(cx, grid)), dtype=torch.uint8, device=cx.device)
+    api.wect_forward(cx, grid, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        api.wect_forward(cx, grid, out=out, ws=ws)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def tune(cx, grid, candidates: Iterable[Tuple[int, int, int]] = CANDIDATES, reps: Optional[int] = None,
+         cache: Optional[str] = DEFAULT_CACHE, apply_best: bool = True) -> dict:
+    """Time every candidate shape, cache and (by default) apply the fastest."""
+    before = api.get_launch()
+    results = []
+    try:
+        for block, bpc, mi in candidates:
+            api.set_launch(block, bpc, mi)
+            t1 = _time_forward(cx, grid, 1)
+            r = reps or max(2, min(50, int(0.05 / max(t1, 1e-6))))
+            results.append((_time_forward(cx, grid, r), block, bpc, mi))
+    finally:
+        api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"])
+    t, block, bpc, mi = min(results)
+    best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "ms": t * 1e3,
+            "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "ms": s * 1e3}
+                      for s, b, c, m in results]}
+    if cache:
+        data = _load(cache)
+        data[signature(cx, grid)] = best
+        _save(cache, data)
+    if apply_best:
+        apply(best)
+    return best
