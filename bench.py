@@ -99,6 +99,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the one-complex-per-launch comparison (profiling the batched kernel alone)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration for profiling runs)")
     a = ap.parse_args(argv)
@@ -191,7 +193,12 @@ def main(argv=None):
         "roofline": roofline,
     }
 
+    result["kernel_sources"] = kernel_source_hash()
+
     # ---------------- one complex per launch (same images) ----------------
+    if a.no_single:
+        print(json.dumps(result), flush=True)
+        return
     singles = [W.CubicalBatch.from_host([C], device=dev) for C in w.complexes]
     outs = [torch.empty((1, d, T), dtype=torch.int32, device=dev) for _ in singles]
     ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(s, grid) for s in singles)), dtype=torch.uint8,

@@ -103,7 +103,8 @@ typedef struct {
   /* ---- cubical (implicit grid; vertex = voxel with intensity > include_above,
           every axis-aligned edge/square/cube whose corners are all vertices is
           a cell, sign (-1)^dim; VERTEX_MAX weight = max corner intensity) ---- */
-  const int32_t* shape;             /* [B, 3] extents (n0, n1, n2) with axis 0 fastest; n2 = 1 when n == 2 */
+  const int32_t* shape;             /* [B, 3] extents (n0, n1, n2) with axis 0 fastest; n2 = 1 when n == 2;
+                                       n0*n1*n2 < 2^31 per complex */
   const int64_t* grid_off;          /* [B+1] voxel offsets into `intensity`; NULL allowed iff B == 1 */
   const uint8_t* intensity;         /* all voxels, complex after complex, axis 0 fastest */
   const float* axis;                /* per complex n0 (+ n1 (+ n2)) coordinates: axis 0, then 1, then 2,
@@ -187,9 +188,11 @@ const char* wect_status_string(wect_status s);
 
 /*
  * Launch shape used by the following calls of this process (for tuning).
- * block: threads per block of the main kernels (256, 512 or 1024; 0 = default);
- * blocks_per_cu: main-kernel blocks per compute unit (0 = default);
- * min_items_per_block: lower bound of stream items per block (0 = default).
+ * block: threads per block of the main kernels (256, 512 or 1024; 0 = default:
+ *        the size giving the most resident wavefronts per compute unit);
+ * blocks_per_cu: main-kernel blocks per compute unit (0 = as many as fit: 32
+ *                wavefronts and 160 KiB of LDS per compute unit);
+ * min_items_per_block: lower bound of stream items per block (0 = default, 256).
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */

@@ -50,9 +50,9 @@ bool device_info(DeviceInfo* out) {
 }
 
 // launch shape (process-wide)
-std::atomic<int> g_block{1024};
-std::atomic<int> g_bpc{1};
-std::atomic<int> g_min_items{2048};
+std::atomic<int> g_block{0};  // 0: chosen per request by auto_block()
+std::atomic<int> g_bpc{0};  // 0: as many as LDS and wave slots allow
+std::atomic<int> g_min_items{256};
 
 // measurement
 std::atomic<int> g_profile{0};
@@ -81,6 +81,44 @@ struct Plan {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Staged entries per tile and LDS bytes of the forward kernel for a block
+// size: the histogram and thresholds are fixed, the staging tile takes what is
+// left (at most one entry per thread, a multiple of 64).  stage = 0: no fit.
+void fwd_stage_lds(const wect_complex* c, const wect_grid* g, int block, int* stage, size_t* lds) {
+  const int acc_bytes = (c->kind == WECT_SIMPLICIAL && c->dtype == WECT_F32) ? 8 : 4;
+  const size_t fixed = wect::forward_lds_fixed(g->T, c->kind, acc_bytes);
+  const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
+  int st = fixed + 64 * entry > kLdsLimit ? 0 : (int)std::min<size_t>(block, (kLdsLimit - fixed) / entry) / 64 * 64;
+  *stage = st;
+  *lds = fixed + (size_t)st * entry;
+}
+
+// Default block size.  Measured on MI355X: 512-thread blocks are fastest when
+// they reach 16 or more resident wavefronts per CU (several independent blocks
+// overlap their staging and histogram phases); otherwise the size with the
+// most resident wavefronts (32 wave slots and 160 KiB of LDS per CU) wins.
+int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only) {
+  if (bwd_only || g->T <= 0) return 1024;
+  auto waves_of = [&](int b) {
+    int stage = 0;
+    size_t lds = 0;
+    fwd_stage_lds(c, g, b, &stage, &lds);
+    if (stage == 0) return 0;
+    const int by_lds = (int)((160 * 1024) / (lds + 1024));
+    return std::min(32 / (b / kW), by_lds) * (b / kW);
+  };
+  if (waves_of(512) >= 16) return 512;
+  int best = 1024, best_waves = -1;
+  for (int b : {1024, 512, 256}) {
+    const int w = waves_of(b);
+    if (w > best_waves) {
+      best_waves = w;
+      best = b;
+    }
+  }
+  return best;
+}
 
 // Check host metadata and build the plan.  need_bwd: backward requested.
 wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl) {
@@ -168,7 +206,8 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     if (c->dtype != WECT_F32 || c->wmode == WECT_W_ONES) return WECT_ERR_ARG;
   }
 
-  const int block = g_block.load();
+  int block = g_block.load();
+  if (!block) block = auto_block(c, g, need_bwd && !need_fwd);
   pl->block = block;
   pl->elems = elems;
   const int ntiles = (int)ceil_div(g->d, kW);
@@ -177,20 +216,27 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   DeviceInfo di;
   const bool have_dev = device_info(&di);
   const int cus = have_dev ? di.cus : 256;
-  const int64_t max_blocks = (int64_t)cus * std::max(1, g_bpc.load());
   const int64_t min_items = std::max(1, g_min_items.load());
+  // blocks resident per compute unit: 32 wavefronts and 160 KiB of LDS per CU
+  auto blocks_per_cu = [&](size_t lds) -> int64_t {
+    const int user = g_bpc.load();
+    if (user > 0) return user;
+    int64_t by_waves = 32 / (block / kW);
+    int64_t by_lds = lds > 0 ? (int64_t)((160 * 1024) / (lds + 1024)) : by_waves;
+    return std::max<int64_t>(1, std::min(by_waves, by_lds));
+  };
 
   if (need_fwd && g->d > 0 && g->T > 0) {
     // forward LDS: histogram [T+1][64] + threshold pairs + staged entries
     const int acc_bytes = (c->kind == WECT_SIMPLICIAL && c->dtype == WECT_F32) ? 8 : 4;
-    const size_t fixed = wect::forward_lds_fixed(g->T, c->kind, acc_bytes);
-    const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
-    if (fixed + 64 * entry > kLdsLimit) return WECT_ERR_UNSUPPORTED;
-    int stage = (int)std::min<size_t>(block, (kLdsLimit - fixed) / entry);
-    stage = stage / 64 * 64;
+    int stage = 0;
+    size_t lds = 0;
+    fwd_stage_lds(c, g, block, &stage, &lds);
+    if (stage == 0) return WECT_ERR_UNSUPPORTED;
     p.stage = stage;
-    pl->lds_fwd = fixed + (size_t)stage * entry;
+    pl->lds_fwd = lds;
     const int64_t S = (int64_t)ntiles * elems;
+    const int64_t max_blocks = (int64_t)cus * blocks_per_cu(pl->lds_fwd);
     int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
     G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
     pl->G_fwd = (int)G;
@@ -198,9 +244,12 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     const int64_t groups = (int64_t)c->B * ntiles;
     const int64_t slots = G + groups;
     const size_t slot_bytes = (size_t)g->T * kW * acc_bytes;
-    // slots a group may have: blocks meeting its stream range
-    const int64_t spg = c->B == 1 ? ceil_div(G, ntiles) + 1 : G;
-    pl->split = spg > 8;
+    // Slots a group may have (blocks meeting its stream range).  A batch's
+    // per-complex sizes are on the device: the kernels decide per group, and
+    // the separate slot summation is launched when the average group has many
+    // slots.  Either way every group is summed correctly.
+    const int64_t spg = c->B == 1 ? ceil_div(G, ntiles) + 1 : ceil_div(G, groups) + 1;
+    pl->split = spg > 16;  // kFusedSlots in the kernels
     pl->partial_bytes = align256((size_t)slots * slot_bytes);
     pl->dsum_bytes = pl->split ? align256((size_t)groups * slot_bytes) : 0;
     pl->absmax_bytes = acc_bytes == 8 ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
@@ -221,6 +270,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->ngd = (int)ceil_div(ntiles, dg);
     pl->lds_bwd = wect::backward_lds_bytes(g->T, stage, dg);
     const int64_t S = (int64_t)pl->ngd * elems;
+    const int64_t max_blocks = (int64_t)cus * blocks_per_cu(pl->lds_bwd);
     int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
     G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
     pl->G_bwd = (int)G;
@@ -407,9 +457,9 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (!l) return WECT_ERR_ARG;
   if (l->block != 0 && !valid_block(l->block)) return WECT_ERR_ARG;
   if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64 || l->min_items_per_block < 0) return WECT_ERR_ARG;
-  g_block.store(l->block ? l->block : 1024);
-  g_bpc.store(l->blocks_per_cu ? l->blocks_per_cu : 1);
-  g_min_items.store(l->min_items_per_block ? l->min_items_per_block : 2048);
+  g_block.store(l->block);
+  g_bpc.store(l->blocks_per_cu);
+  g_min_items.store(l->min_items_per_block ? l->min_items_per_block : 256);
   return WECT_OK;
 }
 

@@ -67,14 +67,19 @@ __device__ __forceinline__ float height(const float* c, float sx, float sy, floa
 // ---------------------------------------------------------------------------
 
 struct Thr {
-  const float2* P;  // LDS [T+1]: (thr[q-1], thr[q]) with -inf / +inf at the ends
-  float a, c;
-  int T, p2, fast;
+  const float* P;   // LDS [T+1]: P[q] = thr[q-1], P[0] = -inf
+  float c, k;       // guess: t = fma(h, c, k) puts thr[q] near q + 1.5
+  float ka;         // arithmetic index: t = fma(h, c, ka) puts thr[q] near q + 1
+  float tmax;       // T + 0.5
+  float half_open;  // 0.5 - delta (see thr_arith)
+  int T, p2, fast, arith;
 };
 
-// Monotone first guess of the index (a cheap affine map, clamped to [0, T]).
-__device__ __forceinline__ int guess(float h, float a, float c, int T) {
-  float t = (h - a) * c;
+// Monotone first guess of the index: an affine map of the height (one fused
+// multiply-add), shifted by half a step so that it never falls below the true
+// index, clamped to [0, T].
+__device__ __forceinline__ int guess(float h, float c, float k, int T) {
+  float t = __builtin_fmaf(h, c, k);
   t = __builtin_amdgcn_fmed3f(t, 0.0f, (float)T);
   return (int)t;
 }
@@ -86,64 +91,134 @@ __device__ __forceinline__ float next_up(float x) {
   return __int_as_float(x > 0.0f ? i + 1 : i - 1);
 }
 
-// Exact index.  Fast path: the guess is within one of the true index for
-// every float (checked against the stored thresholds when the block starts),
-// so one comparison on each side of it settles the index.  Otherwise a
-// branch-free binary search over the stored thresholds.
+// Exact index L(h) = #{q : thr[q] < h}.  Fast path: the guess g is L or L+1
+// for every float (checked against the stored thresholds when the block
+// starts), and g == L+1 exactly when h <= thr[g-1], so one comparison settles
+// it.  Otherwise a branch-free binary search over the stored thresholds.
 template <bool FAST>
 __device__ __forceinline__ int thr_index(float h, const Thr& th) {
   if constexpr (FAST) {
-    int g = guess(h, th.a, th.c, th.T);
-    float2 pr = th.P[g];
-    return g + (h > pr.y ? 1 : 0) - (h <= pr.x ? 1 : 0);
+    const int g = guess(h, th.c, th.k, th.T);
+    return g - (h <= th.P[g] ? 1 : 0);
   }
   int lo = 0;
   for (int s = th.p2; s > 0; s >>= 1) {
     int cand = lo + s;
-    if (cand <= th.T && th.P[cand].x < h) lo = cand;  // P[cand].x == thr[cand-1]
+    if (cand <= th.T && th.P[cand] < h) lo = cand;  // P[cand] == thr[cand-1]
   }
   return lo;
 }
 
-// Block prologue: stage the threshold pairs in LDS and decide whether the
-// fast path is exact for this threshold array.  The guess g(h) is monotone in
-// h and the true index L(h) is constant on (thr[q], thr[q+1]], so checking
-// g at thr[q] and at the next float above thr[q] for every q bounds
-// |g - L| <= 1 everywhere (strictly increasing thresholds required).
-__device__ void setup_thresholds(const float* thr, int T, float2* P, Thr& th) {
-  for (int q = threadIdx.x; q <= T; q += blockDim.x) {
-    float lo = q > 0 ? thr[q - 1] : -INFINITY;
-    float hi = q < T ? thr[q] : INFINITY;
-    P[q] = make_float2(lo, hi);
+// Index from the affine map alone.  With x(h) = h c + ka (exact, strictly
+// increasing) and tau_q = x(thr[q]), L(h) = #{q : tau_q < x(h)}.  The stored
+// thresholds satisfy |tau_q - (q+1)| <= dev and t = fl(x(h)) is within
+// 2^-24 (T+2) <= delta/2 of x(h) (delta = 2 dev + 2^-23 (T+2) + 1e-7, measured
+// when the block starts).  When frac(t) is further than delta from 0 and 1,
+// every tau_q with q+1 <= floor(t) lies below x(h) and every other one above,
+// so L = clamp(floor(t), 0, T).  Otherwise h is within 2 delta of one position
+// m = round(t) and only thr[m-1] can be on either side: L = m - [h <= thr[m-1]].
+__device__ __forceinline__ bool thr_arith(float h, const Thr& th, int& b, float& t) {
+  t = __builtin_fmaf(h, th.c, th.ka);
+  t = __builtin_amdgcn_fmed3f(t, -0.5f, th.tmax);
+  const float fr = __builtin_amdgcn_fractf(t);
+  b = max((int)(t - fr), 0);
+  return fabsf(fr - 0.5f) < th.half_open;
+}
+
+__device__ __forceinline__ int thr_near(float h, float t, const Thr& th) {
+  const int m = min((int)rintf(t), th.T);
+  return m - (h <= th.P[m] ? 1 : 0);
+}
+
+// Per-wavefront choice between the arithmetic index (no LDS read unless a lane
+// sits on a threshold) and the one-read guess: images whose pixel lattice is
+// commensurate with the threshold grid put many heights exactly on thresholds
+// for some directions; a wavefront that needs the near-threshold fix in more
+// than 8 of 32 consecutive pairs switches to the guess for the rest of its range.
+struct IndexMode {
+  int arith, pairs, fallbacks;
+};
+
+template <bool FAST>
+__device__ __forceinline__ void thr_index2(float h0, float h1, const Thr& th, int& b0, int& b1, IndexMode& md) {
+  if constexpr (FAST) {
+    if (md.arith) {
+      float t0, t1;
+      const bool ok0 = thr_arith(h0, th, b0, t0);
+      const bool ok1 = thr_arith(h1, th, b1, t1);
+      if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
+        ++md.fallbacks;
+        if (!ok0) b0 = thr_near(h0, t0, th);
+        if (!ok1) b1 = thr_near(h1, t1, th);
+      }
+      if (++md.pairs == 32) {
+        if (md.fallbacks > 8) md.arith = 0;
+        md.pairs = 0;
+        md.fallbacks = 0;
+      }
+      return;
+    }
   }
+  b0 = thr_index<FAST>(h0, th);
+  b1 = thr_index<FAST>(h1, th);
+}
+
+// Block prologue: stage P in LDS and decide whether the fast path is exact
+// for this threshold array.  g is monotone in h and L is constant on
+// (thr[q], thr[q+1]], so g(thr[q]) in {q, q+1} and g(next float above thr[q])
+// in {q+1, q+2} (clamped to T) for every q give g in {L, L+1} everywhere
+// (strictly increasing thresholds required).
+__device__ void setup_thresholds(const float* thr, int T, float* P, Thr& th) {
+  for (int q = threadIdx.x; q <= T; q += blockDim.x) P[q] = q > 0 ? thr[q - 1] : -INFINITY;
   int p2 = 1;
   while (p2 * 2 <= T) p2 *= 2;
-  float a = 0.0f, c = 0.0f;
+  float c = 0.0f, k = 0.0f;
   int ok = 0;
   if (T >= 2) {
-    float t0 = thr[0], t1 = thr[T - 1];
-    float delta = (t1 - t0) / (float)(T - 1);
-    a = t0 - delta;
+    const float t0 = thr[0], t1 = thr[T - 1];
+    const float delta = (t1 - t0) / (float)(T - 1);
     c = 1.0f / delta;
-    ok = (delta > 0.0f) && isfinite(a) && isfinite(c) && (c > 0.0f);
+    k = 1.5f - t0 * c;  // t(thr[q]) ~ q + 1.5
+    ok = (delta > 0.0f) && isfinite(c) && isfinite(k) && (c > 0.0f);
   }
   int bad = 0;
   if (ok) {
     for (int q = threadIdx.x; q < T; q += blockDim.x) {
-      float x = thr[q];
+      const float x = thr[q];
       if (q + 1 < T && !(x < thr[q + 1])) bad = 1;
-      int g0 = guess(x, a, c, T);
-      int g1 = guess(next_up(x), a, c, T);
-      if (g0 < q - 1 || g0 > q + 1 || g1 < q || g1 > q + 2) bad = 1;
+      const int g0 = guess(x, c, k, T);
+      const int g1 = guess(next_up(x), c, k, T);
+      if (g0 < q || g0 > q + 1 || g1 < min(q + 1, T) || g1 > q + 2) bad = 1;
     }
   }
   bad = __syncthreads_or(bad);
+  // arithmetic index: distance of the stored thresholds from their positions
+  __shared__ double s_dev[16];
+  const float ka = ok ? 1.0f - thr[0] * c : 0.0f;
+  double dev = 0.0;
+  if (ok && !bad) {
+    for (int q = threadIdx.x; q < T; q += blockDim.x) {
+      const double tau = (double)thr[q] * (double)c + (double)ka;  // exact product, one rounding
+      dev = fmax(dev, fabs(tau - (double)(q + 1)));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
+  if ((threadIdx.x & 63) == 0) s_dev[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  dev = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) dev = fmax(dev, s_dev[w]);
+  const double delta = 2.0 * dev + ldexp(1.0, -23) * (T + 2) + 1e-7;
   th.P = P;
-  th.a = a;
   th.c = c;
+  th.k = k;
+  th.ka = ka;
+  th.tmax = (float)T + 0.5f;
+  th.half_open = (float)(0.5 - delta);
   th.T = T;
   th.p2 = p2;
   th.fast = ok && !bad;
+  th.arith = th.fast && delta < 0.25;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -358,6 +433,7 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
     st.gather(p, soff + tile_row(0), voff, fexp);
   }
   int nidx[L::NV];
+  IndexMode md = {th.arith, 0, 0};
   bool have_next = ntile > 1 && tid < TS && tile_row(1) < hi;
   if (have_next) {
     ST tmp;
@@ -383,17 +459,17 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
 #pragma unroll
       for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
     }
-    // histogram of tile t: two entries per iteration for latency overlap
-    int e = wave;
-    for (; e + nw < cnt; e += 2 * nw) {
+    // histogram of tile t: each wavefront takes adjacent pairs of entries
+    int e = 2 * wave;
+    for (; e + 1 < cnt; e += 2 * nw) {
       const float* E0 = stage + e * L::STRIDE;
-      const float* E1 = stage + (e + nw) * L::STRIDE;
+      const float* E1 = E0 + L::STRIDE;
       float h0 = max_height<N, DIM>(E0, sx, sy, sz);
       float h1 = max_height<N, DIM>(E1, sx, sy, sz);
       ACC w0 = load_weight<ACC>(E0 + L::WOFF);
       ACC w1 = load_weight<ACC>(E1 + L::WOFF);
-      int b0 = thr_index<FAST>(h0, th);
-      int b1 = thr_index<FAST>(h1, th);
+      int b0, b1;
+      thr_index2<FAST>(h0, h1, th, b0, b1, md);
       lds_add(&hist[b0 * W + lane], w0);
       lds_add(&hist[b1 * W + lane], w1);
     }
@@ -453,8 +529,8 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = p.T;
   ACC* hist = (ACC*)smem;
-  float2* P = (float2*)(smem + (size_t)(T + 1) * W * sizeof(ACC));
-  float* stage = (float*)(smem + (size_t)(T + 1) * W * sizeof(ACC) + align_up((size_t)(T + 1) * 8, 16));
+  float* P = (float*)(smem + (size_t)(T + 1) * W * sizeof(ACC));
+  float* stage = (float*)(smem + (size_t)(T + 1) * W * sizeof(ACC) + align_up((size_t)(T + 1) * 4, 16));
   Thr th;
   setup_thresholds(p.thr, T, P, th);
   for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = ACC(0);
@@ -524,10 +600,28 @@ struct CubLayout {
   static constexpr int STRIDE = N == 2 ? 8 : 12;
 };
 
+// A cell around the staged vertex v: mx = largest corner intensity, mn =
+// smallest corner value, where a corner that is not a vertex counts as -1; the
+// cell exists iff mn >= 0.
+struct CubCell {
+  int mx, mn;
+};
+
+__device__ __forceinline__ CubCell cub_join(CubCell a, int x) { return {max(a.mx, x), min(a.mn, x)}; }
+__device__ __forceinline__ CubCell cub_join(CubCell a, CubCell b) { return {max(a.mx, b.mx), min(a.mn, b.mn)}; }
+
+template <int WM>
+__device__ __forceinline__ int cub_val(CubCell c) {
+  return c.mn >= 0 ? (WM == WM_ONES ? 1 : c.mx) : 0;
+}
+
+// Combined weights of vertex (i0,i1,i2) for the 2^N orthants.  Orthant bit k
+// set means s_k < 0: the cells topped by v then extend towards +k, otherwise
+// towards -k.  Each distinct cell containing v (2N edges, the squares of each
+// axis pair, the 2^N cubes) is evaluated once.
 template <int N, int WM>
 __device__ __forceinline__ void cub_weights(const Params& p, const uint8_t* vol, int n0, int n1, int n2,
                                             int i0, int i1, int i2, int32_t* cw) {
-  // neighbourhood values: intensity if the voxel exists and is a vertex, else -1
   constexpr int M = N == 2 ? 9 : 27;
   int nb[M];
   const int thr = p.include_above;
@@ -542,29 +636,46 @@ __device__ __forceinline__ void cub_weights(const Params& p, const uint8_t* vol,
     }
     nb[m] = v;
   }
+  auto at = [&](int d0, int d1, int d2) { return nb[(d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0)]; };
+  const int v0 = at(0, 0, 0);
+  const CubCell cv = {v0, v0};
+  // edges E[axis][side], side 0: towards -axis, 1: towards +axis
+  CubCell E[N][2];
 #pragma unroll
-  for (int o = 0; o < (1 << N); ++o) {
-    // orthant bit k set: s_k < 0, the cells topped by v extend towards +k
-    const int s0 = (o & 1) ? 1 : -1, s1 = (o & 2) ? 1 : -1, s2 = (o & 4) ? 1 : -1;
-    int32_t acc = 0;
+  for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int S = 0; S < (1 << N); ++S) {  // axes spanned by the cell
-      int mx = -1;
-      bool inc = true;
-#pragma unroll
-      for (int eps = 0; eps < (1 << N); ++eps) {
-        if ((eps & ~S) != 0) continue;  // corner offsets only along spanned axes
-        const int d0 = (eps & 1) ? s0 : 0, d1 = (eps & 2) ? s1 : 0, d2 = (eps & 4) ? s2 : 0;
-        const int m = (d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0);
-        const int v = nb[m];
-        inc = inc && (v >= 0);
-        mx = max(mx, v);
-      }
-      const int w = WM == WM_ONES ? 1 : mx;
-      const int sgn = (__builtin_popcount(S) & 1) ? -1 : 1;
-      acc += inc ? sgn * w : 0;
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s = sd ? 1 : -1;
+      E[a][sd] = cub_join(cv, at(a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0));
     }
-    cw[o] = acc;
+  if constexpr (N == 2) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const int s0 = o & 1, s1 = (o >> 1) & 1;
+      const CubCell sq = cub_join(cub_join(E[0][s0], E[1][s1]), at(s0 ? 1 : -1, s1 ? 1 : -1, 0));
+      cw[o] = cub_val<WM>(cv) - cub_val<WM>(E[0][s0]) - cub_val<WM>(E[1][s1]) + cub_val<WM>(sq);
+    }
+  } else {
+    // squares F01[s0][s1], F02[s0][s2], F12[s1][s2]
+    CubCell F01[2][2], F02[2][2], F12[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int sa = a ? 1 : -1, sb = b ? 1 : -1;
+        F01[a][b] = cub_join(cub_join(E[0][a], E[1][b]), at(sa, sb, 0));
+        F02[a][b] = cub_join(cub_join(E[0][a], E[2][b]), at(sa, 0, sb));
+        F12[a][b] = cub_join(cub_join(E[1][a], E[2][b]), at(0, sa, sb));
+      }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int s0 = o & 1, s1 = (o >> 1) & 1, s2 = (o >> 2) & 1;
+      // the cube's 8 corners: F01 and F12 cover six of them; add the 0-2 diagonal and the far corner
+      const CubCell cube = cub_join(cub_join(cub_join(F01[s0][s1], F12[s1][s2]), at(s0 ? 1 : -1, 0, s2 ? 1 : -1)),
+                                    at(s0 ? 1 : -1, s1 ? 1 : -1, s2 ? 1 : -1));
+      cw[o] = cub_val<WM>(cv) - cub_val<WM>(E[0][s0]) - cub_val<WM>(E[1][s1]) - cub_val<WM>(E[2][s2]) +
+              cub_val<WM>(F01[s0][s1]) + cub_val<WM>(F02[s0][s2]) + cub_val<WM>(F12[s1][s2]) - cub_val<WM>(cube);
+    }
   }
 }
 
@@ -582,6 +693,7 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
   const float* ax0 = p.axis + aoff;
   const float* ax1 = ax0 + n0;
   const float* ax2 = ax1 + n1;
+  IndexMode md = {th.arith, 0, 0};
   for (int64_t t0 = lo; t0 < hi; t0 += TS) {
     const int cnt = (int)mn64(TS, hi - t0);
     if (tid == 0) *counter = 0;
@@ -590,11 +702,13 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
     float cx = 0.0f, cy = 0.0f, cz = 0.0f;
     int32_t cw[L::NO];
     if (tid < cnt) {
-      const int64_t v = t0 + tid;
-      const int i0 = (int)(v % n0);
-      const int64_t r = v / n0;
-      const int i1 = (int)(r % n1);
-      const int i2 = (int)(r / n1);
+      // voxel counts of one complex are below 2^31 (checked by wect_validate)
+      const uint32_t v = (uint32_t)(t0 + tid);
+      const uint32_t r = v / (uint32_t)n0;
+      const int i0 = (int)(v - r * (uint32_t)n0);
+      const uint32_t i2u = r / (uint32_t)n1;
+      const int i1 = (int)(r - i2u * (uint32_t)n1);
+      const int i2 = (int)i2u;
       if ((int)vol[v] > p.include_above) {
         cub_weights<N, WM>(p, vol, n0, n1, n2, i0, i1, i2, cw);
         bool nz = false;
@@ -622,23 +736,24 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
     }
     __syncthreads();
     const int ne = uniform(*counter);
-    int e = wave;
-    for (; e + nw < ne; e += 2 * nw) {
+    const float* Wl = stage + L::COFF + orth;  // the lane's combined weight within an entry
+    int e = 2 * wave;
+    for (; e + 1 < ne; e += 2 * nw) {
       const float* E0 = stage + e * L::STRIDE;
-      const float* E1 = stage + (e + nw) * L::STRIDE;
+      const float* E1 = E0 + L::STRIDE;
       float h0 = height<N>(E0, sx, sy, sz);
       float h1 = height<N>(E1, sx, sy, sz);
-      uint32_t w0 = bitcast<uint32_t>(E0[L::COFF + orth]);
-      uint32_t w1 = bitcast<uint32_t>(E1[L::COFF + orth]);
-      int b0 = thr_index<FAST>(h0, th);
-      int b1 = thr_index<FAST>(h1, th);
+      uint32_t w0 = bitcast<uint32_t>(Wl[e * L::STRIDE]);
+      uint32_t w1 = bitcast<uint32_t>(Wl[e * L::STRIDE + L::STRIDE]);
+      int b0, b1;
+      thr_index2<FAST>(h0, h1, th, b0, b1, md);
       lds_add(&hist[b0 * W + lane], w0);
       lds_add(&hist[b1 * W + lane], w1);
     }
     if (e < ne) {
       const float* E0 = stage + e * L::STRIDE;
       float h0 = height<N>(E0, sx, sy, sz);
-      uint32_t w0 = bitcast<uint32_t>(E0[L::COFF + orth]);
+      uint32_t w0 = bitcast<uint32_t>(Wl[e * L::STRIDE]);
       int b0 = thr_index<FAST>(h0, th);
       lds_add(&hist[b0 * W + lane], w0);
     }
@@ -652,8 +767,8 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
   const int T = p.T;
   uint32_t* hist = (uint32_t*)smem;
   size_t off = (size_t)(T + 1) * W * 4;
-  float2* P = (float2*)(smem + off);
-  off += align_up((size_t)(T + 1) * 8, 16);
+  float* P = (float*)(smem + off);
+  off += align_up((size_t)(T + 1) * 4, 16);
   int* counter = (int*)(smem + off);
   off += 16;
   float* stage = (float*)(smem + off);
@@ -711,8 +826,12 @@ __device__ __forceinline__ void group_slots(const Params& p, int g, int64_t& kfi
   }
 }
 
-// Sum of the partial histograms of every group into dsum[g][T][64] (used when
-// groups have many slots): one thread per (group, threshold, lane).
+// Groups with at most this many partial slots are summed inside the scan
+// kernel; larger ones are summed first by k_slot_sum (fully parallel).
+constexpr int kFusedSlots = 16;
+
+// Sum of the partial histograms of every group with more than kFusedSlots
+// slots into dsum[g][T][64]: one thread per (group, threshold, lane).
 template <typename ACC>
 __global__ __launch_bounds__(256) void k_slot_sum(Params p) {
   const int g = blockIdx.x;
@@ -722,6 +841,7 @@ __global__ __launch_bounds__(256) void k_slot_sum(Params p) {
   if (q >= T) return;
   int64_t kfirst, klast;
   group_slots(p, g, kfirst, klast);
+  if (klast - kfirst + 1 <= kFusedSlots) return;
   const ACC* src = (const ACC*)p.partial + (int64_t)q * W + lane;
   const int64_t slot_stride = (int64_t)T * W;
   ACC v0 = 0, v1 = 0, v2 = 0, v3 = 0;
@@ -774,23 +894,32 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
   ACC acc[CH];
 #pragma unroll
   for (int j = 0; j < CH; ++j) acc[j] = 0;
-  if (r < 16) {
+  if (r < 16 && nq > 0) {
     const int64_t slot_stride = (int64_t)T * W;
-    if (p.split) {
+    int64_t kfirst, klast;
+    group_slots(p, g, kfirst, klast);
+    // rows q0 .. q0+nq-1 of this thread; loads use clamped (in-range) rows and
+    // the surplus values are dropped, so all CH loads of a slot are independent
+    int rowoff[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) rowoff[j] = min(j, nq - 1) * W;
+    if (p.split && klast - kfirst + 1 > kFusedSlots) {
       const ACC* src = (const ACC*)p.dsum + (int64_t)g * slot_stride + (int64_t)q0 * W + lane;
 #pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (j < nq) acc[j] = src[(int64_t)j * W];
+      for (int j = 0; j < CH; ++j) acc[j] = src[rowoff[j]];
     } else {
-      int64_t kfirst, klast;
-      group_slots(p, g, kfirst, klast);
       for (int64_t kk = kfirst; kk <= klast; ++kk) {
         const ACC* src = (const ACC*)p.partial + (kk + g) * slot_stride + (int64_t)q0 * W + lane;
+        ACC v[CH];
 #pragma unroll
-        for (int j = 0; j < CH; ++j)
-          if (j < nq) acc[j] += src[(int64_t)j * W];
+        for (int j = 0; j < CH; ++j) v[j] = src[rowoff[j]];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) acc[j] += v[j];
       }
     }
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+      if (j >= nq) acc[j] = 0;
   }
   ACC run = 0;
 #pragma unroll
@@ -857,7 +986,7 @@ __device__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, i
                                const float* Gt, float* stage, const Thr& th) {
   using L = SimpLayout<N, DIM, uint64_t>;
   const int tid = threadIdx.x, lane = tid & (W - 1);
-  const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
+  const int wave = uniform(tid >> 6);
   const int TS = p.stage;
   const int T1 = p.T + 1;
   SimpStager<N, DIM, WM, float, false> st;
@@ -869,30 +998,36 @@ __device__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, i
       st.store(stage + tid * L::STRIDE);
     }
     __syncthreads();
-    for (int e = wave; e < cnt; e += nw) {
-      const float* E = stage + e * L::STRIDE;
+    // wavefront w takes the 64 consecutive entries [64 w, 64 w + 64); the
+    // total of entry j is parked in lane j and all 64 are written at once
+    const int e0 = wave * W;
+    const int ne = max(0, min(W, cnt - e0));
+    float mine = 0.0f;
+    for (int j = 0; j < ne; ++j) {
+      const float* E = stage + (e0 + j) * L::STRIDE;
       float acc = 0.0f;
 #pragma unroll
-      for (int j = 0; j < kMaxDG; ++j) {
-        if (j < ntl) {
-          const float h = max_height<N, DIM>(E, sx[j], sy[j], sz[j]);
+      for (int jj = 0; jj < kMaxDG; ++jj) {
+        if (jj < ntl) {
+          const float h = max_height<N, DIM>(E, sx[jj], sy[jj], sz[jj]);
           const int bi = thr_index<FAST>(h, th);
-          acc += Gt[((size_t)j * T1 + bi) * W + lane];
+          acc += Gt[((size_t)jj * T1 + bi) * W + lane];
         }
       }
-      float tot = wave_sum(acc);
-      if constexpr (DIM & 1) tot = -tot;
-      if (lane == 0) {
-        const int64_t row = soff + t0 + e;
-        if constexpr (WM == WM_VMAX) {
-          const int own = bitcast<int>(E[L::OOFF]);
-          atomicAdd(p.grad_vertex + voff + own, tot);
-        } else {
-          float* gw = p.grad_w[DIM];
-          if (gw) {
-            if (p.bwd_atomic) atomicAdd(gw + row, tot);
-            else gw[row] = tot;
-          }
+      const float tot = wave_sum(acc);
+      mine = lane == j ? tot : mine;
+    }
+    if constexpr (DIM & 1) mine = -mine;
+    if (lane < ne) {
+      const int64_t row = soff + t0 + e0 + lane;
+      if constexpr (WM == WM_VMAX) {
+        const int own = bitcast<int>(stage[(e0 + lane) * L::STRIDE + L::OOFF]);
+        atomicAdd(p.grad_vertex + voff + own, mine);
+      } else {
+        float* gw = p.grad_w[DIM];
+        if (gw) {
+          if (p.bwd_atomic) atomicAdd(gw + row, mine);
+          else gw[row] = mine;
         }
       }
     }
@@ -919,8 +1054,8 @@ __global__ __launch_bounds__(1024) void k_simp_bwd(Params p) {
   const int dg = p.dg;
   float* Gt = (float*)smem;
   size_t off = (size_t)dg * T1 * W * 4;
-  float2* P = (float2*)(smem + off);
-  off += align_up((size_t)T1 * 8, 16);
+  float* P = (float*)(smem + off);
+  off += align_up((size_t)T1 * 4, 16);
   float* stage = (float*)(smem + off);
   Thr th;
   setup_thresholds(p.thr, T, P, th);
@@ -1065,6 +1200,7 @@ __global__ void k_validate(Params p, int* flags) {
         const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = p.shape[3 * b + 2];
         if (n0 < 1 || n1 < 1 || n2 < 1 || (p.n == 2 && n2 != 1)) { f |= kFlagIndex; continue; }
         const int64_t nv = (int64_t)n0 * n1 * n2;
+        if (nv >= ((int64_t)1 << 31)) f |= kFlagIndex;
         const int64_t g0 = off_or(p.grid_off, (int)b, p.total_voxels), g1 = off_or(p.grid_off, (int)b + 1, p.total_voxels);
         if (g1 - g0 != nv) f |= kFlagIndex;
         if (b == 0 && g0 != 0) f |= kFlagIndex;
@@ -1109,7 +1245,7 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
 
 size_t forward_lds_fixed(int T, int kind, int acc_bytes) {
   size_t hist = (size_t)(T + 1) * W * acc_bytes;
-  size_t pairs = ((size_t)(T + 1) * 8 + 15) / 16 * 16;
+  size_t pairs = ((size_t)(T + 1) * 4 + 15) / 16 * 16;
   (void)kind;
   return hist + pairs + 16;
 }
@@ -1118,7 +1254,7 @@ size_t forward_entry_bytes(int kind, int n) { return (size_t)(kind == 1 ? (n == 
 
 size_t backward_lds_bytes(int T, int stage, int dg) {
   size_t g = (size_t)dg * (T + 1) * W * 4;
-  size_t pairs = ((size_t)(T + 1) * 8 + 15) / 16 * 16;
+  size_t pairs = ((size_t)(T + 1) * 4 + 15) / 16 * 16;
   return g + pairs + (size_t)stage * kMaxStride * 4;
 }
 

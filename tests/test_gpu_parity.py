@@ -426,3 +426,19 @@ def test_validate_detects_bad_data(W):
     with pytest.raises(L.WectError) as e:
         W.wect_validate(cc, W.Grid(dirs, thr))
     assert e.value.status == L.WECT_ERR_THRESHOLDS
+
+
+def test_autotuner_caches_and_keeps_results(W, tmp_path):
+    from paper_2511_03909_amd import tune
+    w = synth.cfg2(n_images=6, side=48)
+    cx = W.CubicalBatch.from_host(w.complexes)
+    g = W.Grid(w.dirs, w.thr)
+    ref = W.wect_forward(cx, g).cpu().numpy()
+    cache = str(tmp_path / "tune.json")
+    try:
+        best = tune.tune(cx, g, candidates=((512, 0, 0), (1024, 1, 0), (256, 4, 64)), reps=3, cache=cache)
+        assert tune.lookup(cx, g, cache) is not None
+        assert best["block"] in (256, 512, 1024) and len(best["tried"]) == 3
+        assert np.array_equal(W.wect_forward(cx, g).cpu().numpy(), ref)
+    finally:
+        W.set_launch()
