@@ -236,10 +236,22 @@ def main(argv=None):
         with torch.cuda.graph(graph):
             W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5)
         t_g = timed(graph.replay, 10, 2)
+        # the same 64 complexes, one call per complex (forward, and forward + backward)
+        singles5 = [W.SimplicialBatch.from_host([K], device=dev) for K in w5.complexes]
+        ws5s = torch.empty(max(1, max(W.wect_workspace_bytes(c, g5, True) for c in singles5)), dtype=torch.uint8,
+                           device=dev)
+        go5 = [gout[b:b + 1].contiguous() for b in range(cx5.B)]
+        o5s = [torch.empty((1, g5.d, g5.T), dtype=torch.float32, device=dev) for _ in singles5]
+        gv5s = [torch.empty(c.counts[0], dtype=torch.float32, device=dev) for c in singles5]
+        t_f1 = timed(lambda: [W.wect_batched(c, g5, None, out=o, ws=ws5s) for c, o in zip(singles5, o5s)], 3, 1)
+        t_fb1 = timed(lambda: [W.wect_batched(c, g5, gg, out=o, grads=gv, ws=ws5s)
+                               for c, gg, o, gv in zip(singles5, go5, o5s, gv5s)], 3, 1)
         extras["differentiation_batch64"] = {
             "workload": w5.name, "items": it5, "fwd_items_per_s": it5 / t_f, "fwd_bwd_items_per_s": it5 / t_fb,
-            "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_graph_ms": t_g * 1e3}
-        del cx5, o5, gv5, ws5, gout
+            "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_graph_ms": t_g * 1e3,
+            "one_per_launch": {"fwd_ms": t_f1 * 1e3, "fwd_bwd_ms": t_fb1 * 1e3,
+                               "fwd_batched_speedup": t_f1 / t_f, "fwd_bwd_batched_speedup": t_fb1 / t_fb}}
+        del cx5, o5, gv5, ws5, gout, singles5, o5s, gv5s, go5, ws5s
         # 3D simplicial, float32 weights
         w3 = synth.cfg3()
         cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)
@@ -270,8 +282,14 @@ def main(argv=None):
         o4 = torch.empty((cx4.B, g4.d, g4.T), dtype=torch.int32, device=dev)
         ws4 = torch.empty(max(1, W.wect_workspace_bytes(cx4, g4)), dtype=torch.uint8, device=dev)
         t4 = timed(lambda: W.wect_forward(cx4, g4, out=o4, ws=ws4), 3, 1)
-        extras["cubical_3d_16vol"] = {"workload": w4.name, "items": it4, "items_per_s": it4 / t4, "ms": t4 * 1e3}
-        del cx4, o4, ws4
+        singles4 = [W.CubicalBatch.from_host([C], device=dev) for C in w4.complexes]
+        o4s = [torch.empty((1, g4.d, g4.T), dtype=torch.int32, device=dev) for _ in singles4]
+        ws4s = torch.empty(max(1, max(W.wect_workspace_bytes(c, g4) for c in singles4)), dtype=torch.uint8,
+                           device=dev)
+        t41 = timed(lambda: [W.wect_forward(c, g4, out=o, ws=ws4s) for c, o in zip(singles4, o4s)], 2, 1)
+        extras["cubical_3d_16vol"] = {"workload": w4.name, "items": it4, "items_per_s": it4 / t4, "ms": t4 * 1e3,
+                                      "one_per_launch_ms": t41 * 1e3, "batched_speedup": t41 / t4}
+        del cx4, o4, ws4, singles4, o4s, ws4s
         result["extras"] = extras
 
     # ---------------- CPU oracle on a bounded sample of the headline workload ----------------

@@ -442,3 +442,81 @@ def test_autotuner_caches_and_keeps_results(W, tmp_path):
         assert np.array_equal(W.wect_forward(cx, g).cpu().numpy(), ref)
     finally:
         W.set_launch()
+
+
+@pytest.mark.parametrize("T", [255, 256, 257, 300, 500])
+def test_many_thresholds(W, T):
+    """T above 256 takes the wide scan (48 rows per thread chunk) and smaller staging tiles."""
+    _say(f"many thresholds T={T}")
+    Ki = synth.random_tiny_complex(11, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.int32)
+    Kf = synth.random_tiny_complex(11, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.float32)
+    dirs, thr = synth.fibonacci_directions(70), synth.uniform_thresholds(T, 2.0)
+    for K in (Ki, Kf):
+        if T > 290 and K is Kf:
+            continue  # the 64-bit histogram of float weights fits LDS up to T of about 290
+        assert_match(gpu_wect(W, [K], dirs, thr)[0], oracle.wect(K, dirs, thr), K, f"T={T}")
+    C = synth.random_tiny_cubical(3, (9, 7, 5), include_above=40)
+    assert_match(gpu_wect(W, [C], dirs, thr)[0], oracle.wect(C, dirs, thr), C, f"cubical T={T}")
+
+
+def test_float_weights_too_many_thresholds_is_unsupported(W):
+    from paper_2511_03909_amd import _lib as L
+    K = synth.random_tiny_complex(1, n=2, nv=8, top_dim=2, wmode="explicit", wdtype=np.float32)
+    with pytest.raises(L.WectError) as e:
+        gpu_wect(W, [K], synth.s1_directions(8), synth.uniform_thresholds(400, 1.5))
+    assert e.value.status == L.WECT_ERR_UNSUPPORTED
+
+
+def test_many_directions_and_uneven_cubical_batch(W):
+    """d = 300 (five tiles, ragged last one) on a batch of images of different
+    shapes, one of them with no vertex at all."""
+    ims = [synth.random_tiny_cubical(s, shp, include_above=90) for s, shp in
+           enumerate(((12, 9), (3, 17), (20, 1), (7, 7), (16, 11)))]
+    ims.append(synth.Cubical(np.zeros((5, 6), np.uint8), [synth.cubical_axis(6), synth.cubical_axis(5)], 90, True))
+    dirs, thr = synth.s1_directions(300), synth.uniform_thresholds(41, 1.8)
+    _say("uneven cubical batch, d=300")
+    got = gpu_wect(W, ims, dirs, thr)
+    assert np.all(got[-1] == 0)
+    for b, C in enumerate(ims[:-1]):
+        assert_match(got[b], oracle.wect(C, dirs, thr), C, f"image {b}")
+    vols = [synth.random_tiny_cubical(s, shp, include_above=70) for s, shp in
+            enumerate(((6, 5, 4), (3, 8, 2), (1, 1, 9), (5, 5, 5)))]
+    dirs3 = synth.fibonacci_directions(130)
+    _say("uneven cubical volume batch, d=130")
+    got = gpu_wect(W, vols, dirs3, thr)
+    for b, C in enumerate(vols):
+        assert_match(got[b], oracle.wect(C, dirs3, thr), C, f"volume {b}")
+
+
+def test_include_all_and_unweighted_volume(W):
+    C = synth.random_tiny_cubical(5, (6, 7, 5), include_above=-1, weighted=False)
+    dirs, thr = synth.fibonacci_directions(64), synth.uniform_thresholds(33, 1.8)
+    got = gpu_wect(W, [C], dirs, thr)[0]
+    ref = oracle.wect(C, dirs, thr)
+    assert_match(got, ref, C, "all included")
+    assert np.all(ref[:, -1] == 1)  # a solid box is contractible
+
+
+def test_graph_replay_cubical_forward(W):
+    w = synth.cfg2(n_images=9, side=33)
+    cx = W.CubicalBatch.from_host(w.complexes)
+    g = W.Grid(w.dirs, w.thr)
+    ref = W.wect_forward(cx, g).clone()
+    out = torch.empty_like(ref)
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, g)), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        W.wect_forward(cx, g, out=out, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        W.wect_forward(cx, g, out=out, ws=ws)
+    for _ in range(3):
+        out.fill_(-1)
+        _ = torch.randn(500, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
