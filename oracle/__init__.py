@@ -25,6 +25,10 @@ What it computes, and from which passage of the paper:
   (Example "WECT as a special case" in Section "Computation of WECFs").
 * Simplex weights taken as the maximum of the vertex weights (caption of
   Figure 1).
+* General vertex filters (Section "Computation of WECFs", Algorithm 1 with
+  arbitrary filter values per vertex: ``wecf``) and the ECF of an image, whose
+  vertex filter is the intensity itself (Remark on the two ECFs of an image:
+  ``image_ecf``).
 
 The forward is the definition evaluated directly: for every direction the
 filter values of all cells are sorted (a library sort), the signed weights are
@@ -65,7 +69,8 @@ import numpy as np
 
 __all__ = [
     "heights", "simplicial_cells", "cubical_cells", "cells_of", "wecf_sorted", "wect",
-    "wect_bruteforce", "owner_vertex", "wect_backward", "wect_backward_bruteforce",
+    "wect_bruteforce", "wecf", "wecf_bruteforce", "image_ecf", "image_ecf_cells",
+    "owner_vertex", "wect_backward", "wect_backward_bruteforce",
     "loss", "fd_vertex_grad", "euler_characteristic", "total_abs_weight",
 ]
 
@@ -322,6 +327,61 @@ def wect_bruteforce(X, dirs: np.ndarray, thr: np.ndarray):
                         w = int(w) if cells.integer else float(w)
                         out[p][q] += w if dim % 2 == 0 else -w
     return np.array(out, dtype=np.int64 if cells.integer else np.float64)
+
+
+# ---------------------------------------------------------------------------
+# general vertex filters and the ECF of an image
+# ---------------------------------------------------------------------------
+
+def wecf(X, fvals: np.ndarray, thr: np.ndarray):
+    """WECF_{f_p}(thr[q]) [m, T] for m arbitrary vertex filters fvals [V, m] on
+    a simplicial complex: Section "Computation of WECFs" takes the filter values
+    of every vertex as input (Algorithm 1 returns the (m, T) tensor), and the
+    WECT is the case fvals = V D^T.  int64 for integer weights, float64
+    otherwise."""
+    cells = cells_of(X)
+    F = np.asarray(fvals, dtype=np.float32)
+    thr = np.asarray(thr, dtype=np.float32)
+    rows = [wecf_sorted(F[:, p], cells, thr) for p in range(F.shape[1])]
+    dt = np.int64 if cells.integer else np.float64
+    return np.stack(rows).astype(dt) if rows else np.zeros((0, thr.shape[0]), dt)
+
+
+def wecf_bruteforce(X, fvals: np.ndarray, thr: np.ndarray):
+    """``wecf`` as a literal loop over (filter, threshold, cell); tiny inputs."""
+    cells = cells_of(X)
+    F = np.asarray(fvals, dtype=np.float32)
+    thr = np.asarray(thr, dtype=np.float32)
+    m, T = F.shape[1], thr.shape[0]
+    out = [[0 if cells.integer else 0.0 for _ in range(T)] for _ in range(m)]
+    for p in range(m):
+        for q in range(T):
+            for dim, vv in enumerate(cells.verts):
+                for c in range(vv.shape[0]):
+                    if max(F[int(u), p] for u in vv[c]) <= thr[q]:
+                        w = cells.weights[dim][c]
+                        w = int(w) if cells.integer else float(w)
+                        out[p][q] += w if dim % 2 == 0 else -w
+    return np.array(out, dtype=np.int64 if cells.integer else np.float64)
+
+
+def image_ecf(C, thr: np.ndarray):
+    """ECF of an image or volume (Remark on the two ECFs of an image): the
+    intensity itself is the vertex filter, a cell enters at the maximum
+    intensity of its corners, cells as in ``cubical_cells``; weights 1 (the
+    ECF) or, when ``C.weighted``, the maximum corner intensity (a WECF).
+    Returns [T] int64: sum of (-1)^dim w(c) over cells with value <= thr[q]."""
+    I = np.asarray(C.intensity)
+    vals, sw = _cubical_values(C, I.astype(np.float64))   # integer intensities: exact
+    return _sorted_sums(vals, sw.astype(np.int64), np.asarray(thr, dtype=np.float32).astype(np.float64))
+
+
+def image_ecf_cells(C, thr: np.ndarray):
+    """``image_ecf`` by the other route: the explicit cell list of
+    ``cubical_cells`` and ``wecf_sorted`` with the intensity as vertex filter."""
+    cells = cubical_cells(C)
+    f = np.asarray(C.intensity).ravel().astype(np.float64)   # row = linear vertex id (axis 0 fastest)
+    return wecf_sorted(f, cells, np.asarray(thr, dtype=np.float32).astype(np.float64))
 
 
 def euler_characteristic(X) -> float:

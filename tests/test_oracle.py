@@ -365,3 +365,83 @@ def test_cubical_views_match_explicit_cells():
                 a = oracle.wect(C, dirs, thr)
                 b = oracle.wect(oracle.cubical_cells(C), dirs, thr)
                 assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# general vertex filters and the ECF of an image
+# ---------------------------------------------------------------------------
+
+def _image(case):
+    I = np.asarray(case["intensity"], dtype=np.uint8)
+    axes = [synth.cubical_axis(s) for s in I.shape[::-1]]
+    return synth.Cubical(I, axes, include_above=-1, weighted=case["weighted"])
+
+
+def test_image_ecf_hand_examples():
+    with open(os.path.join(GOLD, "image_ecf_examples.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        C = _image(case)
+        thr = np.asarray(case["thr"], dtype=np.float32)
+        assert oracle.image_ecf(C, thr).tolist() == case["ecf"], case["name"]
+        assert oracle.image_ecf_cells(C, thr).tolist() == case["ecf"], case["name"]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_image_ecf_views_equal_explicit_cells(seed):
+    """Tie-heavy tiny images and volumes (intensities in 0..3), with and without
+    an inclusion level and weights: the shifted-view route equals the explicit
+    cell list."""
+    g = np.random.default_rng(seed)
+    shape = [(5, 4), (1, 7), (6, 6), (3, 4, 2), (2, 2, 5)][seed % 5]
+    I = g.integers(0, 4, size=shape[::-1]).astype(np.uint8)
+    C = synth.Cubical(I, [synth.cubical_axis(s) for s in shape], include_above=int(seed % 3) - 1,
+                      weighted=bool(seed & 1))
+    thr = np.array([-1, 0, 0.5, 1, 2, 2.5, 3, 4], dtype=np.float32)
+    assert np.array_equal(oracle.image_ecf(C, thr), oracle.image_ecf_cells(C, thr))
+
+
+def test_image_ecf_closed_forms():
+    """Above the largest intensity the ECF is chi of the whole image (a solid
+    rectangle or box: 1); below the smallest it is 0."""
+    g = np.random.default_rng(5)
+    for shape in ((7, 5), (4, 3, 6)):
+        I = g.integers(0, 256, size=shape[::-1]).astype(np.uint8)
+        C = synth.Cubical(I, [synth.cubical_axis(s) for s in shape], include_above=-1, weighted=False)
+        out = oracle.image_ecf(C, np.array([-0.5, float(I.min()) - 0.5, 255.0], dtype=np.float32))
+        assert out.tolist() == [0, 0, 1]
+
+
+def test_wecf_of_heights_is_the_wect():
+    """The WECT is the WECF with filter values V D^T."""
+    K = synth.random_tiny_complex(4, n=3, nv=9, top_dim=3, wmode="explicit", wdtype=np.int32)
+    dirs, thr = synth.fibonacci_directions(7), synth.uniform_thresholds(11, 1.8)
+    F = oracle.heights(K.coords, dirs).T
+    assert np.array_equal(oracle.wecf(K, F, thr), oracle.wect(K, dirs, thr))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_wecf_matches_bruteforce(seed):
+    """Arbitrary filters with many ties (values from a small set) and thresholds
+    on filter values."""
+    g = np.random.default_rng(100 + seed)
+    wm = ["ones", "explicit", "vertex_max"][seed % 3]
+    wdt = np.float32 if wm == "vertex_max" or seed % 2 else np.int32
+    K = synth.random_tiny_complex(seed, n=2, nv=8, top_dim=2, wmode=wm, wdtype=wdt)
+    F = g.choice(np.array([-1.0, -0.25, 0.0, 0.5, 0.75], np.float32), size=(8, 5))
+    thr = np.array([-1.0, -0.5, 0.0, 0.5, 1.0], dtype=np.float32)
+    got, ref = oracle.wecf(K, F, thr), oracle.wecf_bruteforce(K, F, thr)
+    if np.issubdtype(ref.dtype, np.integer):
+        assert np.array_equal(got, ref)
+    else:
+        assert np.allclose(got, ref, rtol=0, atol=1e-9)
+
+
+def test_wecf_closed_forms():
+    """chi at a threshold above every filter value (octahedron boundary: 2;
+    Freudenthal torus: 0) and 0 below every filter value."""
+    g = np.random.default_rng(7)
+    for K, chi in ((synth.octahedron(), 2), (synth.grid_torus(5, 4), 0)):
+        F = g.uniform(-1, 1, size=(K.coords.shape[0], 6)).astype(np.float32)
+        out = oracle.wecf(K, F, np.array([-1.5, 1.5], dtype=np.float32))
+        assert np.all(out[:, 0] == 0) and np.all(out[:, 1] == chi)
