@@ -175,6 +175,34 @@ wect_status wect_batched(const wect_complex* c, const wect_grid* g, void* out,
                          void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * ECF of images and volumes with the intensity as the vertex filter: the first
+ * of the two ECFs of an image in the paper's Remark on them, i.e. the WECF of
+ * Section "Computation of WECFs" for one vertex filter, f(v) = intensity(v).
+ *
+ * c: kind CUBICAL, n = 2 or 3, dtype I32, B >= 1 images with shape [B,3] and
+ *    (B > 1) grid_off [B+1]; axis and axis_off are not read.  A pixel/voxel is
+ *    a vertex iff intensity > include_above (-1: all); the edges, squares and
+ *    cubes whose corners are all vertices are the other cells, as for
+ *    wect_forward.  A cell enters the filtration at the largest intensity of
+ *    its corners.  Weight: 1 (wmode ONES: the ECF) or that largest intensity
+ *    (wmode VERTEX_MAX: a WECF); EXPLICIT is WECT_ERR_UNSUPPORTED.
+ * thr: [T] float32 device array, any order (each entry is read on its own; a
+ *    NaN entry admits no cell).
+ * out: [B, T] int32 device array (row b = image b), overwritten:
+ *    out[b][q] = sum of (-1)^dim * weight over the cells of image b whose
+ *    value is <= thr[q].  Integer sums wrap modulo 2^32 like int32.
+ * ws:  wect_image_ecf_workspace_bytes(c) bytes of device memory (256-byte
+ *    aligned, contents ignored); it does not depend on T.
+ * Metadata errors return before anything is enqueued; data errors (shapes
+ * inconsistent with grid_off or total_voxels) are reported by wect_validate
+ * (with a grid of d = 0 directions).  Asynchronous on hip_stream and
+ * capture-safe: two kernel launches, no allocation, no synchronisation.
+ */
+size_t wect_image_ecf_workspace_bytes(const wect_complex* c);
+wect_status wect_image_ecf(const wect_complex* c, const float* thr, int32_t T, int32_t* out,
+                           void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
  * Synchronous data check on `hip_stream`: CSR offsets and shapes consistent
  * with the counts, vertex ids in range, thresholds non-decreasing, axes
  * strictly increasing, no NaN/Inf in coordinates, directions, thresholds or
@@ -192,7 +220,16 @@ const char* wect_status_string(wect_status s);
  *        the size giving the most resident wavefronts per compute unit);
  * blocks_per_cu: main-kernel blocks per compute unit (0 = as many as fit: 32
  *                wavefronts and 160 KiB of LDS per compute unit);
- * min_items_per_block: lower bound of stream items per block (0 = default, 256).
+ * min_items_per_block: lower bound of stream items per block (0 = default, 256);
+ * decomposition: how the forward splits its work over blocks
+ *   0 = automatic,
+ *   1 = stream: the (complex, direction tile, cell) stream is cut into equal
+ *       contiguous ranges, one per block; groups (complex, direction tile)
+ *       that a range covers whole are written by that block, the others are
+ *       summed from per-block partial histograms by a second kernel,
+ *   2 = one block per group: every block writes its group's output, with no
+ *       partial histograms and no second kernel (balanced when the groups
+ *       are of similar size and at least as many as the compute units).
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */
@@ -200,7 +237,7 @@ typedef struct {
   int32_t block;
   int32_t blocks_per_cu;
   int32_t min_items_per_block;
-  int32_t reserved;
+  int32_t decomposition;
 } wect_launch;
 
 wect_status wect_set_launch(const wect_launch* l);

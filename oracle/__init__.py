@@ -372,8 +372,11 @@ def image_ecf(C, thr: np.ndarray):
     ECF) or, when ``C.weighted``, the maximum corner intensity (a WECF).
     Returns [T] int64: sum of (-1)^dim w(c) over cells with value <= thr[q]."""
     I = np.asarray(C.intensity)
+    t = np.asarray(thr, dtype=np.float32).astype(np.float64)
     vals, sw = _cubical_values(C, I.astype(np.float64))   # integer intensities: exact
-    return _sorted_sums(vals, sw.astype(np.int64), np.asarray(thr, dtype=np.float32).astype(np.float64))
+    out = _sorted_sums(vals, sw.astype(np.int64), t)
+    out[np.isnan(t)] = 0   # value <= NaN holds for no cell
+    return out
 
 
 def image_ecf_cells(C, thr: np.ndarray):

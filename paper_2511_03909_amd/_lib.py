@@ -37,7 +37,7 @@ class WectGrid(ctypes.Structure):
 
 class WectLaunch(ctypes.Structure):
     _fields_ = [("block", c_int32), ("blocks_per_cu", c_int32), ("min_items_per_block", c_int32),
-                ("reserved", c_int32)]
+                ("decomposition", c_int32)]
 
 
 class WectError(RuntimeError):
@@ -87,6 +87,10 @@ def lib() -> ctypes.CDLL:
     L.wect_version.restype = c_char_p
     L.wect_last_error.argtypes = []
     L.wect_last_error.restype = c_char_p
+    L.wect_image_ecf_workspace_bytes.argtypes = [P(WectComplex)]
+    L.wect_image_ecf_workspace_bytes.restype = c_size_t
+    L.wect_image_ecf.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.wect_image_ecf.restype = c_int
     _lib = L
     return L
 

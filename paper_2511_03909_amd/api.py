@@ -158,6 +158,11 @@ class CubicalBatch:
         images = list(images)
         B = len(images)
         n = images[0].intensity.ndim
+        # one inclusion level, weight mode and dimension per batch (a single wect_complex)
+        for C in images[1:]:
+            if (C.include_above != images[0].include_above or bool(C.weighted) != bool(images[0].weighted)
+                    or np.asarray(C.intensity).ndim != n):
+                raise ValueError("every image of a batch needs the same dimension, include_above and weighting")
         shapes, flat, axes, gv, av = [], [], [], [0], [0]
         for C in images:
             I = np.asarray(C.intensity, np.uint8)
@@ -205,20 +210,44 @@ def wect_workspace_bytes(cx, grid: Grid, with_backward: bool = False) -> int:
     return int(L.lib().wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), int(with_backward)))
 
 
+def _check_tensor(t: torch.Tensor, name: str, device, dtype=None, shape=None) -> None:
+    """Caller-supplied buffers are written by the kernels: reject any that do not
+    match what the call will write (a wrong one would be written out of bounds)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != torch.device(device):
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _output(cx, grid, out):
+    shape = (cx.B, grid.d, grid.T)
+    if out is None:
+        return torch.empty(shape, dtype=_out_dtype(cx), device=cx.device)
+    _check_tensor(out, "out", cx.device, _out_dtype(cx), shape)
+    return out
+
+
 def _workspace(cx, grid, with_backward, ws):
     need = wect_workspace_bytes(cx, grid, with_backward)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
-    return ws, max(need, int(ws.numel()))
+    else:
+        _check_tensor(ws, "ws", cx.device)
+    return ws, int(ws.numel()) * ws.element_size()
 
 
 def wect_forward(cx, grid: Grid, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
     """Forward transform -> out [B, d, T] (int32 or float32); see wect_forward in wect.h."""
-    if out is None:
-        out = torch.empty((cx.B, grid.d, grid.T), dtype=_out_dtype(cx), device=cx.device)
+    out = _output(cx, grid, out)
     ws, nbytes = _workspace(cx, grid, False, ws)
     c, g = cx.struct(), grid.struct()
-    st = L.lib().wect_forward(ctypes.byref(c), ctypes.byref(g), _ptr(out), _ptr(ws), ctypes.c_size_t(int(ws.numel())),
+    st = L.lib().wect_forward(ctypes.byref(c), ctypes.byref(g), _ptr(out), _ptr(ws), ctypes.c_size_t(nbytes),
                               _stream(cx.device))
     L.check(st, "wect_forward")
     return out
@@ -239,14 +268,20 @@ def _gw_array(gw):
     return arr
 
 
+def _grad_in(cx, grid, grad_out: torch.Tensor) -> torch.Tensor:
+    grad_out = grad_out.to(dtype=torch.float32).contiguous()
+    _check_tensor(grad_out, "grad_out", cx.device, torch.float32, (cx.B, grid.d, grid.T))
+    return grad_out
+
+
 def wect_backward(cx, grid: Grid, grad_out: torch.Tensor, ws: Optional[torch.Tensor] = None):
     """Adjoint with respect to the weights: list per dimension (explicit) or [V] (vertex_max)."""
-    grad_out = grad_out.to(dtype=torch.float32).contiguous()
+    grad_out = _grad_in(cx, grid, grad_out)
     gw, gv = _grad_outputs(cx)
     ws, nbytes = _workspace(cx, grid, True, ws)
     c, g = cx.struct(), grid.struct()
     st = L.lib().wect_backward(ctypes.byref(c), ctypes.byref(g), _ptr(grad_out), _gw_array(gw), _ptr(gv),
-                               _ptr(ws), ctypes.c_size_t(int(ws.numel())), _stream(cx.device))
+                               _ptr(ws), ctypes.c_size_t(nbytes), _stream(cx.device))
     L.check(st, "wect_backward")
     return gv if gv is not None else gw
 
@@ -255,21 +290,25 @@ def wect_batched(cx, grid: Grid, grad_out: Optional[torch.Tensor] = None, out: O
                  grads=None, ws: Optional[torch.Tensor] = None):
     """Forward (+ backward when grad_out is given) for a batch in one call.
     Returns (out, grads) with grads None when grad_out is None."""
-    if out is None:
-        out = torch.empty((cx.B, grid.d, grid.T), dtype=_out_dtype(cx), device=cx.device)
+    out = _output(cx, grid, out)
     gw = gv = None
     if grad_out is not None:
-        grad_out = grad_out.to(dtype=torch.float32).contiguous()
+        grad_out = _grad_in(cx, grid, grad_out)
         if grads is None:
             gw, gv = _grad_outputs(cx)
         elif cx.wmode == "vertex_max":
             gv = grads
+            _check_tensor(gv, "grads", cx.device, torch.float32, (cx.counts[0],))
         else:
-            gw = grads
+            gw = list(grads)
+            if len(gw) != len(cx.counts):
+                raise ValueError(f"grads needs {len(cx.counts)} tensors, one per dimension")
+            for i, (t, k) in enumerate(zip(gw, cx.counts)):
+                _check_tensor(t, f"grads[{i}]", cx.device, torch.float32, (k,))
     ws, nbytes = _workspace(cx, grid, grad_out is not None, ws)
     c, g = cx.struct(), grid.struct()
     st = L.lib().wect_batched(ctypes.byref(c), ctypes.byref(g), _ptr(out), _ptr(grad_out), _gw_array(gw), _ptr(gv),
-                              _ptr(ws), ctypes.c_size_t(int(ws.numel())), _stream(cx.device))
+                              _ptr(ws), ctypes.c_size_t(nbytes), _stream(cx.device))
     L.check(st, "wect_batched")
     if grad_out is None:
         return out, None
@@ -282,15 +321,49 @@ def wect_validate(cx, grid: Grid) -> None:
     L.check(L.lib().wect_validate(ctypes.byref(c), ctypes.byref(g), _stream(cx.device)), "wect_validate")
 
 
-def set_launch(block: int = 0, blocks_per_cu: int = 0, min_items_per_block: int = 0) -> None:
-    L.check(L.lib().wect_set_launch(ctypes.byref(L.WectLaunch(block, blocks_per_cu, min_items_per_block, 0))),
-            "wect_set_launch")
+def image_ecf_workspace_bytes(cx) -> int:
+    c = cx.struct()
+    return int(L.lib().wect_image_ecf_workspace_bytes(ctypes.byref(c)))
+
+
+def image_ecf(cx, thr, out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """ECF of every image / volume of a cubical batch with the intensity as the
+    vertex filter -> int32 [B, T]; see wect_image_ecf in wect.h.  Weighted
+    batches (vertex_max) give the WECF with weight = largest corner intensity."""
+    thr = torch.as_tensor(thr, dtype=torch.float32).to(cx.device).contiguous()
+    T = int(thr.numel())
+    shape = (cx.B, T)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int32, device=cx.device)
+    else:
+        _check_tensor(out, "out", cx.device, torch.int32, shape)
+    need = image_ecf_workspace_bytes(cx)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
+    else:
+        _check_tensor(ws, "ws", cx.device)
+    c = cx.struct()
+    st = L.lib().wect_image_ecf(ctypes.byref(c), _ptr(thr), ctypes.c_int32(T), _ptr(out), _ptr(ws),
+                                ctypes.c_size_t(int(ws.numel()) * ws.element_size()), _stream(cx.device))
+    L.check(st, "wect_image_ecf")
+    return out
+
+
+DECOMP_AUTO, DECOMP_STREAM, DECOMP_GROUP = 0, 1, 2
+
+
+def set_launch(block: int = 0, blocks_per_cu: int = 0, min_items_per_block: int = 0,
+               decomposition: int = DECOMP_AUTO) -> None:
+    """Launch shape of the following calls (0 = automatic for each field); see wect_launch."""
+    L.check(L.lib().wect_set_launch(ctypes.byref(L.WectLaunch(block, blocks_per_cu, min_items_per_block,
+                                                              decomposition))), "wect_set_launch")
 
 
 def get_launch() -> dict:
     w = L.WectLaunch()
     L.check(L.lib().wect_get_launch(ctypes.byref(w)), "wect_get_launch")
-    return {"block": w.block, "blocks_per_cu": w.blocks_per_cu, "min_items_per_block": w.min_items_per_block}
+    return {"block": w.block, "blocks_per_cu": w.blocks_per_cu, "min_items_per_block": w.min_items_per_block,
+            "decomposition": w.decomposition}
 
 
 def profile_enable(on: bool = True) -> None:

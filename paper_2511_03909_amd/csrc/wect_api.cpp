@@ -53,6 +53,7 @@ bool device_info(DeviceInfo* out) {
 std::atomic<int> g_block{0};  // 0: chosen per request by auto_block()
 std::atomic<int> g_bpc{0};  // 0: as many as LDS and wave slots allow
 std::atomic<int> g_min_items{256};
+std::atomic<int> g_decomp{0};  // wect_launch.decomposition
 
 // measurement
 std::atomic<int> g_profile{0};
@@ -72,6 +73,7 @@ struct Plan {
   size_t lds_fwd = 0, lds_bwd = 0;
   size_t partial_bytes = 0, dsum_bytes = 0, absmax_bytes = 0;
   bool split = false;
+  bool group_mode = false;
   size_t ws_fwd = 0, ws_bwd = 0;
   int64_t elems = 0;  // stream elements per direction tile / group
   int G_fwd = 0, G_bwd = 0;
@@ -239,17 +241,25 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     const int64_t max_blocks = (int64_t)cus * blocks_per_cu(pl->lds_fwd);
     int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
     G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
+    const int64_t groups = (int64_t)c->B * ntiles;
+    // one block per group: asked for, or automatic when there are at least as
+    // many groups as resident blocks and each is worth a block's set-up
+    const int decomp = g_decomp.load();
+    const bool fits = S > 0 && groups * block < ((int64_t)1 << 32);  // grid limit: 2^32 threads
+    const bool big = S >= groups * 8 * (int64_t)block;                // 8 tiles of work per block or more
+    pl->group_mode = fits && (decomp == 2 || (decomp == 0 && groups >= max_blocks && big));
+    if (pl->group_mode) G = groups;
     pl->G_fwd = (int)G;
     pl->S_fwd = S;
-    const int64_t groups = (int64_t)c->B * ntiles;
-    const int64_t slots = G + groups;
+    p.group_mode = pl->group_mode ? 1 : 0;
+    const int64_t slots = pl->group_mode ? 0 : G + groups;
     const size_t slot_bytes = (size_t)g->T * kW * acc_bytes;
     // Slots a group may have (blocks meeting its stream range).  A batch's
     // per-complex sizes are on the device: the kernels decide per group, and
     // the separate slot summation is launched when the average group has many
     // slots.  Either way every group is summed correctly.
     const int64_t spg = c->B == 1 ? ceil_div(G, ntiles) + 1 : ceil_div(G, groups) + 1;
-    pl->split = spg > 16;  // kFusedSlots in the kernels
+    pl->split = !pl->group_mode && spg > 16;  // kFusedSlots in the kernels
     pl->partial_bytes = align256((size_t)slots * slot_bytes);
     pl->dsum_bytes = pl->split ? align256((size_t)groups * slot_bytes) : 0;
     pl->absmax_bytes = acc_bytes == 8 ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
@@ -370,6 +380,51 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
   return WECT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// image ECF
+// ---------------------------------------------------------------------------
+
+struct EcfPlan {
+  Params p;
+  int block = 1024;
+  size_t ws = 0;
+};
+
+wect_status ecf_plan(const wect_complex* c, int32_t T, const float* thr, EcfPlan* pl) {
+  if (!c || T < 0 || (T > 0 && !thr)) return WECT_ERR_ARG;
+  if (c->kind != WECT_CUBICAL || (c->n != 2 && c->n != 3) || c->B < 1) return WECT_ERR_ARG;
+  if (c->wmode == WECT_W_EXPLICIT) return WECT_ERR_UNSUPPORTED;
+  if (c->wmode != WECT_W_ONES && c->wmode != WECT_W_VERTEX_MAX) return WECT_ERR_ARG;
+  if (c->dtype != WECT_I32 || c->total_voxels < 0 || !c->shape) return WECT_ERR_ARG;
+  if (c->total_voxels > 0 && !c->intensity) return WECT_ERR_ARG;
+  if (c->B > 1 && !c->grid_off) return WECT_ERR_ARG;
+  if (c->include_above < -1 || c->include_above > 255) return WECT_ERR_ARG;
+  Params& p = pl->p;
+  std::memset(&p, 0, sizeof(p));
+  p.kind = WECT_CUBICAL;
+  p.n = c->n;
+  p.B = c->B;
+  p.wmode = c->wmode;
+  p.dtype = WECT_I32;
+  p.shape = c->shape;
+  p.grid_off = c->grid_off;
+  p.intensity = c->intensity;
+  p.total_voxels = c->total_voxels;
+  p.include_above = c->include_above;
+  p.thr = thr;
+  p.T = T;
+  p.ntiles = 1;  // one group per image
+  DeviceInfo di;
+  const int cus = device_info(&di) ? di.cus : 256;
+  const int64_t S = c->total_voxels;
+  // 1024-thread blocks, two per compute unit, at least 8192 voxels each
+  const int64_t G = std::max<int64_t>(1, std::min<int64_t>(2LL * cus, ceil_div(S, 8192)));
+  p.S = S;
+  p.G = (int)G;
+  pl->ws = align256((size_t)(G + c->B) * wect::kEcfSlotBytes);
+  return WECT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -457,6 +512,8 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (!l) return WECT_ERR_ARG;
   if (l->block != 0 && !valid_block(l->block)) return WECT_ERR_ARG;
   if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64 || l->min_items_per_block < 0) return WECT_ERR_ARG;
+  if (l->decomposition < 0 || l->decomposition > 2) return WECT_ERR_ARG;
+  g_decomp.store(l->decomposition);
   g_block.store(l->block);
   g_bpc.store(l->blocks_per_cu);
   g_min_items.store(l->min_items_per_block ? l->min_items_per_block : 256);
@@ -468,7 +525,7 @@ wect_status wect_get_launch(wect_launch* l) {
   l->block = g_block.load();
   l->blocks_per_cu = g_bpc.load();
   l->min_items_per_block = g_min_items.load();
-  l->reserved = 0;
+  l->decomposition = g_decomp.load();
   return WECT_OK;
 }
 
@@ -500,6 +557,26 @@ wect_status wect_profile_read(double* fwd_ms, int64_t* fwd_launches, double* bwd
     }
     g_prof.clear();
   }
+  return WECT_OK;
+}
+
+size_t wect_image_ecf_workspace_bytes(const wect_complex* c) {
+  EcfPlan pl;
+  if (ecf_plan(c, 0, nullptr, &pl) != WECT_OK) return 0;
+  return pl.ws;
+}
+
+wect_status wect_image_ecf(const wect_complex* c, const float* thr, int32_t T, int32_t* out, void* ws,
+                           size_t ws_bytes, void* hip_stream) {
+  EcfPlan pl;
+  if (wect_status st = ecf_plan(c, T, thr, &pl); st != WECT_OK) return st;
+  if ((int64_t)c->B * T == 0) return WECT_OK;
+  if (!out) return WECT_ERR_ARG;
+  if (!ws || ws_bytes < pl.ws) return WECT_ERR_WORKSPACE;
+  pl.p.out = out;
+  pl.p.partial = ws;
+  if (hipError_t e = wect::launch_image_ecf(pl.p, pl.block, static_cast<hipStream_t>(hip_stream)); e != hipSuccess)
+    return device_error(e, "image ECF kernels");
   return WECT_OK;
 }
 

@@ -41,6 +41,7 @@ struct Params {
   void* partial;         // forward: [slots][T][64] uint32 (integer weights) / uint64 (fixed point)
   void* dsum;            // forward, split reduction: [groups][T][64] slot sums
   int32_t split;         // 1: k_slot_sum first, then the scan reads dsum
+  int32_t group_mode;    // 1: block k handles exactly group k (G = groups), no reduction kernel
   float* absmax;         // float32 weights: per-block max |w| ([nabsmax])
   int32_t nabsmax;
   double cells_total;    // bound on the cells of any complex (fixed-point scale)
@@ -58,6 +59,10 @@ hipError_t launch_forward_reduce(const Params& p, hipStream_t s);
 hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s);
 hipError_t launch_validate(const Params& p, int* flags, hipStream_t s);
+// Image ECF: main kernel (p.G blocks of `block` threads, when p.S > 0) and the
+// per-image finish (p.B blocks).
+hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s);
+constexpr int kEcfSlotBytes = 256 * 4;  // one partial histogram over the intensity values
 
 hipError_t launch_absmax(const Params& p, hipStream_t s);
 

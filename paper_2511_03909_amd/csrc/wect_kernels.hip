@@ -69,9 +69,9 @@ __device__ __forceinline__ float height(const float* c, float sx, float sy, floa
 struct Thr {
   const float* P;   // LDS [T+1]: P[q] = thr[q-1], P[0] = -inf
   float c, k;       // guess: t = fma(h, c, k) puts thr[q] near q + 1.5
-  float ka;         // arithmetic index: t = fma(h, c, ka) puts thr[q] near q + 1
+  float ka;         // arithmetic index: t = fma(h, c, ka) puts thr[q] just above q + 1
   float tmax;       // T + 0.5
-  float half_open;  // 0.5 - delta (see thr_arith)
+  float theta;      // arithmetic index exact when frac(t) > theta (see thr_arith)
   int T, p2, fast, arith;
 };
 
@@ -83,6 +83,10 @@ __device__ __forceinline__ int guess(float h, float c, float k, int T) {
   t = __builtin_amdgcn_fmed3f(t, 0.0f, (float)T);
   return (int)t;
 }
+
+// Near-threshold fix of the arithmetic index and of the guess: b is the
+// candidate m (in [0, T]); P[m] = thr[m-1] decides between m-1 and m.
+__device__ __forceinline__ int thr_near(float h, int b, const Thr& th) { return b - (h <= th.P[b] ? 1 : 0); }
 
 __device__ __forceinline__ float next_up(float x) {
   if (!(x == x) || x == INFINITY) return x;
@@ -98,8 +102,7 @@ __device__ __forceinline__ float next_up(float x) {
 template <bool FAST>
 __device__ __forceinline__ int thr_index(float h, const Thr& th) {
   if constexpr (FAST) {
-    const int g = guess(h, th.c, th.k, th.T);
-    return g - (h <= th.P[g] ? 1 : 0);
+    return thr_near(h, guess(h, th.c, th.k, th.T), th);
   }
   int lo = 0;
   for (int s = th.p2; s > 0; s >>= 1) {
@@ -110,57 +113,31 @@ __device__ __forceinline__ int thr_index(float h, const Thr& th) {
 }
 
 // Index from the affine map alone.  With x(h) = h c + ka (exact, strictly
-// increasing) and tau_q = x(thr[q]), L(h) = #{q : tau_q < x(h)}.  The stored
-// thresholds satisfy |tau_q - (q+1)| <= dev and t = fl(x(h)) is within
-// 2^-24 (T+2) <= delta/2 of x(h) (delta = 2 dev + 2^-23 (T+2) + 1e-7, measured
-// when the block starts).  When frac(t) is further than delta from 0 and 1,
-// every tau_q with q+1 <= floor(t) lies below x(h) and every other one above,
-// so L = clamp(floor(t), 0, T).  Otherwise h is within 2 delta of one position
-// m = round(t) and only thr[m-1] can be on either side: L = m - [h <= thr[m-1]].
-__device__ __forceinline__ bool thr_arith(float h, const Thr& th, int& b, float& t) {
-  t = __builtin_fmaf(h, th.c, th.ka);
+// increasing) and tau_q = x(thr[q]), L(h) = #{q : tau_q < x(h)}.  The block
+// prologue picks ka so that every tau_q lies in [q+1+rmin, q+1+rmax] with
+// rmin >= eps, where eps = 2^-24 (T+2) bounds the rounding of t = fl(x(h)).
+// Write t = m + u (m = floor t, 0 <= u < 1).  Every tau_q with q+1 >= m+1 is
+// then >= m+1+eps > x(h), and when u > theta = rmax + eps every tau_q with
+// q+1 <= m is <= m+rmax < x(h): L = clamp(m, 0, T), one truncation.  Otherwise
+// x(h) is within rmax+2 eps of m and only tau_{m-1} can be on either side:
+// L = m - [h <= thr[m-1]] (thr_near).  Clamping t to [-0.5, T+0.5] keeps both
+// ends exact: u = 0.5 there and the truncation gives 0 and T.
+__device__ __forceinline__ bool thr_arith(float h, const Thr& th, int& b) {
+  float t = __builtin_fmaf(h, th.c, th.ka);
   t = __builtin_amdgcn_fmed3f(t, -0.5f, th.tmax);
-  const float fr = __builtin_amdgcn_fractf(t);
-  b = max((int)(t - fr), 0);
-  return fabsf(fr - 0.5f) < th.half_open;
+  b = (int)t;
+  return __builtin_amdgcn_fractf(t) > th.theta;
 }
 
-__device__ __forceinline__ int thr_near(float h, float t, const Thr& th) {
-  const int m = min((int)rintf(t), th.T);
-  return m - (h <= th.P[m] ? 1 : 0);
-}
-
-// Per-wavefront choice between the arithmetic index (no LDS read unless a lane
-// sits on a threshold) and the one-read guess: images whose pixel lattice is
-// commensurate with the threshold grid put many heights exactly on thresholds
-// for some directions; a wavefront that needs the near-threshold fix in more
-// than 8 of 32 consecutive pairs switches to the guess for the rest of its range.
-struct IndexMode {
-  int arith, pairs, fallbacks;
-};
-
-template <bool FAST>
-__device__ __forceinline__ void thr_index2(float h0, float h1, const Thr& th, int& b0, int& b1, IndexMode& md) {
-  if constexpr (FAST) {
-    if (md.arith) {
-      float t0, t1;
-      const bool ok0 = thr_arith(h0, th, b0, t0);
-      const bool ok1 = thr_arith(h1, th, b1, t1);
-      if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
-        ++md.fallbacks;
-        if (!ok0) b0 = thr_near(h0, t0, th);
-        if (!ok1) b1 = thr_near(h1, t1, th);
-      }
-      if (++md.pairs == 32) {
-        if (md.fallbacks > 8) md.arith = 0;
-        md.pairs = 0;
-        md.fallbacks = 0;
-      }
-      return;
-    }
-  }
-  b0 = thr_index<FAST>(h0, th);
-  b1 = thr_index<FAST>(h1, th);
+// Minimum over the block (every thread gets it); red holds 16 doubles.
+__device__ double block_min(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = INFINITY;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v = fmin(v, red[w]);
+  return v;
 }
 
 // Block prologue: stage P in LDS and decide whether the fast path is exact
@@ -192,32 +169,43 @@ __device__ void setup_thresholds(const float* thr, int T, float* P, Thr& th) {
     }
   }
   bad = __syncthreads_or(bad);
-  // arithmetic index: distance of the stored thresholds from their positions
-  __shared__ double s_dev[16];
-  const float ka = ok ? 1.0f - thr[0] * c : 0.0f;
-  double dev = 0.0;
+  // arithmetic index: place every tau_q = thr[q] c + ka at or above q + 1 + eps
+  // (exact products in double, one rounding of about 2^-53 (T+2))
+  __shared__ double s_red[2][16];
+  const double eps = ldexp(1.0, -24) * (T + 2) + 1e-9;
+  float ka = 0.0f;
+  double rmin = 0.0, rmax = 0.0;
+  int arith = 0;
   if (ok && !bad) {
+    const float ka0 = 1.0f - thr[0] * c;
+    double lo = INFINITY;
+    for (int q = threadIdx.x; q < T; q += blockDim.x)
+      lo = fmin(lo, (double)thr[q] * (double)c + (double)ka0 - (double)(q + 1));
+    lo = block_min(lo, s_red[0]);
+    // the smallest float ka >= ka0 + (eps - lo) (exact in double, rounded up)
+    const double want = (double)ka0 + (eps - lo) + 1e-9;
+    ka = (float)want;
+    if ((double)ka < want) ka = next_up(ka);
+    double a = INFINITY, z = -INFINITY;
     for (int q = threadIdx.x; q < T; q += blockDim.x) {
-      const double tau = (double)thr[q] * (double)c + (double)ka;  // exact product, one rounding
-      dev = fmax(dev, fabs(tau - (double)(q + 1)));
+      const double r = (double)thr[q] * (double)c + (double)ka - (double)(q + 1);
+      a = fmin(a, r);
+      z = fmax(z, r);
     }
+    rmin = block_min(a, s_red[0]);
+    rmax = -block_min(-z, s_red[1]);
+    arith = rmin >= eps && rmax + eps < 0.25;
   }
-  for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
-  if ((threadIdx.x & 63) == 0) s_dev[threadIdx.x >> 6] = dev;
-  __syncthreads();
-  dev = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) dev = fmax(dev, s_dev[w]);
-  const double delta = 2.0 * dev + ldexp(1.0, -23) * (T + 2) + 1e-7;
   th.P = P;
   th.c = c;
   th.k = k;
   th.ka = ka;
   th.tmax = (float)T + 0.5f;
-  th.half_open = (float)(0.5 - delta);
+  th.theta = (float)(rmax + eps) + 0x1p-24f;  // rounded up past rmax + eps
   th.T = T;
   th.p2 = p2;
-  th.fast = ok && !bad;
-  th.arith = th.fast && delta < 0.25;
+  th.fast = uniform(ok && !bad);
+  th.arith = uniform(th.fast && arith);
   __syncthreads();
 }
 
@@ -230,6 +218,63 @@ __device__ __forceinline__ void lds_add(uint32_t* a, uint32_t v) {
 }
 __device__ __forceinline__ void lds_add(uint64_t* a, uint64_t v) {
   __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds staged entries to the lane's histogram column col ([T+1] rows of W
+// lanes): the pairs (e, e+1) for e = first, first + step, ... below ne, then a
+// last single entry.  entry(e, h, w) gives the lane's height and the signed
+// weight of entry e.
+//
+// Per-wavefront choice between the arithmetic index (no LDS read unless a lane
+// sits on a threshold) and the one-read guess: images whose pixel lattice is
+// commensurate with the threshold grid put many heights exactly on thresholds
+// for some directions; a wavefront that needs the near-threshold fix in more
+// than a quarter of a run of up to 32 pairs switches to the guess for the rest
+// of its range.  The mode lives in *arith (wavefront-uniform).
+template <bool FAST, typename ACC, typename Entry>
+__device__ __forceinline__ void hist_entries(ACC* col, int first, int step, int ne, const Thr& th, int* arith,
+                                             Entry entry) {
+  int e = first;
+  if constexpr (FAST) {
+    while (*arith && e + 1 < ne) {
+      const int stop = min(ne - 1, e + 32 * step);
+      int fixes = 0, pairs = 0;
+      for (; e < stop; e += step) {
+        float h0, h1;
+        ACC w0, w1;
+        entry(e, h0, w0);
+        entry(e + 1, h1, w1);
+        int b0, b1;
+        const bool ok0 = thr_arith(h0, th, b0);
+        const bool ok1 = thr_arith(h1, th, b1);
+        if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
+          ++fixes;
+          if (!ok0) b0 = thr_near(h0, b0, th);
+          if (!ok1) b1 = thr_near(h1, b1, th);
+        }
+        ++pairs;
+        lds_add(&col[b0 * W], w0);
+        lds_add(&col[b1 * W], w1);
+      }
+      if (4 * fixes > pairs) *arith = 0;
+    }
+  }
+  for (; e + 1 < ne; e += step) {
+    float h0, h1;
+    ACC w0, w1;
+    entry(e, h0, w0);
+    entry(e + 1, h1, w1);
+    const int b0 = thr_index<FAST>(h0, th);
+    const int b1 = thr_index<FAST>(h1, th);
+    lds_add(&col[b0 * W], w0);
+    lds_add(&col[b1 * W], w1);
+  }
+  if (e < ne) {
+    float h0;
+    ACC w0;
+    entry(e, h0, w0);
+    lds_add(&col[thr_index<FAST>(h0, th) * W], w0);
+  }
 }
 
 // Sum over the 64 lanes of a wavefront: rotate-and-add inside each row of 16
@@ -433,7 +478,7 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
     st.gather(p, soff + tile_row(0), voff, fexp);
   }
   int nidx[L::NV];
-  IndexMode md = {th.arith, 0, 0};
+  int arith = th.arith;
   bool have_next = ntile > 1 && tid < TS && tile_row(1) < hi;
   if (have_next) {
     ST tmp;
@@ -460,26 +505,12 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
       for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
     }
     // histogram of tile t: each wavefront takes adjacent pairs of entries
-    int e = 2 * wave;
-    for (; e + 1 < cnt; e += 2 * nw) {
-      const float* E0 = stage + e * L::STRIDE;
-      const float* E1 = E0 + L::STRIDE;
-      float h0 = max_height<N, DIM>(E0, sx, sy, sz);
-      float h1 = max_height<N, DIM>(E1, sx, sy, sz);
-      ACC w0 = load_weight<ACC>(E0 + L::WOFF);
-      ACC w1 = load_weight<ACC>(E1 + L::WOFF);
-      int b0, b1;
-      thr_index2<FAST>(h0, h1, th, b0, b1, md);
-      lds_add(&hist[b0 * W + lane], w0);
-      lds_add(&hist[b1 * W + lane], w1);
-    }
-    if (e < cnt) {
-      const float* E0 = stage + e * L::STRIDE;
-      float h0 = max_height<N, DIM>(E0, sx, sy, sz);
-      ACC w0 = load_weight<ACC>(E0 + L::WOFF);
-      int b0 = thr_index<FAST>(h0, th);
-      lds_add(&hist[b0 * W + lane], w0);
-    }
+    hist_entries<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
+                            [&](int e, float& h, ACC& w) {
+                              const float* E = stage + e * L::STRIDE;
+                              h = max_height<N, DIM>(E, sx, sy, sz);
+                              w = load_weight<ACC>(E + L::WOFF);
+                            });
   }
   __syncthreads();
 }
@@ -507,6 +538,102 @@ __device__ void flush_hist(const Params& p, ACC* hist, int64_t slot) {
   __syncthreads();
 }
 
+template <typename ACC>
+struct OutOf;
+template <>
+struct OutOf<uint32_t> {
+  using T = uint32_t;  // int32 bit pattern
+  __device__ static uint32_t conv(uint32_t x, int) { return x; }
+};
+template <>
+struct OutOf<uint64_t> {
+  using T = float;
+  __device__ static float conv(uint64_t x, int fexp) { return (float)ldexp((double)(int64_t)x, -fexp); }
+};
+
+// A block that covered a whole group (complex b, direction tile t) writes its
+// output itself: out[b][t*64 + lane][q] = sum_{j <= q} hist[j][lane] (the
+// cumulative sum of Algorithm 1), then clears hist.  The scan runs in place:
+// wavefront r takes rows [r c, (r+1) c) and turns them into a running sum, so
+// the last row of each chunk holds the chunk total that later chunks add.
+template <typename ACC>
+__device__ void finish_group(const Params& p, ACC* hist, int b, int t, int fexp) {
+  using O = OutOf<ACC>;
+  using OT = typename O::T;
+  __syncthreads();
+  const int T = p.T;
+  const int lane = threadIdx.x & (W - 1), r = threadIdx.x >> 6, R = blockDim.x >> 6;
+  const int chunk = ((T + R - 1) / R + 3) & ~3;  // a multiple of 4 rows
+  const int q0 = min(T, r * chunk), q1 = min(T, q0 + chunk);
+  ACC run = 0;
+  for (int q = q0; q < q1; ++q) {
+    run += hist[q * W + lane];
+    hist[q * W + lane] = run;
+  }
+  __syncthreads();
+  ACC off = 0;
+  for (int rr = 0; rr < r; ++rr) {
+    const int e = min(T, (rr + 1) * chunk);
+    if (e > rr * chunk) off += hist[(e - 1) * W + lane];
+  }
+  const int dir = t * W + lane;
+  if (dir < p.d && q0 < q1) {
+    OT* o = (OT*)p.out + ((int64_t)b * p.d + dir) * T;
+    if ((T & 3) == 0 && (reinterpret_cast<uintptr_t>(p.out) & 15) == 0) {
+      // rows start 16-byte aligned and q0 is a multiple of 4
+      for (int q = q0; q < q1; q += 4) {
+        OT v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = O::conv(hist[(q + j) * W + lane] + off, fexp);
+        *(uint4*)(o + q) = *(const uint4*)v;
+      }
+    } else {
+      for (int q = q0; q < q1; ++q) o[q] = O::conv(hist[q * W + lane] + off, fexp);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = ACC(0);
+  __syncthreads();
+}
+
+// End of a block's share of group (b, t): the whole group gives the output
+// directly, part of it a partial histogram in slot k + group.
+template <typename ACC>
+__device__ __forceinline__ void end_group(const Params& p, ACC* hist, int k, int b, int t, bool whole, int fexp) {
+  if (whole) finish_group<ACC>(p, hist, b, t, fexp);
+  else flush_hist<ACC>(p, hist, (int64_t)k + (int64_t)b * p.ntiles + t);
+}
+
+// Stream range [pos, end) of block k and the complex it starts in.  Group
+// mode: exactly group k (an empty group writes its zero output here).
+template <typename ACC>
+__device__ __forceinline__ bool block_range(const Params& p, ACC* hist, int k, int fexp, int64_t& pos, int64_t& end,
+                                            int& b) {
+  const int gpc = p.ntiles;
+  if (p.group_mode) {
+    b = k / gpc;
+    const int t = k - b * gpc;
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    pos = (int64_t)gpc * cb + (int64_t)t * nb;
+    end = pos + nb;
+    if (nb == 0) {
+      finish_group<ACC>(p, hist, b, t, fexp);
+      return false;
+    }
+    return true;
+  }
+  pos = block_start(k, p.S, p.G);
+  end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return false;
+  b = find_complex(p, pos, gpc);
+  return true;
+}
+
+// The lane's direction.  The empty asm statement reads the three components,
+// so the compiler waits for their loads here, once per group: otherwise it may
+// place that wait inside the histogram loop, where it would also wait for the
+// loads of the next staging tile that are meant to be in flight.
 __device__ __forceinline__ void load_dir(const Params& p, int gp, float& sx, float& sy, float& sz) {
   sx = sy = sz = 0.0f;
   if (gp < p.d) {
@@ -515,6 +642,7 @@ __device__ __forceinline__ void load_dir(const Params& p, int gp, float& sx, flo
     if (p.n >= 2) sy = s[1];
     if (p.n >= 3) sz = s[2];
   }
+  asm volatile("" ::"v"(sx), "v"(sy), "v"(sz));
 }
 
 __device__ __forceinline__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -539,11 +667,10 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
   __syncthreads();
 
   const int k = blockIdx.x;
-  int64_t pos = block_start(k, p.S, p.G);
-  const int64_t end = block_start(k + 1, p.S, p.G);
-  if (pos >= end) return;
+  int64_t pos, end;
+  int b;
+  if (!block_range<ACC>(p, hist, k, fexp, pos, end, b)) return;
   const int gpc = p.ntiles;
-  int b = find_complex(p, pos, gpc);
   const int lane = threadIdx.x & (W - 1);
   while (pos < end) {
     const int64_t cb = cum_elems(p, b);
@@ -572,7 +699,7 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
       }
       dlo = dhi;
     }
-    flush_hist<ACC>(p, hist, (int64_t)k + (int64_t)b * gpc + t);
+    end_group<ACC>(p, hist, k, b, t, e0 == 0 && e1 == nb, fexp);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;
   }
@@ -615,27 +742,48 @@ __device__ __forceinline__ int cub_val(CubCell c) {
   return c.mn >= 0 ? (WM == WM_ONES ? 1 : c.mx) : 0;
 }
 
-// Combined weights of vertex (i0,i1,i2) for the 2^N orthants.  Orthant bit k
-// set means s_k < 0: the cells topped by v then extend towards +k, otherwise
-// towards -k.  Each distinct cell containing v (2N edges, the squares of each
-// axis pair, the 2^N cubes) is evaluated once.
-template <int N, int WM>
-__device__ __forceinline__ void cub_weights(const Params& p, const uint8_t* vol, int n0, int n1, int n2,
-                                            int i0, int i1, int i2, int32_t* cw) {
-  constexpr int M = N == 2 ? 9 : 27;
+// Raw neighbourhood of one voxel, loaded one tile ahead of its use: the
+// intensities of the 3^N voxels around it (-1 outside the grid), its axis
+// coordinates and its grid position.
+template <int N>
+struct CubFetch {
+  static constexpr int M = N == 2 ? 9 : 27;
   int nb[M];
-  const int thr = p.include_above;
+  float cx, cy, cz;
+  bool valid;
+
+  __device__ __forceinline__ void load(const uint8_t* vol, const float* ax0, const float* ax1, const float* ax2,
+                                       int n0, int n1, int n2, uint32_t v, bool active) {
+    valid = active;
+    // voxel counts of one complex are below 2^31 (checked by wect_validate)
+    const uint32_t r = v / (uint32_t)n0;
+    const int i0 = (int)(v - r * (uint32_t)n0);
+    const uint32_t i2u = r / (uint32_t)n1;
+    const int i1 = (int)(r - i2u * (uint32_t)n1);
+    const int i2 = (int)i2u;
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
-    const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
-    int v = -1;
-    if (j0 >= 0 && j0 < n0 && j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2) {
-      int x = vol[((int64_t)j2 * n1 + j1) * n0 + j0];
-      v = x > thr ? x : -1;
+    for (int m = 0; m < M; ++m) {
+      const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
+      const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
+      const bool in = active && j0 >= 0 && j0 < n0 && j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2;
+      nb[m] = in ? (int)vol[(int)v + d0 + d1 * n0 + (N == 3 ? d2 * n0 * n1 : 0)] : -1;
     }
-    nb[m] = v;
+    cx = active ? ax0[i0] : 0.0f;
+    cy = active ? ax1[i1] : 0.0f;
+    cz = (N == 3 && active) ? ax2[i2] : 0.0f;
   }
+};
+
+// Combined weights of a staged vertex for the 2^N orthants, from its raw
+// neighbourhood.  Orthant bit k set means s_k < 0: the cells topped by v then
+// extend towards +k, otherwise towards -k.  Each distinct cell containing v
+// (2N edges, the squares of each axis pair, the 2^N cubes) is evaluated once.
+template <int N, int WM>
+__device__ __forceinline__ void cub_weights(const CubFetch<N>& f, int include_above, int32_t* cw) {
+  constexpr int M = CubFetch<N>::M;
+  int nb[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) nb[m] = f.nb[m] > include_above ? f.nb[m] : -1;
   auto at = [&](int d0, int d1, int d2) { return nb[(d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0)]; };
   const int v0 = at(0, 0, 0);
   const CubCell cv = {v0, v0};
@@ -679,6 +827,8 @@ __device__ __forceinline__ void cub_weights(const Params& p, const uint8_t* vol,
   }
 }
 
+// Forward over the voxels [lo, hi) of complex b for one direction tile: the
+// neighbourhoods of tile t+1 are loaded while the histogram of tile t runs.
 template <int N, int WM, bool FAST>
 __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, float sx, float sy, float sz,
                               int orth, uint32_t* hist, float* stage, int* counter, const Thr& th) {
@@ -693,32 +843,20 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
   const float* ax0 = p.axis + aoff;
   const float* ax1 = ax0 + n0;
   const float* ax2 = ax1 + n1;
-  IndexMode md = {th.arith, 0, 0};
+  int arith = th.arith;
+  CubFetch<N> f;
+  f.load(vol, ax0, ax1, ax2, n0, n1, n2, (uint32_t)(lo + tid), lo + tid < hi && tid < TS);
   for (int64_t t0 = lo; t0 < hi; t0 += TS) {
-    const int cnt = (int)mn64(TS, hi - t0);
     if (tid == 0) *counter = 0;
     __syncthreads();
     bool keep = false;
-    float cx = 0.0f, cy = 0.0f, cz = 0.0f;
     int32_t cw[L::NO];
-    if (tid < cnt) {
-      // voxel counts of one complex are below 2^31 (checked by wect_validate)
-      const uint32_t v = (uint32_t)(t0 + tid);
-      const uint32_t r = v / (uint32_t)n0;
-      const int i0 = (int)(v - r * (uint32_t)n0);
-      const uint32_t i2u = r / (uint32_t)n1;
-      const int i1 = (int)(r - i2u * (uint32_t)n1);
-      const int i2 = (int)i2u;
-      if ((int)vol[v] > p.include_above) {
-        cub_weights<N, WM>(p, vol, n0, n1, n2, i0, i1, i2, cw);
-        bool nz = false;
+    if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
+      cub_weights<N, WM>(f, p.include_above, cw);
+      bool nz = false;
 #pragma unroll
-        for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
-        keep = nz;
-        cx = ax0[i0];
-        cy = ax1[i1];
-        if constexpr (N == 3) cz = ax2[i2];
-      }
+      for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
+      keep = nz;
     }
     // compact the contributing vertices
     const uint64_t bal = __ballot(keep);
@@ -728,35 +866,23 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
     if (keep) {
       const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
       float* E = stage + slot * L::STRIDE;
-      E[0] = cx;
-      E[1] = cy;
-      if constexpr (N == 3) { E[2] = cz; E[3] = 0.0f; }
+      E[0] = f.cx;
+      E[1] = f.cy;
+      if constexpr (N == 3) { E[2] = f.cz; E[3] = 0.0f; }
 #pragma unroll
       for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
     }
+    // neighbourhoods of the next tile (in flight during this tile's histogram)
+    const int64_t nx = t0 + TS + tid;
+    f.load(vol, ax0, ax1, ax2, n0, n1, n2, (uint32_t)nx, nx < hi && tid < TS);
     __syncthreads();
     const int ne = uniform(*counter);
     const float* Wl = stage + L::COFF + orth;  // the lane's combined weight within an entry
-    int e = 2 * wave;
-    for (; e + 1 < ne; e += 2 * nw) {
-      const float* E0 = stage + e * L::STRIDE;
-      const float* E1 = E0 + L::STRIDE;
-      float h0 = height<N>(E0, sx, sy, sz);
-      float h1 = height<N>(E1, sx, sy, sz);
-      uint32_t w0 = bitcast<uint32_t>(Wl[e * L::STRIDE]);
-      uint32_t w1 = bitcast<uint32_t>(Wl[e * L::STRIDE + L::STRIDE]);
-      int b0, b1;
-      thr_index2<FAST>(h0, h1, th, b0, b1, md);
-      lds_add(&hist[b0 * W + lane], w0);
-      lds_add(&hist[b1 * W + lane], w1);
-    }
-    if (e < ne) {
-      const float* E0 = stage + e * L::STRIDE;
-      float h0 = height<N>(E0, sx, sy, sz);
-      uint32_t w0 = bitcast<uint32_t>(Wl[e * L::STRIDE]);
-      int b0 = thr_index<FAST>(h0, th);
-      lds_add(&hist[b0 * W + lane], w0);
-    }
+    hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
+                                 [&](int e, float& h, uint32_t& w) {
+                                   h = height<N>(stage + e * L::STRIDE, sx, sy, sz);
+                                   w = bitcast<uint32_t>(Wl[e * L::STRIDE]);
+                                 });
     __syncthreads();
   }
 }
@@ -778,11 +904,10 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
   __syncthreads();
 
   const int k = blockIdx.x;
-  int64_t pos = block_start(k, p.S, p.G);
-  const int64_t end = block_start(k + 1, p.S, p.G);
-  if (pos >= end) return;
+  int64_t pos, end;
+  int b;
+  if (!block_range<uint32_t>(p, hist, k, 0, pos, end, b)) return;
   const int gpc = p.ntiles;
-  int b = find_complex(p, pos, gpc);
   const int lane = threadIdx.x & (W - 1);
   while (pos < end) {
     const int64_t cb = cum_elems(p, b);
@@ -797,7 +922,7 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
     const int orth = (sx < 0.0f ? 1 : 0) | (sy < 0.0f ? 2 : 0) | (sz < 0.0f ? 4 : 0);
     if (th.fast) cub_fwd_range<N, WM, true>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
     else cub_fwd_range<N, WM, false>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
-    flush_hist<uint32_t>(p, hist, (int64_t)k + (int64_t)b * gpc + t);
+    end_group<uint32_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, 0);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;
   }
@@ -856,25 +981,18 @@ __global__ __launch_bounds__(256) void k_slot_sum(Params p) {
   ((ACC*)p.dsum)[((int64_t)g * T + q) * W + lane] = (v0 + v1) + (v2 + v3);
 }
 
-template <typename ACC>
-struct OutOf;
-template <>
-struct OutOf<uint32_t> {
-  using T = uint32_t;  // int32 bit pattern
-  __device__ static uint32_t conv(uint32_t x, int) { return x; }
-};
-template <>
-struct OutOf<uint64_t> {
-  using T = float;
-  __device__ static float conv(uint64_t x, int fexp) { return (float)ldexp((double)(int64_t)x, -fexp); }
-};
-
 // Per group (complex, direction tile): sum its slots (or read its dsum row),
 // scan along the thresholds (cumulative sum of Algorithm 1,
 // out[b][p][q] = sum_{j <= q} D[p][j]) and write the 64 x T block of out.
-// 16 row chunks x 64 lanes: each thread keeps its chunk in registers.
-template <typename ACC, int CH>
+// 16 row chunks x 64 lanes; each thread holds PC rows of its chunk in
+// registers at a time.  A chunk of at most PC rows (T <= 16 PC) takes one
+// pass; longer chunks first sum every row group (for the offsets) and then
+// scan piece by piece.
+constexpr int kReducePiece = 16;
+
+template <typename ACC>
 __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
+  constexpr int PC = kReducePiece;
   using O = OutOf<ACC>;
   using OT = typename O::T;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -890,51 +1008,79 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
   const int q0 = min(T, r * chunk), nq = min(T, q0 + chunk) - q0;
   int fexp = 0;
   if constexpr (sizeof(ACC) == 8) fexp = fixed_exp(p);
-
-  ACC acc[CH];
+  const int64_t slot_stride = (int64_t)T * W;
+  int64_t kfirst = 0, klast = -1;
+  group_slots(p, g, kfirst, klast);
+  if (kfirst == klast) return;  // one block covered the whole group and wrote its output
+  const bool active = r < 16 && nq > 0;
+  const bool from_dsum = p.split && klast - kfirst + 1 > kFusedSlots;
+  // v[j] = D[q + j] for j < n (rows past n repeat the last row and are dropped);
+  // loads use clamped rows so that all PC loads of a slot are independent
+  auto rows = [&](int q, int n, ACC* v) {
 #pragma unroll
-  for (int j = 0; j < CH; ++j) acc[j] = 0;
-  if (r < 16 && nq > 0) {
-    const int64_t slot_stride = (int64_t)T * W;
-    int64_t kfirst, klast;
-    group_slots(p, g, kfirst, klast);
-    // rows q0 .. q0+nq-1 of this thread; loads use clamped (in-range) rows and
-    // the surplus values are dropped, so all CH loads of a slot are independent
-    int rowoff[CH];
+    for (int j = 0; j < PC; ++j) v[j] = 0;
+    if (from_dsum) {
+      const ACC* src = (const ACC*)p.dsum + (int64_t)g * slot_stride + (int64_t)q * W + lane;
 #pragma unroll
-    for (int j = 0; j < CH; ++j) rowoff[j] = min(j, nq - 1) * W;
-    if (p.split && klast - kfirst + 1 > kFusedSlots) {
-      const ACC* src = (const ACC*)p.dsum + (int64_t)g * slot_stride + (int64_t)q0 * W + lane;
-#pragma unroll
-      for (int j = 0; j < CH; ++j) acc[j] = src[rowoff[j]];
+      for (int j = 0; j < PC; ++j) v[j] = src[min(j, n - 1) * W];
     } else {
       for (int64_t kk = kfirst; kk <= klast; ++kk) {
-        const ACC* src = (const ACC*)p.partial + (kk + g) * slot_stride + (int64_t)q0 * W + lane;
-        ACC v[CH];
+        const ACC* src = (const ACC*)p.partial + (kk + g) * slot_stride + (int64_t)q * W + lane;
+        ACC x[PC];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) v[j] = src[rowoff[j]];
+        for (int j = 0; j < PC; ++j) x[j] = src[min(j, n - 1) * W];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) acc[j] += v[j];
+        for (int j = 0; j < PC; ++j) v[j] += x[j];
       }
     }
 #pragma unroll
-    for (int j = 0; j < CH; ++j)
-      if (j >= nq) acc[j] = 0;
-  }
-  ACC run = 0;
+    for (int j = 0; j < PC; ++j)
+      if (j >= n) v[j] = 0;
+  };
+  ACC acc[PC];
+  if (chunk <= PC) {
+    // one pass: the whole chunk stays in registers
 #pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    run += acc[j];
-    acc[j] = run;
-  }
-  if (r < 16) tot[r * W + lane] = run;
-  __syncthreads();
-  ACC off = 0;
-  for (int rr = 0; rr < r && rr < 16; ++rr) off += tot[rr * W + lane];
-  if (r < 16) {
+    for (int j = 0; j < PC; ++j) acc[j] = 0;
+    if (active) rows(q0, nq, acc);
+    ACC run = 0;
 #pragma unroll
-    for (int j = 0; j < CH; ++j)
-      if (j < nq) L[lane * LS + q0 + j] = O::conv(acc[j] + off, fexp);
+    for (int j = 0; j < PC; ++j) {
+      run += acc[j];
+      acc[j] = run;
+    }
+    if (r < 16) tot[r * W + lane] = run;
+    __syncthreads();
+    ACC off = 0;
+    for (int rr = 0; rr < r && rr < 16; ++rr) off += tot[rr * W + lane];
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j)
+        if (j < nq) L[lane * LS + q0 + j] = O::conv(acc[j] + off, fexp);
+    }
+  } else {
+    // two passes: chunk totals, then the scan piece by piece
+    ACC run = 0;
+    if (active)
+      for (int q = 0; q < nq; q += PC) {
+        rows(q0 + q, min(PC, nq - q), acc);
+#pragma unroll
+        for (int j = 0; j < PC; ++j) run += acc[j];
+      }
+    if (r < 16) tot[r * W + lane] = run;
+    __syncthreads();
+    ACC carry = 0;
+    for (int rr = 0; rr < r && rr < 16; ++rr) carry += tot[rr * W + lane];
+    if (active)
+      for (int q = 0; q < nq; q += PC) {
+        const int n = min(PC, nq - q);
+        rows(q0 + q, n, acc);
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+          carry += acc[j];
+          if (j < n) L[lane * LS + q0 + q + j] = O::conv(carry, fexp);
+        }
+      }
   }
   __syncthreads();
   const int dv = min(W, p.d - t * W);
@@ -1237,6 +1383,152 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// ECF of an image / volume: the intensity is the vertex filter
+// ---------------------------------------------------------------------------
+//
+// Every included pixel/voxel is a vertex and every axis-aligned edge, square
+// and cube whose corners are all vertices is a cell that enters the filtration
+// at the largest corner intensity.  Give each cell to its largest corner in
+// the order (intensity, linear index): that corner is unique, and the cell's
+// value is that corner's intensity.  Voxel v then contributes, at its own
+// intensity, the signed sum over the cells it owns: itself, the edges towards
+// neighbours it beats, the squares and cubes all of whose other corners it
+// beats.  All of them lie in its 3^N neighbourhood.  With uint8 intensities the
+// histogram runs over the 256 intensity values, whatever the thresholds.
+
+constexpr int kEcfBins = 256;
+
+// Whether offset (d0, d1, d2) precedes the centre in linear order (axis 0 fastest).
+__device__ __forceinline__ constexpr bool precedes(int d0, int d1, int d2) {
+  return d2 < 0 || (d2 == 0 && (d1 < 0 || (d1 == 0 && d0 < 0)));
+}
+
+// Signed sum over the cells that voxel v owns (0 if v is not a vertex); the
+// caller adds it at intensity x.
+template <int N, int WM>
+__device__ __forceinline__ int ecf_owned(const uint8_t* vol, int n0, int n1, int n2, uint32_t v, int inc, int& x) {
+  // neighbour (d0, d1, d2) has bit (d0+1) + 3 (d1+1) + 9 (d2+1) (d2 = 0 in 2D)
+  auto bit = [](int d0, int d1, int d2) { return (d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0); };
+  const uint32_t r = v / (uint32_t)n0;
+  const int i0 = (int)(v - r * (uint32_t)n0);
+  const uint32_t i2u = r / (uint32_t)n1;
+  const int i1 = (int)(r - i2u * (uint32_t)n1);
+  const int i2 = (int)i2u;
+  x = vol[v];
+  if (x <= inc) return 0;
+  // bit set: that neighbour is a vertex and v beats it in (intensity, linear index)
+  uint32_t ok = 0;
+#pragma unroll
+  for (int d2 = (N == 3 ? -1 : 0); d2 <= (N == 3 ? 1 : 0); ++d2)
+#pragma unroll
+    for (int d1 = -1; d1 <= 1; ++d1)
+#pragma unroll
+      for (int d0 = -1; d0 <= 1; ++d0) {
+        if (d0 == 0 && d1 == 0 && d2 == 0) continue;
+        const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
+        if (j0 < 0 || j0 >= n0 || j1 < 0 || j1 >= n1 || j2 < 0 || j2 >= n2) continue;
+        const int u = vol[(int)v + d0 + d1 * n0 + d2 * n0 * n1];
+        const bool beats = precedes(d0, d1, d2) ? x >= u : x > u;
+        if (u > inc && beats) ok |= 1u << bit(d0, d1, d2);
+      }
+  auto has = [&](int d0, int d1, int d2) { return (int)((ok >> bit(d0, d1, d2)) & 1u); };
+  int c = 1;  // the vertex itself
+#pragma unroll
+  for (int s = -1; s <= 1; s += 2) {
+    c -= has(s, 0, 0) + has(0, s, 0);  // edges
+    if constexpr (N == 3) c -= has(0, 0, s);
+  }
+#pragma unroll
+  for (int sa = -1; sa <= 1; sa += 2)
+#pragma unroll
+    for (int sb = -1; sb <= 1; sb += 2) {
+      c += has(sa, 0, 0) & has(0, sb, 0) & has(sa, sb, 0);  // squares, plane 0-1
+      if constexpr (N == 3) {
+        c += has(sa, 0, 0) & has(0, 0, sb) & has(sa, 0, sb);  // plane 0-2
+        c += has(0, sa, 0) & has(0, 0, sb) & has(0, sa, sb);  // plane 1-2
+      }
+    }
+  if constexpr (N == 3) {
+#pragma unroll
+    for (int s0 = -1; s0 <= 1; s0 += 2)
+#pragma unroll
+      for (int s1 = -1; s1 <= 1; s1 += 2)
+#pragma unroll
+        for (int s2 = -1; s2 <= 1; s2 += 2)
+          c -= has(s0, 0, 0) & has(0, s1, 0) & has(0, 0, s2) & has(s0, s1, 0) & has(s0, 0, s2) & has(0, s1, s2) &
+               has(s0, s1, s2);  // cubes
+  }
+  return WM == WM_VMAX ? c * x : c;
+}
+
+// Histogram of the owned signed sums over the intensity values, per block and
+// per image: the voxel stream of the batch is cut into G equal ranges (block k
+// takes [kS/G, (k+1)S/G)), and block k writes the 256 sums of image b into
+// partial slot k + b.  Each wavefront adds into its own LDS histogram.
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_image_ecf(Params p) {
+  __shared__ int32_t H[16][kEcfBins];
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < nw * kEcfBins; i += blockDim.x) H[i / kEcfBins][i % kEcfBins] = 0;
+  __syncthreads();
+  const int k = blockIdx.x;
+  int64_t pos = block_start(k, p.S, p.G);
+  const int64_t end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return;
+  int b = find_complex(p, pos, 1);
+  while (pos < end) {
+    const int64_t gb = cum_elems(p, b), ge = cum_elems(p, b + 1);
+    if (ge <= pos) { ++b; continue; }
+    const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = N == 3 ? p.shape[3 * b + 2] : 1;
+    const uint8_t* vol = p.intensity + gb;
+    const int64_t lo = pos - gb, hi = mn64(ge, end) - gb;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+      int x;
+      const int c = ecf_owned<N, WM>(vol, n0, n1, n2, (uint32_t)v, p.include_above, x);
+      if (c != 0) atomicAdd(&H[wave][x], c);
+    }
+    __syncthreads();
+    int32_t* dst = (int32_t*)p.partial + ((int64_t)k + b) * kEcfBins;
+    for (int j = threadIdx.x; j < kEcfBins; j += blockDim.x) {
+      int32_t sum = 0;
+      for (int w = 0; w < nw; ++w) {
+        sum += H[w][j];
+        H[w][j] = 0;
+      }
+      dst[j] = sum;
+    }
+    __syncthreads();
+    pos = gb + hi;
+    if (gb + hi == ge) ++b;
+  }
+}
+
+// Per image: sum its slots, scan over the intensity values (CH[i] = sum of the
+// contributions at intensities <= i) and read out every threshold: a cell of
+// integer value x enters at thr[q] iff x <= floor(thr[q]).
+__global__ __launch_bounds__(256) void k_image_ecf_finish(Params p) {
+  __shared__ int32_t CH[kEcfBins];
+  const int b = blockIdx.x, j = threadIdx.x;
+  int64_t kfirst, klast;
+  group_slots(p, b, kfirst, klast);
+  int32_t s = 0;
+  for (int64_t kk = kfirst; kk <= klast; ++kk) s += ((const int32_t*)p.partial)[(kk + b) * kEcfBins + j];
+  CH[j] = s;
+  __syncthreads();
+  for (int o = 1; o < kEcfBins; o <<= 1) {
+    const int32_t add = j >= o ? CH[j - o] : 0;
+    __syncthreads();
+    CH[j] += add;
+    __syncthreads();
+  }
+  int32_t* out = (int32_t*)p.out + (int64_t)b * p.T;
+  for (int q = j; q < p.T; q += blockDim.x) {
+    const float t = p.thr[q];
+    out[q] = t >= 0.0f ? CH[t >= 255.0f ? 255 : (int)floorf(t)] : 0;  // NaN and negative: no cell
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1302,7 +1594,7 @@ hipError_t launch_forward_main(const Params& p, int block, size_t lds, hipStream
   }
 }
 
-template <typename ACC, int CH>
+template <typename ACC>
 static hipError_t launch_reduce_t(const Params& p, hipStream_t s) {
   const int groups = p.B * p.ntiles;
   if (p.split) {
@@ -1310,15 +1602,15 @@ static hipError_t launch_reduce_t(const Params& p, hipStream_t s) {
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   }
   const size_t lds = reduce_lds_bytes(p.T);
-  if (hipError_t e = set_lds_limit(k_reduce_scan<ACC, CH>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_reduce_scan<ACC, CH>), dim3(groups), dim3(1024), lds, s, p);
+  if (hipError_t e = set_lds_limit(k_reduce_scan<ACC>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_reduce_scan<ACC>), dim3(groups), dim3(1024), lds, s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_reduce(const Params& p, hipStream_t s) {
+  if (p.group_mode) return hipSuccess;  // every block wrote its group's output
   const bool wide = p.kind == 0 && p.dtype == 1;
-  if (p.T <= 256) return wide ? launch_reduce_t<uint64_t, 16>(p, s) : launch_reduce_t<uint32_t, 16>(p, s);
-  return wide ? launch_reduce_t<uint64_t, 48>(p, s) : launch_reduce_t<uint32_t, 48>(p, s);
+  return wide ? launch_reduce_t<uint64_t>(p, s) : launch_reduce_t<uint32_t>(p, s);
 }
 
 hipError_t launch_absmax(const Params& p, hipStream_t s) {
@@ -1347,6 +1639,22 @@ hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, ptr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s) {
+  if (p.S > 0) {
+    const bool vm = p.wmode == WM_VMAX;
+    if (p.n == 2) {
+      if (vm) hipLaunchKernelGGL((k_image_ecf<2, WM_VMAX>), dim3(p.G), dim3(block), 0, s, p);
+      else hipLaunchKernelGGL((k_image_ecf<2, WM_ONES>), dim3(p.G), dim3(block), 0, s, p);
+    } else {
+      if (vm) hipLaunchKernelGGL((k_image_ecf<3, WM_VMAX>), dim3(p.G), dim3(block), 0, s, p);
+      else hipLaunchKernelGGL((k_image_ecf<3, WM_ONES>), dim3(p.G), dim3(block), 0, s, p);
+    }
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_image_ecf_finish, dim3(p.B), dim3(kEcfBins), 0, s, p);
   return hipGetLastError();
 }
 

@@ -2,13 +2,14 @@
 
 For one request (a complex batch and a sampling grid) it times the forward for a
 set of launch shapes (threads per block, blocks per compute unit, minimum stream
-items per block) and keeps the fastest.  Results are cached in a JSON file
+items per block, work decomposition) and keeps the fastest.  Results are cached in a JSON file
 keyed by a signature of the request (kind, ambient dimension, batch size,
 total cells rounded to a power of two, directions, thresholds, dtype), so a
 workload of the same shape reuses the choice.
 
 The direction tile is fixed at one wavefront (64 directions, one per lane) and
-the histograms always live in LDS, so the shape knobs are the only ones.
+the histograms always live in LDS, so the shape knobs (and the choice between
+the stream decomposition and one block per group) are the only ones.
 
     from paper_2511_03909_amd import tune
     shape = tune.tune(cx, grid)        # times, caches, applies
@@ -28,11 +29,13 @@ from . import api
 
 DEFAULT_CACHE = os.environ.get("WECT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "wect_tune.json"))
 
-CANDIDATES: Tuple[Tuple[int, int, int], ...] = (
-    (1024, 0, 0), (1024, 1, 0), (1024, 2, 0),
-    (512, 0, 0), (512, 2, 0), (512, 4, 0),
-    (256, 0, 0), (256, 4, 0),
-    (512, 0, 256), (1024, 0, 256), (512, 0, 8192),
+# (block, blocks_per_cu, min_items_per_block, decomposition)
+CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = (
+    (1024, 0, 0, 1), (1024, 1, 0, 1), (1024, 2, 0, 1),
+    (512, 0, 0, 1), (512, 2, 0, 1), (512, 4, 0, 1),
+    (256, 0, 0, 1), (256, 4, 0, 1),
+    (512, 0, 256, 1), (1024, 0, 256, 1), (512, 0, 8192, 1),
+    (1024, 0, 0, 2), (512, 0, 0, 2), (256, 0, 0, 2),
 )
 
 
@@ -65,7 +68,8 @@ def _save(path: str, data: Dict[str, dict]) -> None:
 
 def apply(shape: Optional[dict]) -> None:
     if shape:
-        api.set_launch(shape["block"], shape["blocks_per_cu"], shape["min_items_per_block"])
+        api.set_launch(shape["block"], shape["blocks_per_cu"], shape["min_items_per_block"],
+                       shape.get("decomposition", 0))
     else:
         api.set_launch()
 
@@ -87,23 +91,24 @@ def _time_forward(cx, grid, reps: int) -> float:
     return (time.perf_counter() - t0) / reps
 
 
-def tune(cx, grid, candidates: Iterable[Tuple[int, int, int]] = CANDIDATES, reps: Optional[int] = None,
+def tune(cx, grid, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES, reps: Optional[int] = None,
          cache: Optional[str] = DEFAULT_CACHE, apply_best: bool = True) -> dict:
     """Time every candidate shape, cache and (by default) apply the fastest."""
     before = api.get_launch()
     results = []
     try:
-        for block, bpc, mi in candidates:
-            api.set_launch(block, bpc, mi)
+        for block, bpc, mi, dec in candidates:
+            api.set_launch(block, bpc, mi, dec)
             t1 = _time_forward(cx, grid, 1)
             r = reps or max(2, min(50, int(0.05 / max(t1, 1e-6))))
-            results.append((_time_forward(cx, grid, r), block, bpc, mi))
+            results.append((_time_forward(cx, grid, r), block, bpc, mi, dec))
     finally:
-        api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"])
-    t, block, bpc, mi = min(results)
-    best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "ms": t * 1e3,
-            "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "ms": s * 1e3}
-                      for s, b, c, m in results]}
+        api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"],
+                       before["decomposition"])
+    t, block, bpc, mi, dec = min(results)
+    best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "decomposition": dec, "ms": t * 1e3,
+            "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "decomposition": e, "ms": s * 1e3}
+                      for s, b, c, m, e in results]}
     if cache:
         data = _load(cache)
         data[signature(cx, grid)] = best

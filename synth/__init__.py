@@ -441,6 +441,22 @@ def hollow_shell(n: int = 6) -> Cubical:
     return Cubical(I, [ax, ax, ax], include_above=0, weighted=False)
 
 
+def uniform_image(shape_xyz, seed: int = 0, weighted: bool = False, include_above: int = -1) -> Cubical:
+    """Image / volume with intensities drawn uniformly from 0..255 (uint8):
+    the input of the paper's ECF-of-an-image throughput measurement (Section
+    "Experiments": 2048^2 to 8192^2 images, 128^3 to 512^3 volumes).  Item
+    ``seed`` of config 6; every pixel is a vertex unless include_above says
+    otherwise."""
+    g = rng(6, seed, STREAM_FIELD)
+    I = g.integers(0, 256, size=tuple(shape_xyz[::-1]), dtype=np.uint8)
+    return Cubical(I, [cubical_axis(s) for s in shape_xyz], include_above=include_above, weighted=weighted)
+
+
+def ecf_thresholds(T: int) -> np.ndarray:
+    """T float32 thresholds evenly over the uint8 intensity range [0, 255]."""
+    return np.linspace(0.0, 255.0, T).astype(np.float32)
+
+
 def random_tiny_cubical(seed: int, shape_xyz=(5, 4), include_above: int = 80,
                         weighted: bool = True) -> Cubical:
     g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(ROOT_SEED, spawn_key=(98, seed, 0))))

@@ -155,11 +155,31 @@ def test_launch_shape_roundtrip(lib):
     before = L.WectLaunch()
     assert lib.wect_get_launch(ctypes.byref(before)) == L.WECT_OK
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(300, 1, 0, 0))) == L.WECT_ERR_ARG
-    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 0))) == L.WECT_OK
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 3))) == L.WECT_ERR_ARG
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, -1))) == L.WECT_ERR_ARG
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2))) == L.WECT_OK
     now = L.WectLaunch()
     lib.wect_get_launch(ctypes.byref(now))
-    assert (now.block, now.blocks_per_cu, now.min_items_per_block) == (512, 2, 1024)
+    assert (now.block, now.blocks_per_cu, now.min_items_per_block, now.decomposition) == (512, 2, 1024, 2)
     assert lib.wect_set_launch(ctypes.byref(before)) == L.WECT_OK
+
+
+def test_group_decomposition_needs_no_partial_slots(lib):
+    """One block per group writes the output directly: integer requests then
+    need no workspace at all (float ones keep the small max-|w| area)."""
+    before = L.WectLaunch()
+    lib.wect_get_launch(ctypes.byref(before))
+    c, g = _simplicial(), _grid(d=100, T=64)
+    try:
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 0, 0, 1))) == L.WECT_OK
+        assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0) > 0
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 0, 0, 2))) == L.WECT_OK
+        assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0) == 0
+        f = _simplicial(wmode=L.WECT_W_VERTEX_MAX, dtype=L.WECT_F32)
+        f.weights[0] = FAKE
+        assert 0 < lib.wect_workspace_bytes(ctypes.byref(f), ctypes.byref(g), 0) <= 4096
+    finally:
+        lib.wect_set_launch(ctypes.byref(before))
 
 
 def test_workspace_grows_with_batch(lib):
@@ -167,3 +187,45 @@ def test_workspace_grows_with_batch(lib):
     a = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
     assert a % (64 * 64 * 4) == 0  # whole [T][64] slots
     assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(L.WectGrid(FAKE, 100, 100000, FAKE)), 0) == 0
+
+
+def test_binding_rejects_mismatched_buffers():
+    """The kernels write out/grads and read grad_out at the sizes the request
+    implies: the binding refuses buffers that do not match before any call
+    that could launch (CPU tensors here; nothing reaches a kernel)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2511_03909_amd import api as W
+    C = synth.random_tiny_cubical(0, (5, 4), include_above=80)
+    cx = W.CubicalBatch.from_host([C], device="cpu")
+    g = W.Grid(synth.s1_directions(8), synth.uniform_thresholds(6, 1.5), device="cpu")
+    with pytest.raises(ValueError):
+        W.wect_forward(cx, g, out=torch.empty((1, 8, 6), dtype=torch.float32))    # wrong dtype
+    with pytest.raises(ValueError):
+        W.wect_forward(cx, g, out=torch.empty((1, 8, 5), dtype=torch.int32))      # wrong shape
+    with pytest.raises(ValueError):
+        W.wect_forward(cx, g, out=torch.empty((1, 6, 8), dtype=torch.int32).transpose(1, 2))  # not contiguous
+    K = synth.random_tiny_complex(1, n=2, nv=7, top_dim=2, wmode="vertex_max", wdtype=np.float32)
+    sx = W.SimplicialBatch.from_host([K], device="cpu")
+    with pytest.raises(ValueError):
+        W.wect_backward(sx, g, torch.zeros((1, 8, 7)))                            # grad_out shape
+    with pytest.raises(ValueError):
+        W.wect_batched(sx, g, torch.zeros((1, 8, 6)), grads=torch.zeros(3))        # grads size
+
+
+def test_cubical_batch_needs_one_inclusion_level():
+    import numpy as np
+
+    import synth
+    from paper_2511_03909_amd import api as W
+    a = synth.uniform_image((4, 3), 0, include_above=-1)
+    b = synth.uniform_image((4, 3), 1, include_above=10)
+    with pytest.raises(ValueError):
+        W.CubicalBatch.from_host([a, b], device="cpu")
+    c = synth.uniform_image((4, 3), 2, weighted=True)
+    with pytest.raises(ValueError):
+        W.CubicalBatch.from_host([a, c], device="cpu")
+    assert W.CubicalBatch.from_host([a, synth.uniform_image((2, 5), 3)], device="cpu").B == 2
+    del np

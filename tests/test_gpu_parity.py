@@ -312,7 +312,6 @@ def test_batched_equals_singles(W):
 
 
 def test_launch_shapes_give_identical_integers(W):
-    w = synth.cfg1()
     K = with_weights(synth.cfg3(n=12).complexes[0], "int")
     dirs, thr = synth.fibonacci_directions(100), synth.uniform_thresholds(77, 1.8)
     ref = None
@@ -320,16 +319,74 @@ def test_launch_shapes_give_identical_integers(W):
         for block in (256, 512, 1024):
             for bpc in (1, 2):
                 for mi in (64, 4096):
-                    _say(f"launch block={block} bpc={bpc} min_items={mi}")
-                    W.set_launch(block, bpc, mi)
-                    got = gpu_wect(W, [K], dirs, thr)
-                    if ref is None:
-                        ref = got
-                        assert_match(got[0], oracle.wect(K, dirs, thr), K, "launch ref")
-                    assert np.array_equal(got, ref)
+                    for dec in (W.DECOMP_STREAM, W.DECOMP_GROUP):
+                        _say(f"launch block={block} bpc={bpc} min_items={mi} decomposition={dec}")
+                        W.set_launch(block, bpc, mi, dec)
+                        got = gpu_wect(W, [K], dirs, thr)
+                        if ref is None:
+                            ref = got
+                            assert_match(got[0], oracle.wect(K, dirs, thr), K, "launch ref")
+                        assert np.array_equal(got, ref)
     finally:
         W.set_launch()
-    del w
+
+
+def _uneven_batches():
+    ims = [synth.random_tiny_cubical(s, shp, include_above=80) for s, shp in
+           enumerate(((12, 9), (3, 17), (20, 1), (7, 7), (16, 11), (9, 30), (2, 2), (25, 13)))]
+    ims.insert(3, synth.Cubical(np.zeros((5, 6), np.uint8), [synth.cubical_axis(6), synth.cubical_axis(5)], 80, True))
+    Ks = [synth.random_tiny_complex(s, n=2, nv=6 + 3 * s, top_dim=2, wmode="explicit", wdtype=np.int32)
+          for s in range(9)]
+    Ks.insert(4, synth.Simplicial(np.zeros((0, 2), np.float32), [None, np.zeros((0, 2), np.int32),
+                                                                 np.zeros((0, 3), np.int32)],
+                                  "explicit", [np.zeros(0, np.int32)] * 3))
+    return ims, Ks
+
+
+@pytest.mark.parametrize("block,mi,dec", [(256, 64, 1), (256, 100000, 1), (1024, 100000, 1), (512, 0, 2),
+                                          (1024, 0, 2), (256, 0, 2)])
+def test_stream_and_group_decompositions(W, block, mi, dec):
+    """Stream ranges that cover several whole groups (written by the block
+    itself) next to groups split over blocks (partial histograms + reduction),
+    and one block per group; batches with an empty member, ragged tiles."""
+    ims, Ks = _uneven_batches()
+    dirs, thr = synth.s1_directions(70), synth.uniform_thresholds(37, 1.7)
+    try:
+        W.set_launch(block, 0, mi, dec)
+        _say(f"decomposition={dec} block={block} min_items={mi}: cubical")
+        got = gpu_wect(W, ims, dirs, thr)
+        for b, C in enumerate(ims):
+            assert_match(got[b], oracle.wect(C, dirs, thr), C, f"image {b}")
+        _say(f"decomposition={dec} block={block} min_items={mi}: simplicial")
+        got = gpu_wect(W, Ks, dirs, thr)
+        for b, K in enumerate(Ks):
+            assert_match(got[b], oracle.wect(K, dirs, thr), K, f"complex {b}")
+        _say(f"decomposition={dec} block={block} min_items={mi}: float weights")
+        w = synth.cfg5(n_complexes=5, vmin=300, vmax=2000)
+        Kf = w.complexes
+        got = gpu_wect(W, Kf, w.dirs, w.thr)
+        W.set_launch()
+        ref = gpu_wect(W, Kf, w.dirs, w.thr)
+        assert np.array_equal(got, ref)  # fixed point: the decomposition does not change the bits
+        for b, K in enumerate(Kf[:2]):
+            assert_match(got[b], oracle.wect(K, w.dirs, w.thr), K, f"float complex {b}")
+        # T a multiple of 4 (vector stores of the directly written groups), into
+        # an aligned buffer and into one offset by one element
+        W.set_launch(block, 0, mi, dec)
+        thr36 = synth.uniform_thresholds(36, 1.7)
+        cx = W.CubicalBatch.from_host(ims)
+        g = W.Grid(dirs, thr36)
+        n = cx.B * g.d * g.T
+        flat = torch.full((n + 1,), -7, dtype=torch.int32, device="cuda")
+        for off in (0, 1):
+            _say(f"decomposition={dec} block={block} min_items={mi}: T=36, out offset {off}")
+            view = flat[off:off + n].view(cx.B, g.d, g.T)
+            W.wect_forward(cx, g, out=view)
+            got = view.cpu().numpy()
+            for b, C in enumerate(ims):
+                assert_match(got[b], oracle.wect(C, dirs, thr36), C, f"T=36 image {b}")
+    finally:
+        W.set_launch()
 
 
 def test_float_results_independent_of_launch_shape(W):
@@ -436,9 +493,10 @@ def test_autotuner_caches_and_keeps_results(W, tmp_path):
     ref = W.wect_forward(cx, g).cpu().numpy()
     cache = str(tmp_path / "tune.json")
     try:
-        best = tune.tune(cx, g, candidates=((512, 0, 0), (1024, 1, 0), (256, 4, 64)), reps=3, cache=cache)
+        best = tune.tune(cx, g, candidates=((512, 0, 0, 1), (1024, 1, 0, 1), (256, 4, 64, 1), (512, 0, 0, 2)),
+                         reps=3, cache=cache)
         assert tune.lookup(cx, g, cache) is not None
-        assert best["block"] in (256, 512, 1024) and len(best["tried"]) == 3
+        assert best["block"] in (256, 512, 1024) and len(best["tried"]) == 4
         assert np.array_equal(W.wect_forward(cx, g).cpu().numpy(), ref)
     finally:
         W.set_launch()
@@ -446,7 +504,7 @@ def test_autotuner_caches_and_keeps_results(W, tmp_path):
 
 @pytest.mark.parametrize("T", [255, 256, 257, 300, 500])
 def test_many_thresholds(W, T):
-    """T above 256 takes the wide scan (48 rows per thread chunk) and smaller staging tiles."""
+    """T above 256 takes the two-pass scan (row-group totals, then the scan) and smaller staging tiles."""
     _say(f"many thresholds T={T}")
     Ki = synth.random_tiny_complex(11, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.int32)
     Kf = synth.random_tiny_complex(11, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.float32)

@@ -401,6 +401,12 @@ def test_image_ecf_views_equal_explicit_cells(seed):
     assert np.array_equal(oracle.image_ecf(C, thr), oracle.image_ecf_cells(C, thr))
 
 
+def test_image_ecf_nan_threshold_admits_no_cell():
+    C = synth.uniform_image((6, 5), 2)
+    out = oracle.image_ecf(C, np.array([np.nan, 255.0], dtype=np.float32))
+    assert out.tolist() == [0, 1]
+
+
 def test_image_ecf_closed_forms():
     """Above the largest intensity the ECF is chi of the whole image (a solid
     rectangle or box: 1); below the smallest it is 0."""
