@@ -1404,34 +1404,48 @@ __device__ __forceinline__ constexpr bool precedes(int d0, int d1, int d2) {
   return d2 < 0 || (d2 == 0 && (d1 < 0 || (d1 == 0 && d0 < 0)));
 }
 
-// Signed sum over the cells that voxel v owns (0 if v is not a vertex); the
-// caller adds it at intensity x.
+// The 3^N intensities around voxel (i0, i1, i2), neighbour (d0, d1, d2) at
+// index (d0+1) + 3 (d1+1) + 9 (d2+1).  Coordinates are clamped into the grid,
+// so every load is in bounds; the evaluation masks the clamped ones out.
+template <int N>
+struct EcfNbhd {
+  static constexpr int M = N == 2 ? 9 : 27;
+  int u[M];
+
+  __device__ __forceinline__ void load(const uint8_t* vol, int n0, int n1, int n2, int i0, int i1, int i2) {
+    const uint32_t col[3] = {(uint32_t)max(i0 - 1, 0), (uint32_t)i0, (uint32_t)min(i0 + 1, n0 - 1)};
+    const int row[3] = {max(i1 - 1, 0), i1, min(i1 + 1, n1 - 1)};
+    const int lay[3] = {max(i2 - 1, 0), i2, min(i2 + 1, n2 - 1)};
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int d0 = m % 3, d1 = (m / 3) % 3, d2 = N == 3 ? m / 9 : 1;
+      u[m] = vol[(uint32_t)(lay[d2] * n1 + row[d1]) * (uint32_t)n0 + col[d0]];
+    }
+  }
+};
+
+// Signed sum over the cells that voxel (i0, i1, i2) owns (0 if it is not a
+// vertex); the caller adds it at intensity x = its own intensity.
 template <int N, int WM>
-__device__ __forceinline__ int ecf_owned(const uint8_t* vol, int n0, int n1, int n2, uint32_t v, int inc, int& x) {
+__device__ __forceinline__ int ecf_owned(const EcfNbhd<N>& nb, int n0, int n1, int n2, int i0, int i1, int i2,
+                                         int inc, int& x) {
   // neighbour (d0, d1, d2) has bit (d0+1) + 3 (d1+1) + 9 (d2+1) (d2 = 0 in 2D)
   auto bit = [](int d0, int d1, int d2) { return (d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0); };
-  const uint32_t r = v / (uint32_t)n0;
-  const int i0 = (int)(v - r * (uint32_t)n0);
-  const uint32_t i2u = r / (uint32_t)n1;
-  const int i1 = (int)(r - i2u * (uint32_t)n1);
-  const int i2 = (int)i2u;
-  x = vol[v];
-  if (x <= inc) return 0;
+  constexpr int M = EcfNbhd<N>::M;
+  x = nb.u[(M - 1) / 2];
   // bit set: that neighbour is a vertex and v beats it in (intensity, linear index)
+  const bool lo0 = i0 > 0, hi0 = i0 < n0 - 1, lo1 = i1 > 0, hi1 = i1 < n1 - 1, lo2 = i2 > 0, hi2 = i2 < n2 - 1;
   uint32_t ok = 0;
 #pragma unroll
-  for (int d2 = (N == 3 ? -1 : 0); d2 <= (N == 3 ? 1 : 0); ++d2)
-#pragma unroll
-    for (int d1 = -1; d1 <= 1; ++d1)
-#pragma unroll
-      for (int d0 = -1; d0 <= 1; ++d0) {
-        if (d0 == 0 && d1 == 0 && d2 == 0) continue;
-        const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
-        if (j0 < 0 || j0 >= n0 || j1 < 0 || j1 >= n1 || j2 < 0 || j2 >= n2) continue;
-        const int u = vol[(int)v + d0 + d1 * n0 + d2 * n0 * n1];
-        const bool beats = precedes(d0, d1, d2) ? x >= u : x > u;
-        if (u > inc && beats) ok |= 1u << bit(d0, d1, d2);
-      }
+  for (int m = 0; m < M; ++m) {
+    const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
+    if (d0 == 0 && d1 == 0 && d2 == 0) continue;
+    const bool in = (d0 < 0 ? lo0 : d0 > 0 ? hi0 : true) && (d1 < 0 ? lo1 : d1 > 0 ? hi1 : true) &&
+                    (d2 < 0 ? lo2 : d2 > 0 ? hi2 : true);
+    const int u = nb.u[m];
+    const bool beats = precedes(d0, d1, d2) ? x >= u : x > u;
+    ok |= (uint32_t)(in && u > inc && beats) << bit(d0, d1, d2);
+  }
   auto has = [&](int d0, int d1, int d2) { return (int)((ok >> bit(d0, d1, d2)) & 1u); };
   int c = 1;  // the vertex itself
 #pragma unroll
@@ -1459,6 +1473,7 @@ __device__ __forceinline__ int ecf_owned(const uint8_t* vol, int n0, int n1, int
           c -= has(s0, 0, 0) & has(0, s1, 0) & has(0, 0, s2) & has(s0, s1, 0) & has(s0, 0, s2) & has(0, s1, s2) &
                has(s0, s1, s2);  // cubes
   }
+  if (x <= inc) c = 0;  // not a vertex
   return WM == WM_VMAX ? c * x : c;
 }
 
@@ -1483,10 +1498,36 @@ __global__ __launch_bounds__(1024) void k_image_ecf(Params p) {
     const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = N == 3 ? p.shape[3 * b + 2] : 1;
     const uint8_t* vol = p.intensity + gb;
     const int64_t lo = pos - gb, hi = mn64(ge, end) - gb;
-    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+    // grid position of the thread's first voxel (voxel counts of one image are
+    // below 2^31, checked by wect_validate), then advanced by blockDim voxels
+    // per step without division
+    const uint32_t bd = blockDim.x;
+    const uint32_t s0 = bd % (uint32_t)n0, s1 = (bd / (uint32_t)n0) % (uint32_t)n1;
+    const uint32_t s2 = bd / ((uint32_t)n0 * (uint32_t)n1);
+    uint32_t v = (uint32_t)(lo + threadIdx.x);
+    int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
+    int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
+    // the neighbourhood of the next voxel is loaded before the current one is
+    // evaluated (past the end of the range the current one is loaded again)
+    EcfNbhd<N> cur, nxt;
+    if (v < (uint32_t)hi) cur.load(vol, n0, n1, n2, i0, i1, i2);
+    for (; v < (uint32_t)hi; v += bd) {
+      int j0 = i0 + (int)s0;
+      int carry = j0 >= n0;
+      j0 -= carry ? n0 : 0;
+      int j1 = i1 + (int)s1 + carry;
+      carry = j1 >= n1;
+      j1 -= carry ? n1 : 0;
+      int j2 = i2 + (int)s2 + carry;
+      const bool more = v + bd < (uint32_t)hi;
+      nxt.load(vol, n0, n1, n2, more ? j0 : i0, more ? j1 : i1, more ? j2 : i2);
       int x;
-      const int c = ecf_owned<N, WM>(vol, n0, n1, n2, (uint32_t)v, p.include_above, x);
+      const int c = ecf_owned<N, WM>(cur, n0, n1, n2, i0, i1, i2, p.include_above, x);
       if (c != 0) atomicAdd(&H[wave][x], c);
+      cur = nxt;
+      i0 = j0;
+      i1 = j1;
+      i2 = j2;
     }
     __syncthreads();
     int32_t* dst = (int32_t*)p.partial + ((int64_t)k + b) * kEcfBins;
