@@ -192,11 +192,13 @@ wect_status wect_batched(const wect_complex* c, const wect_grid* g, void* out,
  *    out[b][q] = sum of (-1)^dim * weight over the cells of image b whose
  *    value is <= thr[q].  Integer sums wrap modulo 2^32 like int32.
  * ws:  wect_image_ecf_workspace_bytes(c) bytes of device memory (256-byte
- *    aligned, contents ignored); it does not depend on T.
+ *    aligned, contents ignored): one 256-entry accumulator per image, so it
+ *    does not depend on T.
  * Metadata errors return before anything is enqueued; data errors (shapes
  * inconsistent with grid_off or total_voxels) are reported by wect_validate
  * (with a grid of d = 0 directions).  Asynchronous on hip_stream and
- * capture-safe: two kernel launches, no allocation, no synchronisation.
+ * capture-safe: three kernel launches (clear, histogram, read-out), no
+ * allocation, no memset, no synchronisation.
  */
 size_t wect_image_ecf_workspace_bytes(const wect_complex* c);
 wect_status wect_image_ecf(const wect_complex* c, const float* thr, int32_t T, int32_t* out,

@@ -427,7 +427,7 @@ wect_status ecf_plan(const wect_complex* c, int32_t T, const float* thr, EcfPlan
   const int64_t G = std::max<int64_t>(1, std::min<int64_t>(2LL * cus, ceil_div(S, 8192)));
   p.S = S;
   p.G = (int)G;
-  pl->ws = align256((size_t)(G + c->B) * wect::kEcfSlotBytes);
+  pl->ws = align256((size_t)c->B * wect::kEcfRowBytes);
   return WECT_OK;
 }
 

@@ -62,7 +62,7 @@ hipError_t launch_validate(const Params& p, int* flags, hipStream_t s);
 // Image ECF: main kernel (p.G blocks of `block` threads, when p.S > 0) and the
 // per-image finish (p.B blocks).
 hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s);
-constexpr int kEcfSlotBytes = 256 * 4;  // one partial histogram over the intensity values
+constexpr int kEcfRowBytes = 256 * 4;  // one image's sums over the intensity values
 
 hipError_t launch_absmax(const Params& p, hipStream_t s);
 

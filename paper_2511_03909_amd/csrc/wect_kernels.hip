@@ -1477,10 +1477,11 @@ __device__ __forceinline__ int ecf_owned(const EcfNbhd<N>& nb, int n0, int n1, i
   return WM == WM_VMAX ? c * x : c;
 }
 
-// Histogram of the owned signed sums over the intensity values, per block and
-// per image: the voxel stream of the batch is cut into G equal ranges (block k
-// takes [kS/G, (k+1)S/G)), and block k writes the 256 sums of image b into
-// partial slot k + b.  Each wavefront adds into its own LDS histogram.
+// Histogram of the owned signed sums over the intensity values, per image: the
+// voxel stream of the batch is cut into G equal ranges (block k takes
+// [kS/G, (k+1)S/G)); each wavefront adds into its own LDS histogram, and at the
+// end of every image segment the block adds its 256 sums into the image's row
+// of acc [B][256] (zeroed beforehand) with integer atomics, which commute.
 template <int N, int WM>
 __global__ __launch_bounds__(1024) void k_image_ecf(Params p) {
   __shared__ int32_t H[16][kEcfBins];
@@ -1530,14 +1531,14 @@ __global__ __launch_bounds__(1024) void k_image_ecf(Params p) {
       i2 = j2;
     }
     __syncthreads();
-    int32_t* dst = (int32_t*)p.partial + ((int64_t)k + b) * kEcfBins;
+    int32_t* acc = (int32_t*)p.partial + (int64_t)b * kEcfBins;
     for (int j = threadIdx.x; j < kEcfBins; j += blockDim.x) {
       int32_t sum = 0;
       for (int w = 0; w < nw; ++w) {
         sum += H[w][j];
         H[w][j] = 0;
       }
-      dst[j] = sum;
+      if (sum != 0) atomicAdd(&acc[j], sum);
     }
     __syncthreads();
     pos = gb + hi;
@@ -1545,17 +1546,13 @@ __global__ __launch_bounds__(1024) void k_image_ecf(Params p) {
   }
 }
 
-// Per image: sum its slots, scan over the intensity values (CH[i] = sum of the
+// Per image: scan its 256 sums over the intensity values (CH[i] = sum of the
 // contributions at intensities <= i) and read out every threshold: a cell of
 // integer value x enters at thr[q] iff x <= floor(thr[q]).
 __global__ __launch_bounds__(256) void k_image_ecf_finish(Params p) {
   __shared__ int32_t CH[kEcfBins];
   const int b = blockIdx.x, j = threadIdx.x;
-  int64_t kfirst, klast;
-  group_slots(p, b, kfirst, klast);
-  int32_t s = 0;
-  for (int64_t kk = kfirst; kk <= klast; ++kk) s += ((const int32_t*)p.partial)[(kk + b) * kEcfBins + j];
-  CH[j] = s;
+  CH[j] = ((const int32_t*)p.partial)[(int64_t)b * kEcfBins + j];
   __syncthreads();
   for (int o = 1; o < kEcfBins; o <<= 1) {
     const int32_t add = j >= o ? CH[j - o] : 0;
@@ -1684,6 +1681,8 @@ hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s) {
+  // clear the [B][256] accumulator with a kernel (no memset node in a captured graph)
+  if (hipError_t e = launch_fill_zero((float*)p.partial, (int64_t)p.B * kEcfBins, s); e != hipSuccess) return e;
   if (p.S > 0) {
     const bool vm = p.wmode == WM_VMAX;
     if (p.n == 2) {
