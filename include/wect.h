@@ -175,6 +175,27 @@ wect_status wect_batched(const wect_complex* c, const wect_grid* g, void* out,
                          void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * WECF of general vertex filters on simplicial complexes (Section "Computation
+ * of WECFs": Algorithm 1 takes m filter values per vertex and returns the
+ * (m, T) tensor; the WECT is the case fvals = V D^T):
+ *   out[b][p][q] = sum over simplices s of complex b with
+ *                  max_{v in s} fvals[v][p] <= thr[q] of (-1)^dim(s) * w(s).
+ * c:     as for wect_forward with kind SIMPLICIAL (weights ONES / EXPLICIT /
+ *        VERTEX_MAX, CSR batch when B > 1); n and coords are not read.
+ * fvals: [sum V, m] float32 device array, row-major (row = vertex in batch
+ *        order, finite values).
+ * thr, T: as in wect_grid (non-decreasing, finite).
+ * out:   [B, m, T] int32 (integer weights) or float32 (float weights).
+ * ws:    wect_wecf_workspace_bytes(c, m, T) bytes.  Work is split like
+ *        wect_forward with the m columns in place of the d directions, 64 per
+ *        wavefront (m below 64 leaves lanes idle).  Errors, asynchrony and
+ *        capture safety as for wect_forward; no backward is provided.
+ */
+size_t wect_wecf_workspace_bytes(const wect_complex* c, int32_t m, int32_t T);
+wect_status wect_wecf_forward(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T,
+                              void* out, void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
  * ECF of images and volumes with the intensity as the vertex filter: the first
  * of the two ECFs of an image in the paper's Remark on them, i.e. the WECF of
  * Section "Computation of WECFs" for one vertex filter, f(v) = intensity(v).

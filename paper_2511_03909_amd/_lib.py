@@ -87,6 +87,11 @@ def lib() -> ctypes.CDLL:
     L.wect_version.restype = c_char_p
     L.wect_last_error.argtypes = []
     L.wect_last_error.restype = c_char_p
+    L.wect_wecf_workspace_bytes.argtypes = [P(WectComplex), c_int32, c_int32]
+    L.wect_wecf_workspace_bytes.restype = c_size_t
+    L.wect_wecf_forward.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
+                                    c_size_t, c_void_p]
+    L.wect_wecf_forward.restype = c_int
     L.wect_image_ecf_workspace_bytes.argtypes = [P(WectComplex)]
     L.wect_image_ecf_workspace_bytes.restype = c_size_t
     L.wect_image_ecf.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]

@@ -321,6 +321,38 @@ def wect_validate(cx, grid: Grid) -> None:
     L.check(L.lib().wect_validate(ctypes.byref(c), ctypes.byref(g), _stream(cx.device)), "wect_validate")
 
 
+def wecf_workspace_bytes(cx, m: int, T: int) -> int:
+    c = cx.struct()
+    return int(L.lib().wect_wecf_workspace_bytes(ctypes.byref(c), int(m), int(T)))
+
+
+def wecf_forward(cx, fvals, thr, out: Optional[torch.Tensor] = None,
+                 ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """WECF of m general vertex filters fvals [sum V, m] on a simplicial batch ->
+    [B, m, T] (int32 or float32 like wect_forward); see wect_wecf_forward."""
+    fvals = torch.as_tensor(fvals, dtype=torch.float32).to(cx.device).contiguous()
+    if fvals.dim() != 2 or fvals.shape[0] != cx.counts[0]:
+        raise ValueError(f"fvals must be [{cx.counts[0]}, m], got {tuple(fvals.shape)}")
+    thr = torch.as_tensor(thr, dtype=torch.float32).to(cx.device).contiguous()
+    m, T = int(fvals.shape[1]), int(thr.numel())
+    shape = (cx.B, m, T)
+    if out is None:
+        out = torch.empty(shape, dtype=_out_dtype(cx), device=cx.device)
+    else:
+        _check_tensor(out, "out", cx.device, _out_dtype(cx), shape)
+    need = wecf_workspace_bytes(cx, m, T)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
+    else:
+        _check_tensor(ws, "ws", cx.device)
+    c = cx.struct()
+    st = L.lib().wect_wecf_forward(ctypes.byref(c), _ptr(fvals), ctypes.c_int32(m), _ptr(thr), ctypes.c_int32(T),
+                                   _ptr(out), _ptr(ws), ctypes.c_size_t(int(ws.numel()) * ws.element_size()),
+                                   _stream(cx.device))
+    L.check(st, "wect_wecf_forward")
+    return out
+
+
 def image_ecf_workspace_bytes(cx) -> int:
     c = cx.struct()
     return int(L.lib().wect_image_ecf_workspace_bytes(ctypes.byref(c)))

@@ -390,6 +390,25 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
 // image ECF
 // ---------------------------------------------------------------------------
 
+// WECF of a general vertex filter on a simplicial complex: planned as a
+// forward over m columns whose heights are read from fvals [V, m] (n = 0 in
+// the kernels), so decomposition, staging and reduction are shared.
+wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T, Plan* pl) {
+  if (!c || c->kind != WECT_SIMPLICIAL || m < 0 || T < 0) return WECT_ERR_ARG;
+  if (m > 0 && c->count[0] > 0 && !fvals) return WECT_ERR_ARG;
+  if (c->count[0] > 0 && m > 0 && c->count[0] > INT64_MAX / m) return WECT_ERR_ARG;
+  wect_complex cc = *c;
+  cc.n = 1;                                        // coordinates are not read
+  cc.coords = fvals ? fvals : reinterpret_cast<const float*>(c);  // any non-null: not dereferenced
+  const wect_grid gg = {fvals ? fvals : cc.coords, m, T, thr};
+  if (wect_status st = make_plan(&cc, &gg, true, false, pl); st != WECT_OK) return st;
+  pl->p.n = 0;
+  pl->p.coords = nullptr;
+  pl->p.dirs = nullptr;
+  pl->p.fvals = fvals;
+  return WECT_OK;
+}
+
 struct EcfPlan {
   Params p;
   int block = 1024;
@@ -564,6 +583,20 @@ wect_status wect_profile_read(double* fwd_ms, int64_t* fwd_launches, double* bwd
     g_prof.clear();
   }
   return WECT_OK;
+}
+
+size_t wect_wecf_workspace_bytes(const wect_complex* c, int32_t m, int32_t T) {
+  Plan pl;
+  if (wecf_plan(c, reinterpret_cast<const float*>(c), m, reinterpret_cast<const float*>(c), T, &pl) != WECT_OK)
+    return 0;
+  return pl.ws_fwd;
+}
+
+wect_status wect_wecf_forward(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T,
+                              void* out, void* ws, size_t ws_bytes, void* hip_stream) {
+  Plan pl;
+  if (wect_status st = wecf_plan(c, fvals, m, thr, T, &pl); st != WECT_OK) return st;
+  return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
 }
 
 size_t wect_image_ecf_workspace_bytes(const wect_complex* c) {

@@ -15,6 +15,7 @@ struct Params {
   // complex
   int32_t kind, n, B, top_dim, wmode, dtype;
   const float* coords;
+  const float* fvals;    // n = 0: vertex filter values [V, d] row-major (WECF of a general filter)
   const int64_t* vert_off;
   int64_t count[4];
   const int32_t* simp[4];

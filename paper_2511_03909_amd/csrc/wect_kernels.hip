@@ -348,11 +348,14 @@ struct AccOf<float> {
   using T = uint64_t;
 };
 
+// N = 0 is the WECF of a general vertex filter: a staged vertex is then its
+// global row in fvals (one word) instead of its N coordinates.
 template <int N, int DIM, typename ACC>
 struct SimpLayout {
   static constexpr int NV = DIM + 1;
+  static constexpr int NC = N == 0 ? 1 : N;                   // words per staged vertex
   static constexpr int WW = sizeof(ACC) / 4;                 // words of the staged weight
-  static constexpr int WOFF = ((NV * N + WW - 1) / WW) * WW;  // weight slot, aligned to its size
+  static constexpr int WOFF = ((NV * NC + WW - 1) / WW) * WW;  // weight slot, aligned to its size
   static constexpr int OOFF = WOFF + WW;                     // owner slot (vertex-max backward)
   static constexpr int STRIDE = ((OOFF + 1 + 3) / 4) * 4;
   static_assert(STRIDE <= kMaxStride, "entry too large");
@@ -402,16 +405,20 @@ struct SimpStager {
       e[L::WOFF + 1] = bitcast<float>((uint32_t)(a >> 32));
     }
   }
-  // coordinates, signed weight and owner vertex of the simplex whose ids are in idx
+  // coordinates (or filter rows), signed weight and owner vertex of the simplex whose ids are in idx
   __device__ __forceinline__ void gather(const Params& p, int64_t row, int64_t voff, int fexp) {
 #pragma unroll
     for (int j = 0; j < L::NV; ++j) {
-      const float* c = p.coords + (voff + idx[j]) * N;
+      if constexpr (N == 0) {
+        e[j] = bitcast<float>((int32_t)(voff + idx[j]));  // global vertex row (< 2^31)
+      } else {
+        const float* c = p.coords + (voff + idx[j]) * N;
 #pragma unroll
-      for (int k = 0; k < N; ++k) e[j * N + k] = c[k];
+        for (int k = 0; k < N; ++k) e[j * N + k] = c[k];
+      }
     }
 #pragma unroll
-    for (int k = L::NV * N; k < L::WOFF; ++k) e[k] = 0.0f;
+    for (int k = L::NV * L::NC; k < L::WOFF; ++k) e[k] = 0.0f;
     e[L::OOFF] = 0.0f;
     if constexpr (WM == WM_ONES) {
       if constexpr (FWD) put_weight(ACC(1));
@@ -446,6 +453,16 @@ __device__ __forceinline__ ACC load_weight(const float* E) {
   else return *(const uint64_t*)E;
 }
 
+// Largest filter value of a staged simplex for the lane's filter column col
+// (fvals row-major [V, m]; the 64 lanes read 64 consecutive words of a row).
+template <int DIM>
+__device__ __forceinline__ float max_filter(const float* E, const float* fvals, int m, int col) {
+  float h = fvals[(int64_t)bitcast<int32_t>(E[0]) * m + col];
+#pragma unroll
+  for (int j = 1; j <= DIM; ++j) h = fmaxf(h, fvals[(int64_t)bitcast<int32_t>(E[j]) * m + col]);
+  return h;
+}
+
 // Maximum height of a staged simplex for the lane's direction.
 template <int N, int DIM>
 __device__ __forceinline__ float max_height(const float* E, float sx, float sy, float sz) {
@@ -461,7 +478,7 @@ __device__ __forceinline__ float max_height(const float* E, float sx, float sy, 
 // of the coordinate gather, which runs one tile ahead of the histogram.
 template <int N, int DIM, int WM, typename WT, bool FAST>
 __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
-                               float sx, float sy, float sz, typename AccOf<WT>::T* hist, float* stage,
+                               float sx, float sy, float sz, int fcol, typename AccOf<WT>::T* hist, float* stage,
                                const Thr& th, int fexp) {
   using ACC = typename AccOf<WT>::T;
   using L = SimpLayout<N, DIM, ACC>;
@@ -508,7 +525,8 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
     hist_entries<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
                             [&](int e, float& h, ACC& w) {
                               const float* E = stage + e * L::STRIDE;
-                              h = max_height<N, DIM>(E, sx, sy, sz);
+                              if constexpr (N == 0) h = max_filter<DIM>(E, p.fvals, p.d, fcol);
+                              else h = max_height<N, DIM>(E, sx, sy, sz);
                               w = load_weight<ACC>(E + L::WOFF);
                             });
   }
@@ -517,13 +535,13 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
 
 template <int N, int WM, typename WT, bool FAST>
 __device__ __forceinline__ void simp_fwd_dim(int dim, const Params& p, int64_t lo, int64_t hi, int64_t voff,
-                                             int64_t soff, float sx, float sy, float sz,
+                                             int64_t soff, float sx, float sy, float sz, int fcol,
                                              typename AccOf<WT>::T* hist, float* stage, const Thr& th, int fexp) {
   switch (dim) {
-    case 0: simp_fwd_range<N, 0, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
-    case 1: simp_fwd_range<N, 1, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
-    case 2: simp_fwd_range<N, 2, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
-    default: simp_fwd_range<N, 3, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, hist, stage, th, fexp); break;
+    case 0: simp_fwd_range<N, 0, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    case 1: simp_fwd_range<N, 1, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    case 2: simp_fwd_range<N, 2, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    default: simp_fwd_range<N, 3, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
   }
 }
 
@@ -680,8 +698,11 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
     const int t = (int)((pos - base) / nb);
     const int64_t e0 = (pos - base) - (int64_t)t * nb;
     const int64_t e1 = mn64(nb, e0 + (end - pos));
-    float sx, sy, sz;
-    load_dir(p, t * W + lane, sx, sy, sz);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    // filter column of the lane (N = 0); lanes past the last column read the
+    // last one and their histogram column is never written out
+    const int fcol = min(t * W + lane, p.d - 1);
+    if constexpr (N > 0) load_dir(p, t * W + lane, sx, sy, sz);
     const int64_t voff = off_or(p.vert_off, b, p.count[0]);
     // dimension ranges within the complex's element numbering
     int64_t dlo = 0;
@@ -693,9 +714,11 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
       if (lo < hi) {
         const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
         if (th.fast)
-          simp_fwd_dim<N, WM, WT, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th, fexp);
+          simp_fwd_dim<N, WM, WT, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, fcol, hist, stage, th,
+                                        fexp);
         else
-          simp_fwd_dim<N, WM, WT, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, hist, stage, th, fexp);
+          simp_fwd_dim<N, WM, WT, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, fcol, hist, stage, th,
+                                         fexp);
       }
       dlo = dhi;
     }
@@ -1626,6 +1649,7 @@ hipError_t launch_forward_main(const Params& p, int block, size_t lds, hipStream
                               : launch_cub_fwd_t<3, WM_VMAX>(p, block, lds, s);
   }
   switch (p.n) {
+    case 0: return launch_simp_fwd_n<0>(p, block, lds, s);  // general vertex filter
     case 1: return launch_simp_fwd_n<1>(p, block, lds, s);
     case 2: return launch_simp_fwd_n<2>(p, block, lds, s);
     default: return launch_simp_fwd_n<3>(p, block, lds, s);

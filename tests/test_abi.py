@@ -229,3 +229,16 @@ def test_cubical_batch_needs_one_inclusion_level():
         W.CubicalBatch.from_host([a, c], device="cpu")
     assert W.CubicalBatch.from_host([a, synth.uniform_image((2, 5), 3)], device="cpu").B == 2
     del np
+
+
+def test_wecf_metadata(lib):
+    c = _simplicial()
+    assert lib.wect_wecf_workspace_bytes(ctypes.byref(c), 70, 16) > 0
+    # fvals missing while there are vertices and columns
+    assert lib.wect_wecf_forward(ctypes.byref(c), None, 3, FAKE, 6, FAKE, FAKE, 1 << 40, None) == L.WECT_ERR_ARG
+    # cubical complexes take wect_image_ecf
+    cub = _simplicial(kind=L.WECT_CUBICAL)
+    assert lib.wect_wecf_forward(ctypes.byref(cub), FAKE, 3, FAKE, 6, FAKE, FAKE, 1 << 40, None) == L.WECT_ERR_ARG
+    assert lib.wect_wecf_forward(ctypes.byref(c), FAKE, -1, FAKE, 6, FAKE, FAKE, 1 << 40, None) == L.WECT_ERR_ARG
+    # nothing to compute: no workspace needed, nothing enqueued
+    assert lib.wect_wecf_forward(ctypes.byref(c), FAKE, 0, FAKE, 6, None, None, 0, None) == L.WECT_OK

@@ -1,0 +1,119 @@
+"""Parity of the general vertex-filter WECF (fvals [V, m]) with the oracle,
+through the C ABI.  Integer weights: bit-exact; float32 weights: within
+1e-5 * sum|w| of the oracle's float64 value, and the same complex re-run with
+integer weights bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+F32_RTOL = 1e-5
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_03909_amd import api
+    api.set_launch()
+    return api
+
+
+def gpu_wecf(W, complexes, fvals, thr):
+    cx = W.SimplicialBatch.from_host(list(complexes))
+    out = W.wecf_forward(cx, np.asarray(fvals, np.float32), np.asarray(thr, np.float32))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check(got, ref, K, what):
+    if np.issubdtype(ref.dtype, np.integer):
+        bad = np.argwhere(got.astype(np.int64) != ref)
+        assert bad.size == 0, f"{what}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+    else:
+        tol = F32_RTOL * max(oracle.total_abs_weight(K), 1e-30)
+        err = np.abs(got.astype(np.float64) - ref).max() if ref.size else 0.0
+        assert err <= tol, f"{what}: max error {err} > {tol}"
+
+
+def tie_filter(g, V, m):
+    """Filter values from a small set (many ties with each other and with the thresholds)."""
+    return g.choice(np.array([-1.0, -0.5, -0.25, 0.0, 0.25, 0.5, 1.0, 1.5], np.float32), size=(V, m))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tiny(W, seed):
+    g = np.random.default_rng(seed)
+    n, top = [(2, 2), (3, 3), (1, 1), (3, 2)][seed % 4]
+    wm = ["ones", "explicit", "vertex_max", "explicit"][seed % 4]
+    wdt = np.float32 if wm == "vertex_max" or seed >= 4 else np.int32
+    K = synth.random_tiny_complex(seed, n=n, nv=9, top_dim=top, wmode=wm, wdtype=wdt)
+    m = [1, 7, 64, 65][seed % 4]
+    F = tie_filter(g, K.coords.shape[0], m)
+    thr = np.array([-1.0, -0.5, 0.0, 0.25, 0.5, 1.0], np.float32)
+    _say(f"tiny wecf seed={seed} m={m} {wm}")
+    check(gpu_wecf(W, [K], F, thr)[0], oracle.wecf(K, F, thr), K, f"seed {seed}")
+
+
+def test_heights_give_the_wect(W):
+    """fvals = V D^T (computed on the host in the fixed order) reproduces wect_forward bit for bit."""
+    K = synth.random_tiny_complex(3, n=3, nv=11, top_dim=3, wmode="explicit", wdtype=np.int32)
+    dirs, thr = synth.fibonacci_directions(70), synth.uniform_thresholds(33, 1.8)
+    F = oracle.heights(K.coords, dirs).T
+    cx = W.SimplicialBatch.from_host([K])
+    ref = W.wect_forward(cx, W.Grid(dirs, thr)).cpu().numpy()
+    assert np.array_equal(gpu_wecf(W, [K], F, thr), ref)
+
+
+@pytest.mark.parametrize("dec", [1, 2])
+def test_batch_with_empty_member_and_many_columns(W, dec):
+    g = np.random.default_rng(11)
+    Ks = [synth.random_tiny_complex(s, n=2, nv=6 + 2 * s, top_dim=2, wmode="explicit", wdtype=np.int32)
+          for s in range(5)]
+    Ks.insert(2, synth.Simplicial(np.zeros((0, 2), np.float32), [None, np.zeros((0, 2), np.int32),
+                                                                 np.zeros((0, 3), np.int32)],
+                                  "explicit", [np.zeros(0, np.int32)] * 3))
+    V = sum(K.coords.shape[0] for K in Ks)
+    F = tie_filter(g, V, 130)
+    thr = np.linspace(-1.2, 1.6, 29).astype(np.float32)
+    try:
+        W.set_launch(0, 0, 0, dec)
+        _say(f"wecf batch, m=130, decomposition={dec}")
+        got = gpu_wecf(W, Ks, F, thr)
+    finally:
+        W.set_launch()
+    v0 = 0
+    for b, K in enumerate(Ks):
+        nv = K.coords.shape[0]
+        check(got[b], oracle.wecf(K, F[v0:v0 + nv], thr), K, f"member {b}")
+        v0 += nv
+
+
+def test_float_weights_larger_batch(W):
+    """Vertex-max float weights on jittered Freudenthal grids with random filters."""
+    w = synth.cfg5(n_complexes=6, vmin=300, vmax=3000)
+    g = np.random.default_rng(5)
+    V = sum(K.coords.shape[0] for K in w.complexes)
+    F = g.uniform(-1.5, 1.5, size=(V, 100)).astype(np.float32)
+    thr = w.thr
+    _say("wecf float weights, 6 grids, m=100")
+    got = gpu_wecf(W, w.complexes, F, thr)
+    v0 = 0
+    for b, K in enumerate(w.complexes):
+        nv = K.coords.shape[0]
+        check(got[b], oracle.wecf(K, F[v0:v0 + nv], thr), K, f"grid {b}")
+        # the same complex with integer weights: bit-exact membership
+        Ki = synth.Simplicial(K.coords, K.simplices, "ones", [])
+        check(gpu_wecf(W, [Ki], F[v0:v0 + nv], thr)[0], oracle.wecf(Ki, F[v0:v0 + nv], thr), Ki, f"ones {b}")
+        v0 += nv
