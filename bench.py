@@ -251,7 +251,16 @@ def main(argv=None):
             "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_graph_ms": t_g * 1e3,
             "one_per_launch": {"fwd_ms": t_f1 * 1e3, "fwd_bwd_ms": t_fb1 * 1e3,
                                "fwd_batched_speedup": t_f1 / t_f, "fwd_bwd_batched_speedup": t_fb1 / t_fb}}
-        del cx5, o5, gv5, ws5, gout, singles5, o5s, gv5s, go5, ws5s
+        # the same complexes through the general vertex-filter WECF, with the filter values
+        # given as an array (here the heights of the 128 directions, formed on the device)
+        F5 = (cx5.coords @ g5.dirs.t()).contiguous()
+        o5w = torch.empty((cx5.B, F5.shape[1], g5.T), dtype=torch.float32, device=dev)
+        ws5w = torch.empty(max(1, W.wecf_workspace_bytes(cx5, F5.shape[1], g5.T)), dtype=torch.uint8, device=dev)
+        t_w = timed(lambda: W.wecf_forward(cx5, F5, g5.thr, out=o5w, ws=ws5w), 5, 1)
+        extras["differentiation_batch64"]["wecf_filter_array_m128"] = {
+            "fwd_ms": t_w * 1e3, "items_per_s": it5 / t_w,
+            "note": "filter values read from a [V, 128] array instead of formed from coordinates"}
+        del cx5, o5, gv5, ws5, gout, singles5, o5s, gv5s, go5, ws5s, F5, o5w, ws5w
         # 3D simplicial, float32 weights
         w3 = synth.cfg3()
         cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)
