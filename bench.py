@@ -141,6 +141,19 @@ def main(argv=None):
         W.wect_forward(cx, grid, out=out, ws=ws)
 
     sec = timed(step, a.steps, a.warmup)
+    # cold runs: before each, a 1 GiB write evicts the inputs from the caches
+    # (L2 and the 256 MiB Infinity Cache), then one step is timed with events
+    flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(5):
+        flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    del flush
     # live kernel timing of the dominant (histogram) kernel with HIP events on its stream
     W.profile_enable(True)
     W.profile_read(reset=True)
@@ -191,6 +204,7 @@ def main(argv=None):
                    "cells": cells, "included_vertices": nverts, "items_per_step": items,
                    "mode": "batched forward, one call for all images"},
         "roofline": roofline,
+        "cold_ms_per_step": sorted(cold)[len(cold) // 2],
     }
 
     result["kernel_sources"] = kernel_source_hash()

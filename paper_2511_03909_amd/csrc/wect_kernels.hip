@@ -1179,7 +1179,13 @@ __device__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, i
       for (int jj = 0; jj < kMaxDG; ++jj) {
         if (jj < ntl) {
           const float h = max_height<N, DIM>(E, sx[jj], sy[jj], sz[jj]);
-          const int bi = thr_index<FAST>(h, th);
+          int bi;
+          if (FAST && th.arith) {
+            // arithmetic index; the one-read fix only where a lane sits on a threshold
+            if (__builtin_amdgcn_ballot_w64(!thr_arith(h, th, bi) ? 1 : 0) != 0) bi = thr_index<FAST>(h, th);
+          } else {
+            bi = thr_index<FAST>(h, th);
+          }
           acc += Gt[((size_t)jj * T1 + bi) * W + lane];
         }
       }
