@@ -766,34 +766,38 @@ __device__ __forceinline__ int cub_val(CubCell c) {
 }
 
 // Raw neighbourhood of one voxel, loaded one tile ahead of its use: the
-// intensities of the 3^N voxels around it (-1 outside the grid), its axis
-// coordinates and its grid position.
+// intensities of the 3^N voxels around it, its axis coordinates and which of
+// its neighbours lie inside the grid.  Coordinates are clamped into the grid,
+// so every load is unconditional and in bounds; cub_weights masks the
+// neighbours outside (bits of `inside`: i0 > 0, i0 < n0-1, i1 > 0, i1 < n1-1,
+// i2 > 0, i2 < n2-1).
 template <int N>
 struct CubFetch {
   static constexpr int M = N == 2 ? 9 : 27;
   int nb[M];
   float cx, cy, cz;
+  uint32_t inside;
   bool valid;
 
   __device__ __forceinline__ void load(const uint8_t* vol, const float* ax0, const float* ax1, const float* ax2,
-                                       int n0, int n1, int n2, uint32_t v, bool active) {
+                                       int n0, int n1, int n2, int i0, int i1, int i2, bool active) {
     valid = active;
-    // voxel counts of one complex are below 2^31 (checked by wect_validate)
-    const uint32_t r = v / (uint32_t)n0;
-    const int i0 = (int)(v - r * (uint32_t)n0);
-    const uint32_t i2u = r / (uint32_t)n1;
-    const int i1 = (int)(r - i2u * (uint32_t)n1);
-    const int i2 = (int)i2u;
+    i0 = min(i0, n0 - 1);  // past the end of the range: any in-bounds voxel
+    i1 = min(i1, n1 - 1);
+    i2 = min(i2, n2 - 1);
+    const uint32_t col[3] = {(uint32_t)max(i0 - 1, 0), (uint32_t)i0, (uint32_t)min(i0 + 1, n0 - 1)};
+    const int row[3] = {max(i1 - 1, 0), i1, min(i1 + 1, n1 - 1)};
+    const int lay[3] = {max(i2 - 1, 0), i2, min(i2 + 1, n2 - 1)};
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-      const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
-      const int j0 = i0 + d0, j1 = i1 + d1, j2 = i2 + d2;
-      const bool in = active && j0 >= 0 && j0 < n0 && j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2;
-      nb[m] = in ? (int)vol[(int)v + d0 + d1 * n0 + (N == 3 ? d2 * n0 * n1 : 0)] : -1;
+      const int d0 = m % 3, d1 = (m / 3) % 3, d2 = N == 3 ? m / 9 : 1;
+      nb[m] = vol[(uint32_t)(lay[d2] * n1 + row[d1]) * (uint32_t)n0 + col[d0]];
     }
-    cx = active ? ax0[i0] : 0.0f;
-    cy = active ? ax1[i1] : 0.0f;
-    cz = (N == 3 && active) ? ax2[i2] : 0.0f;
+    inside = (uint32_t)(i0 > 0) | (uint32_t)(i0 < n0 - 1) << 1 | (uint32_t)(i1 > 0) << 2 |
+             (uint32_t)(i1 < n1 - 1) << 3 | (uint32_t)(i2 > 0) << 4 | (uint32_t)(i2 < n2 - 1) << 5;
+    cx = ax0[i0];
+    cy = ax1[i1];
+    cz = N == 3 ? ax2[i2] : 0.0f;
   }
 };
 
@@ -806,7 +810,13 @@ __device__ __forceinline__ void cub_weights(const CubFetch<N>& f, int include_ab
   constexpr int M = CubFetch<N>::M;
   int nb[M];
 #pragma unroll
-  for (int m = 0; m < M; ++m) nb[m] = f.nb[m] > include_above ? f.nb[m] : -1;
+  for (int m = 0; m < M; ++m) {
+    const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
+    const bool in = (d0 < 0 ? (f.inside & 1) : d0 > 0 ? (f.inside & 2) : 1) &&
+                    (d1 < 0 ? (f.inside & 4) : d1 > 0 ? (f.inside & 8) : 1) &&
+                    (d2 < 0 ? (f.inside & 16) : d2 > 0 ? (f.inside & 32) : 1);
+    nb[m] = in && f.nb[m] > include_above ? f.nb[m] : -1;
+  }
   auto at = [&](int d0, int d1, int d2) { return nb[(d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0)]; };
   const int v0 = at(0, 0, 0);
   const CubCell cv = {v0, v0};
@@ -867,8 +877,16 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
   const float* ax1 = ax0 + n0;
   const float* ax2 = ax1 + n1;
   int arith = th.arith;
+  // grid position of the thread's voxel lo + tid, advanced by TS voxels per
+  // tile without division (voxel counts of one complex are below 2^31)
+  const uint32_t ts = (uint32_t)TS;
+  const uint32_t s0 = ts % (uint32_t)n0, s1 = (ts / (uint32_t)n0) % (uint32_t)n1;
+  const uint32_t s2 = ts / ((uint32_t)n0 * (uint32_t)n1);
+  uint32_t v = (uint32_t)(lo + tid);
+  int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
+  int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
   CubFetch<N> f;
-  f.load(vol, ax0, ax1, ax2, n0, n1, n2, (uint32_t)(lo + tid), lo + tid < hi && tid < TS);
+  f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
   for (int64_t t0 = lo; t0 < hi; t0 += TS) {
     if (tid == 0) *counter = 0;
     __syncthreads();
@@ -896,8 +914,15 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
       for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
     }
     // neighbourhoods of the next tile (in flight during this tile's histogram)
-    const int64_t nx = t0 + TS + tid;
-    f.load(vol, ax0, ax1, ax2, n0, n1, n2, (uint32_t)nx, nx < hi && tid < TS);
+    i0 += (int)s0;
+    int carry = i0 >= n0;
+    i0 -= carry ? n0 : 0;
+    i1 += (int)s1 + carry;
+    carry = i1 >= n1;
+    i1 -= carry ? n1 : 0;
+    i2 += (int)s2 + carry;
+    v += ts;
+    f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
     __syncthreads();
     const int ne = uniform(*counter);
     const float* Wl = stage + L::COFF + orth;  // the lane's combined weight within an entry
