@@ -453,16 +453,6 @@ __device__ __forceinline__ ACC load_weight(const float* E) {
   else return *(const uint64_t*)E;
 }
 
-// Largest filter value of a staged simplex for the lane's filter column col
-// (fvals row-major [V, m]; the 64 lanes read 64 consecutive words of a row).
-template <int DIM>
-__device__ __forceinline__ float max_filter(const float* E, const float* fvals, int m, int col) {
-  float h = fvals[(int64_t)bitcast<int32_t>(E[0]) * m + col];
-#pragma unroll
-  for (int j = 1; j <= DIM; ++j) h = fmaxf(h, fvals[(int64_t)bitcast<int32_t>(E[j]) * m + col]);
-  return h;
-}
-
 // Maximum height of a staged simplex for the lane's direction.
 template <int N, int DIM>
 __device__ __forceinline__ float max_height(const float* E, float sx, float sy, float sz) {
@@ -470,6 +460,74 @@ __device__ __forceinline__ float max_height(const float* E, float sx, float sy, 
 #pragma unroll
   for (int j = 1; j <= DIM; ++j) h = fmaxf(h, height<N>(E + j * N, sx, sy, sz));
   return h;
+}
+
+// Histogram of staged simplices for a general vertex filter (n = 0): like
+// hist_entries, but the filter values come from global memory, so the values
+// of the next pair of entries are loaded before the current pair is binned
+// (past the end, the current pair's rows are loaded again: always in bounds).
+template <int DIM, bool FAST, typename ACC, typename L>
+__device__ __forceinline__ void filter_hist(ACC* col, const float* stage, int first, int step, int ne, const Thr& th,
+                                            const float* fvals, int m, int fcol) {
+  constexpr int NV = DIM + 1;
+  auto rowv = [&](const float* E, int j) { return fvals[(int64_t)bitcast<int32_t>(E[j]) * m + fcol]; };
+  int e = first;
+  if (e + 1 < ne) {
+    float c0[NV], c1[NV];
+    {
+      const float* E0 = stage + e * L::STRIDE;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        c0[j] = rowv(E0, j);
+        c1[j] = rowv(E0 + L::STRIDE, j);
+      }
+    }
+    for (; e + 1 < ne; e += step) {
+      const int en = e + step + 1 < ne ? e + step : e;
+      const float* N0 = stage + en * L::STRIDE;
+      float n0[NV], n1[NV];
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        n0[j] = rowv(N0, j);
+        n1[j] = rowv(N0 + L::STRIDE, j);
+      }
+      float h0 = c0[0], h1 = c1[0];
+#pragma unroll
+      for (int j = 1; j < NV; ++j) {
+        h0 = fmaxf(h0, c0[j]);
+        h1 = fmaxf(h1, c1[j]);
+      }
+      const float* E0 = stage + e * L::STRIDE;
+      const ACC w0 = load_weight<ACC>(E0 + L::WOFF);
+      const ACC w1 = load_weight<ACC>(E0 + L::STRIDE + L::WOFF);
+      int b0, b1;
+      if (FAST && th.arith) {
+        const bool ok0 = thr_arith(h0, th, b0);
+        const bool ok1 = thr_arith(h1, th, b1);
+        if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
+          if (!ok0) b0 = thr_near(h0, b0, th);
+          if (!ok1) b1 = thr_near(h1, b1, th);
+        }
+      } else {
+        b0 = thr_index<FAST>(h0, th);
+        b1 = thr_index<FAST>(h1, th);
+      }
+      lds_add(&col[b0 * W], w0);
+      lds_add(&col[b1 * W], w1);
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        c0[j] = n0[j];
+        c1[j] = n1[j];
+      }
+    }
+  }
+  if (e < ne) {
+    const float* E0 = stage + e * L::STRIDE;
+    float h0 = rowv(E0, 0);
+#pragma unroll
+    for (int j = 1; j < NV; ++j) h0 = fmaxf(h0, rowv(E0, j));
+    lds_add(&col[thr_index<FAST>(h0, th) * W], load_weight<ACC>(E0 + L::WOFF));
+  }
 }
 
 // Forward over the simplices [lo, hi) (local numbering) of dimension DIM of
@@ -522,13 +580,16 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
       for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
     }
     // histogram of tile t: each wavefront takes adjacent pairs of entries
-    hist_entries<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
-                            [&](int e, float& h, ACC& w) {
-                              const float* E = stage + e * L::STRIDE;
-                              if constexpr (N == 0) h = max_filter<DIM>(E, p.fvals, p.d, fcol);
-                              else h = max_height<N, DIM>(E, sx, sy, sz);
-                              w = load_weight<ACC>(E + L::WOFF);
-                            });
+    if constexpr (N == 0) {
+      filter_hist<DIM, FAST, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, th, p.fvals, p.d, fcol);
+    } else {
+      hist_entries<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
+                              [&](int e, float& h, ACC& w) {
+                                const float* E = stage + e * L::STRIDE;
+                                h = max_height<N, DIM>(E, sx, sy, sz);
+                                w = load_weight<ACC>(E + L::WOFF);
+                              });
+    }
   }
   __syncthreads();
 }
