@@ -72,6 +72,7 @@ struct Plan {
   int block = 1024;
   size_t lds_fwd = 0, lds_bwd = 0;
   size_t partial_bytes = 0, dsum_bytes = 0, absmax_bytes = 0;
+  size_t vb_bytes = 0;        // general-filter WECF: threshold indices of the filter values
   bool split = false;
   bool group_mode = false;
   size_t ws_fwd = 0, ws_bwd = 0;
@@ -325,12 +326,17 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   p.dsum = pl.dsum_bytes ? w8 + pl.partial_bytes : nullptr;
   p.split = pl.split ? 1 : 0;
   p.absmax = pl.absmax_bytes ? reinterpret_cast<float*>(w8 + pl.partial_bytes + pl.dsum_bytes) : nullptr;
+  p.vbuckets = pl.vb_bytes ? w8 + pl.partial_bytes + pl.dsum_bytes + pl.absmax_bytes : nullptr;
   p.G = pl.G_fwd;
   p.S = pl.S_fwd;
   const bool prof = g_profile.load() != 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p.nabsmax > 0) {
     if (hipError_t e = wect::launch_absmax(p, s); e != hipSuccess) return device_error(e, "abs-max kernel");
+  }
+  if (p.n == 0 && p.S > 0) {
+    if (hipError_t e = wect::launch_vertex_buckets(p, p.count[0] * (int64_t)p.d, s); e != hipSuccess)
+      return device_error(e, "vertex index kernel");
   }
   if (p.S > 0) {
     if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
@@ -406,6 +412,12 @@ wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, cons
   pl->p.coords = nullptr;
   pl->p.dirs = nullptr;
   pl->p.fvals = fvals;
+  // threshold index of every filter value, one byte while T < 255
+  pl->p.vb_bytes = T < 255 ? 1 : 2;
+  if (pl->ws_fwd > 0 || (m > 0 && T > 0)) {
+    pl->vb_bytes = align256((size_t)c->count[0] * (size_t)m * (size_t)pl->p.vb_bytes);
+    pl->ws_fwd += pl->vb_bytes;
+  }
   return WECT_OK;
 }
 

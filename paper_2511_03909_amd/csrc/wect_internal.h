@@ -16,6 +16,8 @@ struct Params {
   int32_t kind, n, B, top_dim, wmode, dtype;
   const float* coords;
   const float* fvals;    // n = 0: vertex filter values [V, d] row-major (WECF of a general filter)
+  void* vbuckets;        // n = 0: threshold index of every filter value [V, d], uint8 or uint16
+  int32_t vb_bytes;      // 1 (T < 255) or 2
   const int64_t* vert_off;
   int64_t count[4];
   const int32_t* simp[4];
@@ -66,6 +68,8 @@ hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s);
 constexpr int kEcfRowBytes = 256 * 4;  // one image's sums over the intensity values
 
 hipError_t launch_absmax(const Params& p, hipStream_t s);
+// n = 0: threshold index of every filter value (first pass of the general-filter WECF).
+hipError_t launch_vertex_buckets(const Params& p, int64_t nvals, hipStream_t s);
 
 // LDS bytes of the forward kernels: fixed part (histogram, thresholds) plus
 // forward_entry_bytes per staged entry; of the backward kernel in total.

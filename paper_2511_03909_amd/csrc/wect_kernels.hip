@@ -462,71 +462,58 @@ __device__ __forceinline__ float max_height(const float* E, float sx, float sy, 
   return h;
 }
 
-// Histogram of staged simplices for a general vertex filter (n = 0): like
-// hist_entries, but the filter values come from global memory, so the values
-// of the next pair of entries are loaded before the current pair is binned
-// (past the end, the current pair's rows are loaded again: always in bounds).
-template <int DIM, bool FAST, typename ACC, typename L>
-__device__ __forceinline__ void filter_hist(ACC* col, const float* stage, int first, int step, int ne, const Thr& th,
-                                            const float* fvals, int m, int fcol) {
+// Histogram of staged simplices for a general vertex filter (n = 0).  The
+// threshold index of every filter value was computed by k_vertex_buckets
+// (Algorithm 1 indexes the vertex filter values first); since the index is
+// monotone, a simplex's index is the largest of its vertices' indices.  The
+// 64 lanes read 64 consecutive indices of a vertex row.  Global-memory latency
+// dominates, so a wavefront gathers the indices of K pairs of entries before
+// it adds any of them (out-of-range pairs re-read a valid one: always in bounds).
+template <int DIM, typename VB, typename ACC, typename L>
+__device__ __forceinline__ void filter_hist(ACC* col, const float* stage, int first, int step, int ne,
+                                            const VB* vb, int m, int fcol) {
   constexpr int NV = DIM + 1;
-  auto rowv = [&](const float* E, int j) { return fvals[(int64_t)bitcast<int32_t>(E[j]) * m + fcol]; };
+  constexpr int K = 8;
+  auto rowb = [&](const float* E, int j) { return (int)vb[(int64_t)bitcast<int32_t>(E[j]) * m + fcol]; };
   int e = first;
-  if (e + 1 < ne) {
-    float c0[NV], c1[NV];
-    {
-      const float* E0 = stage + e * L::STRIDE;
+  for (; e + 1 < ne; e += K * step) {
+    int x[K][2][NV];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int ek = e + k * step;
+      const float* E = stage + (ek + 1 < ne ? ek : e) * L::STRIDE;
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        c0[j] = rowv(E0, j);
-        c1[j] = rowv(E0 + L::STRIDE, j);
+        x[k][0][j] = rowb(E, j);
+        x[k][1][j] = rowb(E + L::STRIDE, j);
       }
     }
-    for (; e + 1 < ne; e += step) {
-      const int en = e + step + 1 < ne ? e + step : e;
-      const float* N0 = stage + en * L::STRIDE;
-      float n0[NV], n1[NV];
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        n0[j] = rowv(N0, j);
-        n1[j] = rowv(N0 + L::STRIDE, j);
-      }
-      float h0 = c0[0], h1 = c1[0];
+    for (int k = 0; k < K; ++k) {
+      const int ek = e + k * step;
+      if (ek + 1 < ne) {
+        int b0 = x[k][0][0], b1 = x[k][1][0];
 #pragma unroll
-      for (int j = 1; j < NV; ++j) {
-        h0 = fmaxf(h0, c0[j]);
-        h1 = fmaxf(h1, c1[j]);
-      }
-      const float* E0 = stage + e * L::STRIDE;
-      const ACC w0 = load_weight<ACC>(E0 + L::WOFF);
-      const ACC w1 = load_weight<ACC>(E0 + L::STRIDE + L::WOFF);
-      int b0, b1;
-      if (FAST && th.arith) {
-        const bool ok0 = thr_arith(h0, th, b0);
-        const bool ok1 = thr_arith(h1, th, b1);
-        if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
-          if (!ok0) b0 = thr_near(h0, b0, th);
-          if (!ok1) b1 = thr_near(h1, b1, th);
+        for (int j = 1; j < NV; ++j) {
+          b0 = max(b0, x[k][0][j]);
+          b1 = max(b1, x[k][1][j]);
         }
-      } else {
-        b0 = thr_index<FAST>(h0, th);
-        b1 = thr_index<FAST>(h1, th);
-      }
-      lds_add(&col[b0 * W], w0);
-      lds_add(&col[b1 * W], w1);
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        c0[j] = n0[j];
-        c1[j] = n1[j];
+        const float* E = stage + ek * L::STRIDE;
+        lds_add(&col[b0 * W], load_weight<ACC>(E + L::WOFF));
+        lds_add(&col[b1 * W], load_weight<ACC>(E + L::STRIDE + L::WOFF));
       }
     }
   }
+  // pair starts are first + k step with first + k step + 1 < ne; the next start
+  // after them holds a last single entry when it is below ne
+  const int npairs = first + 1 < ne ? (ne - 2 - first) / step + 1 : 0;
+  e = first + npairs * step;
   if (e < ne) {
     const float* E0 = stage + e * L::STRIDE;
-    float h0 = rowv(E0, 0);
+    int c0 = 0;
 #pragma unroll
-    for (int j = 1; j < NV; ++j) h0 = fmaxf(h0, rowv(E0, j));
-    lds_add(&col[thr_index<FAST>(h0, th) * W], load_weight<ACC>(E0 + L::WOFF));
+    for (int j = 0; j < NV; ++j) c0 = max(c0, rowb(E0, j));
+    lds_add(&col[c0 * W], load_weight<ACC>(E0 + L::WOFF));
   }
 }
 
@@ -581,7 +568,12 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
     }
     // histogram of tile t: each wavefront takes adjacent pairs of entries
     if constexpr (N == 0) {
-      filter_hist<DIM, FAST, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, th, p.fvals, p.d, fcol);
+      if (p.vb_bytes == 1)
+        filter_hist<DIM, uint8_t, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, (const uint8_t*)p.vbuckets, p.d,
+                                          fcol);
+      else
+        filter_hist<DIM, uint16_t, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, (const uint16_t*)p.vbuckets,
+                                           p.d, fcol);
     } else {
       hist_entries<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
                               [&](int e, float& h, ACC& w) {
@@ -1682,6 +1674,32 @@ __global__ __launch_bounds__(256) void k_image_ecf_finish(Params p) {
   }
 }
 
+// First pass of the general-filter WECF: the threshold index of every filter
+// value (the index step that Algorithm 1 applies to the vertex filter values),
+// stored as uint8 (T < 255) or uint16.  Grid-stride over the [V, m] array;
+// every block sets up the threshold search once.
+template <typename VB>
+__global__ __launch_bounds__(256) void k_vertex_buckets(Params p, int64_t nvals) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* P = (float*)smem;
+  Thr th;
+  setup_thresholds(p.thr, p.T, P, th);
+  VB* out = (VB*)p.vbuckets;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvals; i += stride) {
+    const float h = p.fvals[i];
+    int b;
+    if (th.arith) {
+      if (!thr_arith(h, th, b)) b = thr_near(h, b, th);
+    } else if (th.fast) {
+      b = thr_index<true>(h, th);
+    } else {
+      b = thr_index<false>(h, th);
+    }
+    out[i] = (VB)b;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1811,6 +1829,21 @@ hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s) {
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_image_ecf_finish, dim3(p.B), dim3(kEcfBins), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_vertex_buckets(const Params& p, int64_t nvals, hipStream_t s) {
+  if (nvals <= 0) return hipSuccess;
+  const size_t lds = ((size_t)(p.T + 1) * 4 + 15) / 16 * 16;
+  int64_t blocks = (nvals + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (p.vb_bytes == 1) {
+    if (hipError_t e = set_lds_limit(k_vertex_buckets<uint8_t>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vertex_buckets<uint8_t>, dim3((unsigned)blocks), dim3(256), lds, s, p, nvals);
+  } else {
+    if (hipError_t e = set_lds_limit(k_vertex_buckets<uint16_t>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vertex_buckets<uint16_t>, dim3((unsigned)blocks), dim3(256), lds, s, p, nvals);
+  }
   return hipGetLastError();
 }
 
