@@ -803,21 +803,6 @@ struct CubLayout {
   static constexpr int STRIDE = N == 2 ? 8 : 12;
 };
 
-// A cell around the staged vertex v: mx = largest corner intensity, mn =
-// smallest corner value, where a corner that is not a vertex counts as -1; the
-// cell exists iff mn >= 0.
-struct CubCell {
-  int mx, mn;
-};
-
-__device__ __forceinline__ CubCell cub_join(CubCell a, int x) { return {max(a.mx, x), min(a.mn, x)}; }
-__device__ __forceinline__ CubCell cub_join(CubCell a, CubCell b) { return {max(a.mx, b.mx), min(a.mn, b.mn)}; }
-
-template <int WM>
-__device__ __forceinline__ int cub_val(CubCell c) {
-  return c.mn >= 0 ? (WM == WM_ONES ? 1 : c.mx) : 0;
-}
-
 // Raw neighbourhood of one voxel, loaded one tile ahead of its use: the
 // intensities of the 3^N voxels around it, its axis coordinates and which of
 // its neighbours lie inside the grid.  Coordinates are clamped into the grid,
@@ -861,54 +846,69 @@ struct CubFetch {
 template <int N, int WM>
 __device__ __forceinline__ void cub_weights(const CubFetch<N>& f, int include_above, int32_t* cw) {
   constexpr int M = CubFetch<N>::M;
-  int nb[M];
+  auto nbi = [](int d0, int d1, int d2) { return (d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0); };
+  // neighbour present: inside the grid and a vertex (lane masks, no arithmetic)
+  bool pr[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
     const bool in = (d0 < 0 ? (f.inside & 1) : d0 > 0 ? (f.inside & 2) : 1) &&
                     (d1 < 0 ? (f.inside & 4) : d1 > 0 ? (f.inside & 8) : 1) &&
                     (d2 < 0 ? (f.inside & 16) : d2 > 0 ? (f.inside & 32) : 1);
-    nb[m] = in && f.nb[m] > include_above ? f.nb[m] : -1;
+    pr[m] = in && f.nb[m] > include_above;
   }
-  auto at = [&](int d0, int d1, int d2) { return nb[(d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0)]; };
-  const int v0 = at(0, 0, 0);
-  const CubCell cv = {v0, v0};
-  // edges E[axis][side], side 0: towards -axis, 1: towards +axis
-  CubCell E[N][2];
+  const int x = f.nb[nbi(0, 0, 0)];  // the voxel itself (a vertex: the caller checked)
+  // a cell's weight: 1, or (vertex-max) the largest corner intensity; x is a corner of every cell here
+  auto val = [&](bool present, int mx) { return present ? (WM == WM_ONES ? 1 : mx) : 0; };
+  auto at = [&](int d0, int d1, int d2) { return f.nb[nbi(d0, d1, d2)]; };
+  auto has = [&](int d0, int d1, int d2) { return pr[nbi(d0, d1, d2)]; };
+  // edges E[axis][side] (side 0: towards -axis)
+  int E[N][2], Emx[N][2];
 #pragma unroll
   for (int a = 0; a < N; ++a)
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
       const int s = sd ? 1 : -1;
-      E[a][sd] = cub_join(cv, at(a == 0 ? s : 0, a == 1 ? s : 0, a == 2 ? s : 0));
+      const int d0 = a == 0 ? s : 0, d1 = a == 1 ? s : 0, d2 = a == 2 ? s : 0;
+      Emx[a][sd] = max(x, at(d0, d1, d2));
+      E[a][sd] = val(has(d0, d1, d2), Emx[a][sd]);
     }
+  const int vx = WM == WM_ONES ? 1 : x;
   if constexpr (N == 2) {
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
       const int s0 = o & 1, s1 = (o >> 1) & 1;
-      const CubCell sq = cub_join(cub_join(E[0][s0], E[1][s1]), at(s0 ? 1 : -1, s1 ? 1 : -1, 0));
-      cw[o] = cub_val<WM>(cv) - cub_val<WM>(E[0][s0]) - cub_val<WM>(E[1][s1]) + cub_val<WM>(sq);
+      const int a0 = s0 ? 1 : -1, a1 = s1 ? 1 : -1;
+      const bool sq = has(a0, 0, 0) && has(0, a1, 0) && has(a0, a1, 0);
+      const int sqv = val(sq, max(max(Emx[0][s0], at(0, a1, 0)), at(a0, a1, 0)));
+      cw[o] = vx - E[0][s0] - E[1][s1] + sqv;
     }
   } else {
-    // squares F01[s0][s1], F02[s0][s2], F12[s1][s2]
-    CubCell F01[2][2], F02[2][2], F12[2][2];
+    // squares F01[s0][s1], F02[s0][s2], F12[s1][s2]: presence and largest corner
+    int F01[2][2], F02[2][2], F12[2][2], M01[2][2], M12[2][2];
+    bool P01[2][2], P12[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int sa = a ? 1 : -1, sb = b ? 1 : -1;
-        F01[a][b] = cub_join(cub_join(E[0][a], E[1][b]), at(sa, sb, 0));
-        F02[a][b] = cub_join(cub_join(E[0][a], E[2][b]), at(sa, 0, sb));
-        F12[a][b] = cub_join(cub_join(E[1][a], E[2][b]), at(0, sa, sb));
+        P01[a][b] = has(sa, 0, 0) && has(0, sb, 0) && has(sa, sb, 0);
+        M01[a][b] = max(max(Emx[0][a], at(0, sb, 0)), at(sa, sb, 0));
+        F01[a][b] = val(P01[a][b], M01[a][b]);
+        const bool p02 = has(sa, 0, 0) && has(0, 0, sb) && has(sa, 0, sb);
+        F02[a][b] = val(p02, max(max(Emx[0][a], at(0, 0, sb)), at(sa, 0, sb)));
+        P12[a][b] = has(0, sa, 0) && has(0, 0, sb) && has(0, sa, sb);
+        M12[a][b] = max(max(Emx[1][a], at(0, 0, sb)), at(0, sa, sb));
+        F12[a][b] = val(P12[a][b], M12[a][b]);
       }
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
       const int s0 = o & 1, s1 = (o >> 1) & 1, s2 = (o >> 2) & 1;
-      // the cube's 8 corners: F01 and F12 cover six of them; add the 0-2 diagonal and the far corner
-      const CubCell cube = cub_join(cub_join(cub_join(F01[s0][s1], F12[s1][s2]), at(s0 ? 1 : -1, 0, s2 ? 1 : -1)),
-                                    at(s0 ? 1 : -1, s1 ? 1 : -1, s2 ? 1 : -1));
-      cw[o] = cub_val<WM>(cv) - cub_val<WM>(E[0][s0]) - cub_val<WM>(E[1][s1]) - cub_val<WM>(E[2][s2]) +
-              cub_val<WM>(F01[s0][s1]) + cub_val<WM>(F02[s0][s2]) + cub_val<WM>(F12[s1][s2]) - cub_val<WM>(cube);
+      const int a0 = s0 ? 1 : -1, a1 = s1 ? 1 : -1, a2 = s2 ? 1 : -1;
+      // the cube's corners: those of F01 and F12 plus the 0-2 diagonal and the far corner
+      const bool pc = P01[s0][s1] && P12[s1][s2] && has(a0, 0, a2) && has(a0, a1, a2);
+      const int cube = val(pc, max(max(M01[s0][s1], M12[s1][s2]), max(at(a0, 0, a2), at(a0, a1, a2))));
+      cw[o] = vx - E[0][s0] - E[1][s1] - E[2][s2] + F01[s0][s1] + F02[s0][s2] + F12[s1][s2] - cube;
     }
   }
 }
