@@ -313,6 +313,19 @@ def main(argv=None):
         extras["cubical_3d_16vol"] = {"workload": w4.name, "items": it4, "items_per_s": it4 / t4, "ms": t4 * 1e3,
                                       "one_per_launch_ms": t41 * 1e3, "batched_speedup": t41 / t4}
         del cx4, o4, ws4, singles4, o4s, ws4s
+        # the headline images as weighted Freudenthal complexes built on the device
+        # (vertex weights = intensities), then their WECT through the simplicial path
+        cxf = W.CubicalBatch.from_host(w.complexes, device=dev)
+        t_build = timed(lambda: W.freudenthal_from_images(cxf), 10, 2)
+        sbf = W.freudenthal_from_images(cxf)
+        nf = sum(sbf.counts)
+        of = torch.empty((sbf.B, d, T), dtype=torch.float32, device=dev)
+        wsf = torch.empty(max(1, W.wect_workspace_bytes(sbf, grid)), dtype=torch.uint8, device=dev)
+        t_fw = timed(lambda: W.wect_forward(sbf, grid, out=of, ws=wsf), 10, 2)
+        extras["freudenthal_2d_256x128x128"] = {
+            "workload": "headline images as Freudenthal complexes (every pixel a vertex, vertex-max weights)",
+            "build_ms": t_build * 1e3, "simplices": nf, "wect_ms": t_fw * 1e3, "items_per_s": d * nf / t_fw}
+        del cxf, sbf, of, wsf
         # ECF of an image (intensity as the vertex filter), uniform intensities as in the
         # paper's throughput measurement; pixels (voxels) per second at 1,000 and 10,000 thresholds
         ecf = {}

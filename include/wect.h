@@ -196,6 +196,34 @@ wect_status wect_wecf_forward(const wect_complex* c, const float* fvals, int32_t
                               void* out, void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * Weighted Freudenthal complexes of images, built on the device (images become
+ * weighted simplicial complexes through the Freudenthal triangulation with
+ * weights from the pixel intensities: the paper's Background section, after
+ * the definition of weighted simplicial complexes).
+ *
+ * Pixel (i0, i1) of an n0 x n1 image is vertex i1 n0 + i0, at (axis0[i0],
+ * axis1[i1]), with weight = its intensity (use wmode VERTEX_MAX: a simplex
+ * weighs the largest intensity of its vertices).  Edges: the (n0-1) n1
+ * horizontal ones (row-major), the n0 (n1-1) vertical ones, then the
+ * (n0-1)(n1-1) diagonals (i0,i1)-(i0+1,i1+1).  Triangles: every
+ * {(i0,i1), (i0+1,i1), (i0+1,i1+1)}, then every {(i0,i1), (i0,i1+1), (i0+1,i1+1)}.
+ * Every pixel is a vertex (include_above is not read).
+ *
+ * wect_freudenthal_counts: host shapes [B][3] (n0, n1, 1, as in
+ *   wect_complex.shape) -> total vertices, edges and triangles (host).
+ * wect_freudenthal_build: c is a 2D cubical batch (shape, grid_off, intensity,
+ *   axis, axis_off as for wect_forward); outputs are device arrays sized by the
+ *   counts: coords [V,2] f32, vweights [V] f32, edges [E,2] and tris [F,3]
+ *   int32 (vertex ids local to their image), and the CSR offsets vert_off,
+ *   edge_off, tri_off [B+1] int64, ready for a wect_complex with top_dim 2.
+ *   Asynchronous and capture-safe (two kernels, no allocation).
+ */
+wect_status wect_freudenthal_counts(int32_t B, const int32_t* shape_host, int64_t counts[3]);
+wect_status wect_freudenthal_build(const wect_complex* c, float* coords, float* vweights, int32_t* edges,
+                                   int32_t* tris, int64_t* vert_off, int64_t* edge_off, int64_t* tri_off,
+                                   void* hip_stream);
+
+/*
  * ECF of images and volumes with the intensity as the vertex filter: the first
  * of the two ECFs of an image in the paper's Remark on them, i.e. the WECF of
  * Section "Computation of WECFs" for one vertex filter, f(v) = intensity(v).

@@ -92,6 +92,10 @@ def lib() -> ctypes.CDLL:
     L.wect_wecf_forward.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
                                     c_size_t, c_void_p]
     L.wect_wecf_forward.restype = c_int
+    L.wect_freudenthal_counts.argtypes = [c_int32, c_void_p, P(c_int64)]
+    L.wect_freudenthal_counts.restype = c_int
+    L.wect_freudenthal_build.argtypes = [P(WectComplex)] + [c_void_p] * 8
+    L.wect_freudenthal_build.restype = c_int
     L.wect_image_ecf_workspace_bytes.argtypes = [P(WectComplex)]
     L.wect_image_ecf_workspace_bytes.restype = c_size_t
     L.wect_image_ecf.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]

@@ -7,7 +7,7 @@ nothing here computes any part of the transform.
 from __future__ import annotations
 
 import ctypes
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -152,6 +152,7 @@ class CubicalBatch:
         self.B = int(B)
         self.total_voxels = int(intensity.numel())
         self.device = intensity.device
+        self.shape_host = None  # host copy of shape when known (set by from_host)
 
     @classmethod
     def from_host(cls, images: Sequence, device="cuda") -> "CubicalBatch":
@@ -175,9 +176,11 @@ class CubicalBatch:
             av.append(av[-1] + ax.size)
         T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
         inc = images[0].include_above
-        return cls(n, T(np.concatenate(flat)), T(np.array(shapes, np.int32)),
-                   T(np.array(gv, np.int64)) if B > 1 else None, T(np.concatenate(axes)),
-                   T(np.array(av, np.int64)) if B > 1 else None, inc, images[0].weighted, B)
+        out = cls(n, T(np.concatenate(flat)), T(np.array(shapes, np.int32)),
+                  T(np.array(gv, np.int64)) if B > 1 else None, T(np.concatenate(axes)),
+                  T(np.array(av, np.int64)) if B > 1 else None, inc, images[0].weighted, B)
+        out.shape_host = np.array(shapes, np.int32)  # for host-side sizes (builders)
+        return out
 
     def struct(self) -> L.WectComplex:
         c = L.WectComplex()
@@ -351,6 +354,37 @@ def wecf_forward(cx, fvals, thr, out: Optional[torch.Tensor] = None,
                                    _stream(cx.device))
     L.check(st, "wect_wecf_forward")
     return out
+
+
+def freudenthal_counts(shapes) -> Tuple[int, int, int]:
+    """Total vertices, edges and triangles of the Freudenthal complexes of
+    images with host shapes [B, 3] (n0, n1, 1)."""
+    sh = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(-1, 3))
+    out = (ctypes.c_int64 * 3)()
+    L.check(L.lib().wect_freudenthal_counts(int(sh.shape[0]), sh.ctypes.data, out), "wect_freudenthal_counts")
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def freudenthal_from_images(cx) -> "SimplicialBatch":
+    """The weighted Freudenthal complexes of a 2D image batch, built on the device:
+    vertex weights = intensities, simplex weight = the largest vertex weight
+    ('vertex_max'); see wect_freudenthal_build."""
+    if cx.n != 2:
+        raise ValueError("the Freudenthal builder takes 2D images")
+    shapes = cx.shape_host if getattr(cx, "shape_host", None) is not None else cx.shape.cpu().numpy()
+    V, E, F = freudenthal_counts(shapes)
+    dev = cx.device
+    coords = torch.empty((V, 2), dtype=torch.float32, device=dev)
+    vw = torch.empty(V, dtype=torch.float32, device=dev)
+    edges = torch.empty((E, 2), dtype=torch.int32, device=dev)
+    tris = torch.empty((F, 3), dtype=torch.int32, device=dev)
+    offs = [torch.empty(cx.B + 1, dtype=torch.int64, device=dev) for _ in range(3)]
+    c = cx.struct()
+    L.check(L.lib().wect_freudenthal_build(ctypes.byref(c), _ptr(coords), _ptr(vw), _ptr(edges), _ptr(tris),
+                                           _ptr(offs[0]), _ptr(offs[1]), _ptr(offs[2]), _stream(dev)),
+            "wect_freudenthal_build")
+    return SimplicialBatch(coords, [None, edges, tris], "vertex_max", [vw], offs[0], [None, offs[1], offs[2]],
+                           cx.B)
 
 
 def image_ecf_workspace_bytes(cx) -> int:

@@ -611,6 +611,47 @@ wect_status wect_wecf_forward(const wect_complex* c, const float* fvals, int32_t
   return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
 }
 
+wect_status wect_freudenthal_counts(int32_t B, const int32_t* shape_host, int64_t counts[3]) {
+  if (B < 1 || !shape_host || !counts) return WECT_ERR_ARG;
+  int64_t v = 0, e = 0, t = 0;
+  for (int32_t b = 0; b < B; ++b) {
+    const int64_t n0 = shape_host[3 * b], n1 = shape_host[3 * b + 1];
+    if (n0 < 1 || n1 < 1 || shape_host[3 * b + 2] != 1 || n0 * n1 > INT32_MAX) return WECT_ERR_ARG;
+    v += n0 * n1;
+    e += (n0 - 1) * n1 + n0 * (n1 - 1) + (n0 - 1) * (n1 - 1);
+    t += 2 * (n0 - 1) * (n1 - 1);
+  }
+  counts[0] = v;
+  counts[1] = e;
+  counts[2] = t;
+  return WECT_OK;
+}
+
+wect_status wect_freudenthal_build(const wect_complex* c, float* coords, float* vweights, int32_t* edges,
+                                   int32_t* tris, int64_t* vert_off, int64_t* edge_off, int64_t* tri_off,
+                                   void* hip_stream) {
+  if (!c || c->kind != WECT_CUBICAL || c->n != 2 || c->B < 1 || !c->shape || !c->axis) return WECT_ERR_ARG;
+  if (c->total_voxels < 0 || (c->B > 1 && (!c->grid_off || !c->axis_off))) return WECT_ERR_ARG;
+  if (!vert_off || !edge_off || !tri_off) return WECT_ERR_ARG;
+  if (c->total_voxels > 0 && (!c->intensity || !coords || !vweights || !edges || !tris)) return WECT_ERR_ARG;
+  Params p;
+  std::memset(&p, 0, sizeof(p));
+  p.kind = WECT_CUBICAL;
+  p.n = 2;
+  p.B = c->B;
+  p.shape = c->shape;
+  p.grid_off = c->grid_off;
+  p.intensity = c->intensity;
+  p.axis = c->axis;
+  p.axis_off = c->axis_off;
+  p.total_voxels = c->total_voxels;
+  if (hipError_t e = wect::launch_freudenthal(p, vert_off, edge_off, tri_off, coords, vweights, edges, tris,
+                                              static_cast<hipStream_t>(hip_stream));
+      e != hipSuccess)
+    return device_error(e, "Freudenthal builder");
+  return WECT_OK;
+}
+
 size_t wect_image_ecf_workspace_bytes(const wect_complex* c) {
   EcfPlan pl;
   if (ecf_plan(c, 0, nullptr, &pl) != WECT_OK) return 0;

@@ -62,6 +62,10 @@ hipError_t launch_forward_reduce(const Params& p, hipStream_t s);
 hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s);
 hipError_t launch_validate(const Params& p, int* flags, hipStream_t s);
+// Freudenthal complexes of a 2D image batch: CSR offsets (device), then the
+// per-pixel coordinates, weights, edges and triangles.
+hipError_t launch_freudenthal(const Params& p, int64_t* voff, int64_t* eoff, int64_t* toff, float* coords,
+                              float* vw, int32_t* edges, int32_t* tris, hipStream_t s);
 // Image ECF: main kernel (p.G blocks of `block` threads, when p.S > 0) and the
 // per-image finish (p.B blocks).
 hipError_t launch_image_ecf(const Params& p, int block, hipStream_t s);

@@ -1700,6 +1700,112 @@ __global__ __launch_bounds__(256) void k_vertex_buckets(Params p, int64_t nvals)
   }
 }
 
+// ---------------------------------------------------------------------------
+// device builder: the weighted Freudenthal complex of an image
+// ---------------------------------------------------------------------------
+//
+// Images become weighted simplicial complexes through the Freudenthal
+// triangulation, with vertex weights from the pixel intensities (Section
+// "Background", after the weighted simplicial complex definition).  Pixel
+// (i0, i1) of an n0 x n1 image is vertex i1 n0 + i0 at (axis0[i0], axis1[i1]);
+// edges are the (n0-1) n1 horizontal ones (row-major), the n0 (n1-1) vertical
+// ones, then the (n0-1)(n1-1) diagonals (i0,i1)-(i0+1,i1+1); triangles are
+// first every {(i0,i1), (i0+1,i1), (i0+1,i1+1)}, then every
+// {(i0,i1), (i0,i1+1), (i0+1,i1+1)}.
+
+// CSR offsets of the B complexes (one block; chunked scan over the images).
+__global__ __launch_bounds__(1024) void k_freudenthal_offsets(Params p, int64_t* voff, int64_t* eoff, int64_t* toff) {
+  __shared__ int64_t sv[1024], se[1024], st[1024];
+  const int B = p.B, tid = threadIdx.x, nt = blockDim.x;
+  const int per = (B + nt - 1) / nt;
+  const int b0 = min(B, tid * per), b1 = min(B, b0 + per);
+  auto sizes = [&](int b, int64_t& v, int64_t& e, int64_t& t) {
+    const int64_t n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1];
+    v = n0 * n1;
+    e = (n0 - 1) * n1 + n0 * (n1 - 1) + (n0 - 1) * (n1 - 1);
+    t = 2 * (n0 - 1) * (n1 - 1);
+  };
+  int64_t cv = 0, ce = 0, ct = 0;
+  for (int b = b0; b < b1; ++b) {
+    int64_t v, e, t;
+    sizes(b, v, e, t);
+    cv += v;
+    ce += e;
+    ct += t;
+  }
+  sv[tid] = cv;
+  se[tid] = ce;
+  st[tid] = ct;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {  // inclusive scan of the chunk totals
+    const int64_t av = tid >= o ? sv[tid - o] : 0, ae = tid >= o ? se[tid - o] : 0, at = tid >= o ? st[tid - o] : 0;
+    __syncthreads();
+    sv[tid] += av;
+    se[tid] += ae;
+    st[tid] += at;
+    __syncthreads();
+  }
+  int64_t ov = sv[tid] - cv, oe = se[tid] - ce, ot = st[tid] - ct;
+  for (int b = b0; b < b1; ++b) {
+    voff[b] = ov;
+    eoff[b] = oe;
+    toff[b] = ot;
+    int64_t v, e, t;
+    sizes(b, v, e, t);
+    ov += v;
+    oe += e;
+    ot += t;
+  }
+  if (tid == nt - 1) {
+    voff[B] = sv[tid];
+    eoff[B] = se[tid];
+    toff[B] = st[tid];
+  }
+}
+
+// One thread per pixel: its coordinates and weight, and the edges and
+// triangles it starts (those of the square to its upper right).
+__global__ __launch_bounds__(256) void k_freudenthal_build(Params p, const int64_t* eoff, const int64_t* toff,
+                                                           float* coords, float* vw, int32_t* edges, int32_t* tris) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < p.total_voxels; g += stride) {
+    const int b = find_complex(p, g, 1);  // cum_elems = grid_off (every pixel is a vertex)
+    const int64_t gb = cum_elems(p, b);
+    const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1];
+    const int v = (int)(g - gb);  // local vertex id (< 2^31)
+    const int i1 = v / n0, i0 = v - i1 * n0;
+    const float* ax0 = p.axis + (p.axis_off ? p.axis_off[b] : 0);
+    coords[2 * g] = ax0[i0];
+    coords[2 * g + 1] = ax0[n0 + i1];
+    vw[g] = (float)p.intensity[g];
+    const int64_t H = (int64_t)(n0 - 1) * n1, Vt = (int64_t)n0 * (n1 - 1), S = (int64_t)(n0 - 1) * (n1 - 1);
+    int32_t* E = edges + 2 * eoff[b];
+    int32_t* F = tris + 3 * toff[b];
+    if (i0 < n0 - 1) {
+      const int64_t k = (int64_t)i1 * (n0 - 1) + i0;
+      E[2 * k] = v;
+      E[2 * k + 1] = v + 1;
+    }
+    if (i1 < n1 - 1) {
+      const int64_t k = H + (int64_t)i1 * n0 + i0;
+      E[2 * k] = v;
+      E[2 * k + 1] = v + n0;
+    }
+    if (i0 < n0 - 1 && i1 < n1 - 1) {
+      const int64_t sq = (int64_t)i1 * (n0 - 1) + i0;
+      const int64_t k = H + Vt + sq;
+      E[2 * k] = v;
+      E[2 * k + 1] = v + n0 + 1;
+      F[3 * sq] = v;
+      F[3 * sq + 1] = v + 1;
+      F[3 * sq + 2] = v + n0 + 1;
+      F[3 * (S + sq)] = v;
+      F[3 * (S + sq) + 1] = v + n0;
+      F[3 * (S + sq) + 2] = v + n0 + 1;
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1844,6 +1950,18 @@ hipError_t launch_vertex_buckets(const Params& p, int64_t nvals, hipStream_t s) 
     if (hipError_t e = set_lds_limit(k_vertex_buckets<uint16_t>, lds); e != hipSuccess) return e;
     hipLaunchKernelGGL(k_vertex_buckets<uint16_t>, dim3((unsigned)blocks), dim3(256), lds, s, p, nvals);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_freudenthal(const Params& p, int64_t* voff, int64_t* eoff, int64_t* toff, float* coords,
+                              float* vw, int32_t* edges, int32_t* tris, hipStream_t s) {
+  hipLaunchKernelGGL(k_freudenthal_offsets, dim3(1), dim3(1024), 0, s, p, voff, eoff, toff);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  if (p.total_voxels <= 0) return hipSuccess;
+  int64_t blocks = (p.total_voxels + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_freudenthal_build, dim3((unsigned)blocks), dim3(256), 0, s, p, eoff, toff, coords, vw, edges,
+                     tris);
   return hipGetLastError();
 }
 

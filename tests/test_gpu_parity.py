@@ -578,3 +578,20 @@ def test_graph_replay_cubical_forward(W):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("T", [300, 301])
+def test_group_decomposition_many_thresholds(W, T):
+    """One block per group with long rows: the in-place chunked scan of the
+    directly written groups (vector stores when T is a multiple of 4)."""
+    ims = [synth.random_tiny_cubical(s, shp, include_above=60) for s, shp in
+           enumerate(((40, 33), (7, 51), (64, 9)))]
+    dirs, thr = synth.s1_directions(70), synth.uniform_thresholds(T, 1.8)
+    try:
+        W.set_launch(1024, 0, 0, W.DECOMP_GROUP)
+        _say(f"group decomposition, T={T}")
+        got = gpu_wect(W, ims, dirs, thr)
+    finally:
+        W.set_launch()
+    for b, C in enumerate(ims):
+        assert_match(got[b], oracle.wect(C, dirs, thr), C, f"image {b}")
