@@ -29,6 +29,9 @@ What it computes, and from which passage of the paper:
   arbitrary filter values per vertex: ``wecf``) and the ECF of an image, whose
   vertex filter is the intensity itself (Remark on the two ECFs of an image:
   ``image_ecf``).
+* The sigmoid relaxation of the WECT and its gradients with respect to
+  weights, coordinates and directions (the differentiable forms named as
+  future work in Section "Discussion"): submodule ``oracle.smooth``.
 
 The forward is the definition evaluated directly: for every direction the
 filter values of all cells are sorted (a library sort), the signed weights are
