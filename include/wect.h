@@ -254,6 +254,60 @@ wect_status wect_image_ecf(const wect_complex* c, const float* thr, int32_t T, i
                            void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * Sigmoid relaxation of the WECT (simplicial complexes), a differentiable form
+ * of the transform (the paper names differentiable transforms as future work,
+ * Section "Discussion", and cites the differentiable ECT among related
+ * software, Section "Related Work"):
+ *
+ *   S[b][p][q] = sum over simplices c of complex b of
+ *                (-1)^dim(c) w(c) sig(lam (thr[q] - f_p^max(c))),
+ *   sig(x) = 1 / (1 + exp(-x)),
+ *
+ * with f_p^max(c) the float32 maximum vertex height of c as in wect_forward.
+ * lam >= 0 is the sharpness (finite): as lam grows S tends to the WECT away
+ * from the cell values; lam = 0 gives half the weighted Euler characteristic.
+ *
+ * Numerics: a term with |lam (thr[q] - f)| above 17 is taken as 0 or w (error
+ * below exp(-17) |w| < 2^-24 |w|); inside that window sig is evaluated in
+ * float32 (hardware exp2 and reciprocal), each term w sig is rounded to a
+ * fixed-point grid of 2^-e with |w| 2^e < 2^30, and the terms are summed
+ * exactly in 64-bit integers, so the output does not depend on the order of
+ * the work and differs from the exact value by about 30 ulp of |w| per cell.
+ *
+ * c:    kind SIMPLICIAL, weights ONES, EXPLICIT float32 or VERTEX_MAX (EXPLICIT
+ *       int32 is WECT_ERR_UNSUPPORTED; cubical complexes likewise).
+ * g:    directions and thresholds as for wect_forward (thresholds non-decreasing).
+ * out:  [B, d, T] float32, overwritten.
+ * ws:   wect_smooth_workspace_bytes(c, g, lam) bytes (0 possible).
+ * Cost: about 34 / (lam * threshold spacing) sigmoid terms per cell and
+ * direction, plus the WECT's own work.
+ */
+size_t wect_smooth_workspace_bytes(const wect_complex* c, const wect_grid* g, float lam);
+wect_status wect_smooth_forward(const wect_complex* c, const wect_grid* g, float lam, float* out,
+                                void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Adjoint of wect_smooth_forward for L = sum grad_out[b][p][q] S[b][p][q]:
+ *   dL/dw(c)       = (-1)^dim(c) sum_{p,q} grad_out[p][q] sig_pq(c),
+ *   dL/df_p^max(c) = -(-1)^dim(c) w(c) lam sum_q grad_out[p][q] sig_pq(c) (1 - sig_pq(c)),
+ * and f_p^max(c) = <l(a), s_p> for the vertex a of c attaining the maximum
+ * height (the lowest vertex id among equal heights), so that the coordinates
+ * of a receive dL/df s_p and the direction s_p receives dL/df l(a).
+ *   grad_out:    [B, d, T] float32.
+ *   grad_coords: [count[0], n] float32 or NULL (not computed).
+ *   grad_dirs:   [d, n] float32 or NULL; sums over the whole batch.
+ *   grad_w:      EXPLICIT: 4 pointers, grad_w[i] = [count[i]] float32 or NULL.
+ *   grad_vertex: VERTEX_MAX: [count[0]] float32 or NULL; each simplex's weight
+ *                gradient goes to the lowest-numbered vertex of maximum weight.
+ * Window as in the forward.  Outputs are overwritten (cleared by kernels,
+ * then accumulated with float32 atomics: the order of the additions is not
+ * fixed).  No workspace.  Asynchronous and capture-safe.
+ */
+wect_status wect_smooth_backward(const wect_complex* c, const wect_grid* g, float lam, const float* grad_out,
+                                 float* grad_coords, float* grad_dirs, float* const grad_w[4],
+                                 float* grad_vertex, void* hip_stream);
+
+/*
  * Synchronous data check on `hip_stream`: CSR offsets and shapes consistent
  * with the counts, vertex ids in range, thresholds non-decreasing, axes
  * strictly increasing, no NaN/Inf in coordinates, directions, thresholds or

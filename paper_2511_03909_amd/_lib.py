@@ -7,7 +7,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
-from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_void_p
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libwect.so")
@@ -100,6 +100,13 @@ def lib() -> ctypes.CDLL:
     L.wect_image_ecf_workspace_bytes.restype = c_size_t
     L.wect_image_ecf.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]
     L.wect_image_ecf.restype = c_int
+    L.wect_smooth_workspace_bytes.argtypes = [P(WectComplex), P(WectGrid), c_float]
+    L.wect_smooth_workspace_bytes.restype = c_size_t
+    L.wect_smooth_forward.argtypes = [P(WectComplex), P(WectGrid), c_float, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.wect_smooth_forward.restype = c_int
+    L.wect_smooth_backward.argtypes = [P(WectComplex), P(WectGrid), c_float, c_void_p, c_void_p, c_void_p,
+                                       P(c_void_p), c_void_p, c_void_p]
+    L.wect_smooth_backward.restype = c_int
     _lib = L
     return L
 

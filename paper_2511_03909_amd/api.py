@@ -17,7 +17,8 @@ from . import _lib as L
 __all__ = [
     "Grid", "SimplicialBatch", "CubicalBatch", "wect_workspace_bytes", "wect_forward", "wect_backward",
     "wect_batched", "wect_validate", "set_launch", "get_launch", "profile_enable", "profile_read",
-    "WECTFunction", "wect", "WECT",
+    "WECTFunction", "wect", "WECT", "smooth_workspace_bytes", "smooth_forward", "smooth_backward",
+    "SmoothWECTFunction", "smooth_wect", "SmoothWECT",
 ]
 
 _WMODES = {"ones": L.WECT_W_ONES, "explicit": L.WECT_W_EXPLICIT, "vertex_max": L.WECT_W_VERTEX_MAX}
@@ -490,3 +491,109 @@ class WECT(torch.nn.Module):
         if weights:
             return wect(cx, grid, *weights)
         return wect_forward(cx, grid)
+
+
+# ---------------------------------------------------------------------------
+# sigmoid relaxation (differentiable in coordinates, directions and weights)
+# ---------------------------------------------------------------------------
+
+def _lam(lam) -> float:
+    lam = float(lam)
+    if not (lam >= 0.0) or lam == float("inf"):
+        raise ValueError("lam must be finite and >= 0")
+    return lam
+
+
+def smooth_workspace_bytes(cx, grid: Grid, lam: float) -> int:
+    c, g = cx.struct(), grid.struct()
+    return int(L.lib().wect_smooth_workspace_bytes(ctypes.byref(c), ctypes.byref(g), _lam(lam)))
+
+
+def smooth_forward(cx, grid: Grid, lam: float, out: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Sigmoid relaxation S [B, d, T] float32; see wect_smooth_forward in wect.h."""
+    lam = _lam(lam)
+    shape = (cx.B, grid.d, grid.T)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=cx.device)
+    else:
+        _check_tensor(out, "out", cx.device, torch.float32, shape)
+    need = smooth_workspace_bytes(cx, grid, lam)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
+    else:
+        _check_tensor(ws, "ws", cx.device)
+    c, g = cx.struct(), grid.struct()
+    st = L.lib().wect_smooth_forward(ctypes.byref(c), ctypes.byref(g), lam, _ptr(out), _ptr(ws),
+                                     ctypes.c_size_t(int(ws.numel()) * ws.element_size()), _stream(cx.device))
+    L.check(st, "wect_smooth_forward")
+    return out
+
+
+def smooth_backward(cx, grid: Grid, lam: float, grad_out: torch.Tensor, coords: bool = True, dirs: bool = True,
+                    weights: bool = True) -> dict:
+    """Adjoint of ``smooth_forward``: {"coords": [V, n] or None, "dirs": [d, n] or None,
+    "weights": list per dimension (explicit) / [V] (vertex_max) / None}."""
+    lam = _lam(lam)
+    grad_out = _grad_in(cx, grid, grad_out)
+    dev = cx.device
+    gx = torch.empty((cx.counts[0], cx.n), dtype=torch.float32, device=dev) if coords else None
+    gd = torch.empty((grid.d, cx.n), dtype=torch.float32, device=dev) if dirs else None
+    gw = gv = None
+    if weights and cx.wmode != "ones":
+        gw, gv = _grad_outputs(cx)
+    c, g = cx.struct(), grid.struct()
+    st = L.lib().wect_smooth_backward(ctypes.byref(c), ctypes.byref(g), lam, _ptr(grad_out), _ptr(gx), _ptr(gd),
+                                      _gw_array(gw), _ptr(gv), _stream(dev))
+    L.check(st, "wect_smooth_backward")
+    return {"coords": gx, "dirs": gd, "weights": gv if gv is not None else gw}
+
+
+class SmoothWECTFunction(torch.autograd.Function):
+    """S = relaxation(coords, dirs, weights) with gradients to all three."""
+
+    @staticmethod
+    def forward(ctx, cx, thr, lam, coords, dirs, *weights):
+        ws = [w.detach().contiguous() for w in weights] if weights else list(cx.weights)
+        cxw = SimplicialBatch(coords.detach().contiguous(), cx.simplices, cx.wmode, ws, cx.vert_off,
+                              cx.simp_off, cx.B)
+        grid = Grid(dirs.detach(), thr, device=coords.device)
+        ctx.cx, ctx.grid, ctx.lam, ctx.nw = cxw, grid, lam, len(weights)
+        return smooth_forward(cxw, grid, lam)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        need = ctx.needs_input_grad
+        r = smooth_backward(ctx.cx, ctx.grid, ctx.lam, grad_out, coords=need[3], dirs=need[4],
+                            weights=any(need[5:]))
+        gw = r["weights"]
+        if gw is None:
+            gw = [None] * ctx.nw
+        elif isinstance(gw, torch.Tensor):
+            gw = [gw]
+        return (None, None, None, r["coords"], r["dirs"], *gw)
+
+
+def smooth_wect(cx: SimplicialBatch, thr, lam: float, coords: torch.Tensor, dirs: torch.Tensor,
+                *weights: torch.Tensor) -> torch.Tensor:
+    """Differentiable relaxation S [B, d, T] of a simplicial batch whose
+    coordinates, directions and (float32) weights may require gradients."""
+    thr = torch.as_tensor(thr, dtype=torch.float32, device=coords.device)
+    return SmoothWECTFunction.apply(cx, thr, _lam(lam), coords, dirs, *weights)
+
+
+class SmoothWECT(torch.nn.Module):
+    """Layer form: learnable directions (optional), fixed thresholds and sharpness."""
+
+    def __init__(self, dirs, thr, lam: float, learn_dirs: bool = True):
+        super().__init__()
+        d = torch.as_tensor(dirs, dtype=torch.float32)
+        if learn_dirs:
+            self.dirs = torch.nn.Parameter(d)
+        else:
+            self.register_buffer("dirs", d)
+        self.register_buffer("thr", torch.as_tensor(thr, dtype=torch.float32))
+        self.lam = _lam(lam)
+
+    def forward(self, cx, coords, *weights):
+        return smooth_wect(cx, self.thr, self.lam, coords, self.dirs, *weights)

@@ -49,9 +49,6 @@ def build(asm_dir: str | None = None, verbose: bool = False) -> str:
         obj = os.path.join(tmp, src + ".o")
         cmd = [cc, f"--offload-arch={ARCH}", *COMMON, "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
-        if asm_dir and src.endswith(".hip"):
-            os.makedirs(asm_dir, exist_ok=True)
-            cmd += ["-save-temps=obj"] if False else []
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
@@ -63,6 +60,7 @@ def build(asm_dir: str | None = None, verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(out_tmp, LIB)
     if asm_dir:
+        os.makedirs(asm_dir, exist_ok=True)
         # device assembly of the kernels, for inspection
         cmd = [cc, f"--offload-arch={ARCH}", *COMMON, "-I", INCLUDE, "-I", CSRC, "--cuda-device-only", "-S",
                os.path.join(CSRC, "wect_kernels.hip"), "-o", os.path.join(asm_dir, "wect_kernels.s")]

@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cfloat>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -80,6 +82,7 @@ struct Plan {
   int G_fwd = 0, G_bwd = 0;
   int64_t S_fwd = 0, S_bwd = 0;
   int dg = 0, ngd = 0;
+  int sm_block = 0, sm_stage = 0;  // adjoint of the sigmoid relaxation
 };
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -88,8 +91,15 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Staged entries per tile and LDS bytes of the forward kernel for a block
 // size: the histogram and thresholds are fixed, the staging tile takes what is
 // left (at most one entry per thread, a multiple of 64).  stage = 0: no fit.
-void fwd_stage_lds(const wect_complex* c, const wect_grid* g, int block, int* stage, size_t* lds) {
-  const int acc_bytes = (c->kind == WECT_SIMPLICIAL && c->dtype == WECT_F32) ? 8 : 4;
+// Accumulator width of the forward: float32 weights and the sigmoid relaxation
+// accumulate in 64-bit fixed point, integer weights in 32 bits.
+int acc_bytes_of(const wect_complex* c, bool smooth) {
+  return (smooth || (c->kind == WECT_SIMPLICIAL && c->dtype == WECT_F32)) ? 8 : 4;
+}
+
+void fwd_stage_lds(const wect_complex* c, const wect_grid* g, int block, int* stage, size_t* lds,
+                   bool smooth = false) {
+  const int acc_bytes = acc_bytes_of(c, smooth);
   const size_t fixed = wect::forward_lds_fixed(g->T, c->kind, acc_bytes);
   const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
   int st = fixed + 64 * entry > kLdsLimit ? 0 : (int)std::min<size_t>(block, (kLdsLimit - fixed) / entry) / 64 * 64;
@@ -101,12 +111,12 @@ void fwd_stage_lds(const wect_complex* c, const wect_grid* g, int block, int* st
 // they reach 16 or more resident wavefronts per CU (several independent blocks
 // overlap their staging and histogram phases); otherwise the size with the
 // most resident wavefronts (32 wave slots and 160 KiB of LDS per CU) wins.
-int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only) {
+int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only, bool smooth) {
   if (bwd_only || g->T <= 0) return 1024;
   auto waves_of = [&](int b) {
     int stage = 0;
     size_t lds = 0;
-    fwd_stage_lds(c, g, b, &stage, &lds);
+    fwd_stage_lds(c, g, b, &stage, &lds, smooth);
     if (stage == 0) return 0;
     const int by_lds = (int)((160 * 1024) / (lds + 1024));
     return std::min(32 / (b / kW), by_lds) * (b / kW);
@@ -124,7 +134,10 @@ int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only) {
 }
 
 // Check host metadata and build the plan.  need_bwd: backward requested.
-wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl) {
+// smooth: forward of the sigmoid relaxation (fixed-point accumulation for
+// every weight mode, float32 output); its adjoint is planned by smooth_plan.
+wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl,
+                      bool smooth = false) {
   if (!c || !g) return WECT_ERR_ARG;
   if (c->kind != WECT_SIMPLICIAL && c->kind != WECT_CUBICAL) return WECT_ERR_ARG;
   if (c->B < 1) return WECT_ERR_ARG;
@@ -224,7 +237,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   const bool auto_group = need_fwd && decomp == 0 && g->T > 0 && S_fwd > 0 && groups_fwd >= cus &&
                           S_fwd >= groups_fwd * 8 * 1024;
   int block = g_block.load();
-  if (!block) block = auto_group ? 1024 : auto_block(c, g, need_bwd && !need_fwd);
+  if (!block) block = auto_group ? 1024 : auto_block(c, g, need_bwd && !need_fwd, smooth);
   pl->block = block;
   pl->elems = elems;
   p.ntiles = ntiles;
@@ -241,10 +254,10 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
 
   if (need_fwd && g->d > 0 && g->T > 0) {
     // forward LDS: histogram [T+1][64] + threshold pairs + staged entries
-    const int acc_bytes = (c->kind == WECT_SIMPLICIAL && c->dtype == WECT_F32) ? 8 : 4;
+    const int acc_bytes = acc_bytes_of(c, smooth);
     int stage = 0;
     size_t lds = 0;
-    fwd_stage_lds(c, g, block, &stage, &lds);
+    fwd_stage_lds(c, g, block, &stage, &lds, smooth);
     if (stage == 0) return WECT_ERR_UNSUPPORTED;
     p.stage = stage;
     pl->lds_fwd = lds;
@@ -269,9 +282,10 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->split = !pl->group_mode && spg > 16;  // kFusedSlots in the kernels
     pl->partial_bytes = align256((size_t)slots * slot_bytes);
     pl->dsum_bytes = pl->split ? align256((size_t)groups * slot_bytes) : 0;
-    pl->absmax_bytes = acc_bytes == 8 ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
+    const bool absmax = acc_bytes == 8 && c->wmode != WECT_W_ONES;  // unit weights: M = 1
+    pl->absmax_bytes = absmax ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
     pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes;
-    p.nabsmax = acc_bytes == 8 ? wect::kAbsmaxSlots : 0;
+    p.nabsmax = absmax ? wect::kAbsmaxSlots : 0;
     p.cells_total = (double)std::max<int64_t>(elems, 1);
   }
   if (need_bwd && g->d > 0 && g->T > 0) {
@@ -417,6 +431,87 @@ wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, cons
   if (pl->ws_fwd > 0 || (m > 0 && T > 0)) {
     pl->vb_bytes = align256((size_t)c->count[0] * (size_t)m * (size_t)pl->p.vb_bytes);
     pl->ws_fwd += pl->vb_bytes;
+  }
+  return WECT_OK;
+}
+
+// Sigmoid relaxation (simplicial): the forward is planned like the WECT's with
+// fixed-point accumulation; the adjoint takes one direction tile per block
+// pass (g and its reverse scan in LDS) over the stream of ntiles x cells.
+wect_status smooth_plan(const wect_complex* c, const wect_grid* g, float lam, bool need_fwd, bool need_bwd,
+                        Plan* pl) {
+  if (!c || !g) return WECT_ERR_ARG;
+  if (!(lam >= 0.0f) || !std::isfinite(lam)) return WECT_ERR_ARG;
+  if (c->kind != WECT_SIMPLICIAL) return WECT_ERR_UNSUPPORTED;
+  if (c->wmode == WECT_W_EXPLICIT && c->dtype != WECT_F32) return WECT_ERR_UNSUPPORTED;
+  if (wect_status st = make_plan(c, g, need_fwd, false, pl, true); st != WECT_OK) return st;
+  Params& p = pl->p;
+  p.smooth = 1;
+  p.dtype = WECT_F32;  // float32 output from 64-bit fixed point
+  p.sm_lam = lam;
+  p.sm_k = (float)((double)lam * 1.4426950408889634);  // lam log2(e)
+  const double r = lam > 0.0f ? wect::kSmoothW / (double)lam : (double)FLT_MAX;
+  p.sm_r = (float)std::min(r, (double)FLT_MAX);
+  if (need_bwd && g->d > 0 && g->T > 0) {
+    int block = g_block.load();
+    if (!block) block = 1024;
+    int stage = block;
+    while (stage > 64 && wect::smooth_backward_lds_bytes(g->T, stage) > kLdsLimit) stage /= 2;
+    if (wect::smooth_backward_lds_bytes(g->T, stage) > kLdsLimit) return WECT_ERR_UNSUPPORTED;
+    const size_t lds = wect::smooth_backward_lds_bytes(g->T, stage);
+    DeviceInfo di;
+    const int cus = device_info(&di) ? di.cus : 256;
+    const int user = g_bpc.load();
+    const int64_t bpc = user > 0 ? user
+                                 : std::max<int64_t>(1, std::min<int64_t>(32 / (block / kW),
+                                                                          (int64_t)((160 * 1024) / (lds + 1024))));
+    const int64_t S = (int64_t)p.ntiles * pl->elems;
+    int64_t G = std::min<int64_t>((int64_t)cus * bpc, std::max<int64_t>(1, ceil_div(S, std::max(1, g_min_items.load()))));
+    G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
+    pl->sm_block = block;
+    pl->sm_stage = stage;
+    pl->lds_bwd = lds;
+    pl->G_bwd = (int)G;
+    pl->S_bwd = S;
+  }
+  return WECT_OK;
+}
+
+wect_status run_smooth_backward(const Plan& pl0, const float* grad_out, float* grad_coords, float* grad_dirs,
+                                float* const grad_w[4], float* grad_vertex, hipStream_t s) {
+  Plan pl = pl0;
+  Params& p = pl.p;
+  if (!grad_out && (int64_t)p.B * p.d * p.T > 0) return WECT_ERR_ARG;
+  p.grad_out = grad_out;
+  p.grad_coords = grad_coords;
+  p.grad_dirs = grad_dirs;
+  if (p.wmode == WECT_W_VERTEX_MAX) p.grad_vertex = grad_vertex;
+  else if (p.wmode == WECT_W_EXPLICIT)
+    for (int i = 0; i < 4; ++i) p.grad_w[i] = grad_w ? grad_w[i] : nullptr;
+  p.G = pl.G_bwd;
+  p.S = pl.S_bwd;
+  p.stage = pl.sm_stage;
+  const bool work = p.d > 0 && p.T > 0 && p.S > 0;
+  // explicit-weight gradients are written once when there is one direction tile
+  p.bwd_atomic = p.ntiles > 1 ? 1 : 0;
+  auto zero = [&](float* x, int64_t n) { return x ? wect::launch_fill_zero(x, n, s) : hipSuccess; };
+  if (zero(grad_coords, p.count[0] * (int64_t)p.n) != hipSuccess) return WECT_ERR_DEVICE;
+  if (zero(grad_dirs, (int64_t)p.d * p.n) != hipSuccess) return WECT_ERR_DEVICE;
+  if (p.wmode == WECT_W_VERTEX_MAX && zero(grad_vertex, p.count[0]) != hipSuccess) return WECT_ERR_DEVICE;
+  if (p.wmode == WECT_W_EXPLICIT && (p.bwd_atomic || !work)) {
+    for (int i = 0; i <= p.top_dim; ++i)
+      if (zero(p.grad_w[i], p.count[i]) != hipSuccess) return WECT_ERR_DEVICE;
+  }
+  if (!work) return WECT_OK;
+  const bool prof = g_profile.load() != 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
+  if (hipError_t e = wect::launch_smooth_backward(p, pl.sm_block, pl.lds_bwd, s); e != hipSuccess)
+    return device_error(e, "relaxation adjoint kernel");
+  if (prof) {
+    if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({e0, e1, 1});
   }
   return WECT_OK;
 }
@@ -650,6 +745,27 @@ wect_status wect_freudenthal_build(const wect_complex* c, float* coords, float* 
       e != hipSuccess)
     return device_error(e, "Freudenthal builder");
   return WECT_OK;
+}
+
+size_t wect_smooth_workspace_bytes(const wect_complex* c, const wect_grid* g, float lam) {
+  Plan pl;
+  if (smooth_plan(c, g, lam, true, false, &pl) != WECT_OK) return 0;
+  return pl.ws_fwd;
+}
+
+wect_status wect_smooth_forward(const wect_complex* c, const wect_grid* g, float lam, float* out, void* ws,
+                                size_t ws_bytes, void* hip_stream) {
+  Plan pl;
+  if (wect_status st = smooth_plan(c, g, lam, true, false, &pl); st != WECT_OK) return st;
+  return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
+wect_status wect_smooth_backward(const wect_complex* c, const wect_grid* g, float lam, const float* grad_out,
+                                 float* grad_coords, float* grad_dirs, float* const grad_w[4], float* grad_vertex,
+                                 void* hip_stream) {
+  Plan pl;
+  if (wect_status st = smooth_plan(c, g, lam, false, true, &pl); st != WECT_OK) return st;
+  return run_smooth_backward(pl, grad_out, grad_coords, grad_dirs, grad_w, grad_vertex, (hipStream_t)hip_stream);
 }
 
 size_t wect_image_ecf_workspace_bytes(const wect_complex* c) {

@@ -54,12 +54,25 @@ struct Params {
   float* grad_w[4];
   float* grad_vertex;
   int32_t bwd_atomic;            // 1: accumulate with atomics (output pre-zeroed)
+  // sigmoid relaxation: sig(lam (thr - h)) in place of the step [h <= thr]
+  int32_t smooth;                // 1: smooth forward / adjoint
+  float sm_lam;                  // lam
+  float sm_k;                    // lam log2(e), the exponent scale for exp2
+  float sm_r;                    // window half-width in height units (kSmoothW / lam, capped at FLT_MAX)
+  float* grad_coords;            // smooth adjoint: [count0, n], accumulated (pre-zeroed); may be null
+  float* grad_dirs;              // smooth adjoint: [d, n], accumulated (pre-zeroed); may be null
 };
+
+// Sigmoid terms with |lam (thr - h)| > kSmoothW are taken as 0 (below) or 1
+// (above): each such term is then off by less than exp(-17) < 2^-24.
+constexpr double kSmoothW = 17.0;
 
 // Launchers (enqueue only, return hipError_t of the launch).
 hipError_t launch_forward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 hipError_t launch_forward_reduce(const Params& p, hipStream_t s);
 hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+// Adjoint of the sigmoid relaxation (p.G blocks over p.S = ntiles * cells).
+hipError_t launch_smooth_backward(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_zero(float* ptr, int64_t n, hipStream_t s);
 hipError_t launch_validate(const Params& p, int* flags, hipStream_t s);
 // Freudenthal complexes of a 2D image batch: CSR offsets (device), then the
@@ -80,6 +93,7 @@ hipError_t launch_vertex_buckets(const Params& p, int64_t nvals, hipStream_t s);
 size_t forward_lds_fixed(int T, int kind, int acc_bytes);
 size_t forward_entry_bytes(int kind, int n);
 size_t backward_lds_bytes(int T, int stage, int dg);
+size_t smooth_backward_lds_bytes(int T, int stage);
 
 constexpr int kAbsmaxSlots = 256;  // 64 blocks x 4 weight arrays
 

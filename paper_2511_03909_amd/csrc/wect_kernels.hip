@@ -277,6 +277,41 @@ __device__ __forceinline__ void hist_entries(ACC* col, int first, int step, int 
   }
 }
 
+// Logistic sigmoid 1 / (1 + 2^-x) of x = lam (thr - h) log2(e); also returns
+// e = 2^-x, from which sig (1 - sig) = e sig^2 follows without cancellation.
+__device__ __forceinline__ float sigmoid2(float x, float& e) {
+  e = __builtin_amdgcn_exp2f(-x);
+  return __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// Relaxation: the entry's signed fixed-point weight C is spread over the
+// thresholds.  Inside its window [lo, hi) = {q : |thr[q] - h| <= R} the entry
+// contributes F_q = round(C sig(lam (thr[q] - h))) at threshold q, and from hi
+// on all of C.  The histogram holds differences (F_lo at lo, F_q - F_{q-1} at
+// q, C - F_{hi-1} at hi), so the threshold scan that follows returns exactly
+// these values.  |C| < 2^30, so every F_q and difference fits in int32.
+template <bool FAST, typename Entry>
+__device__ __forceinline__ void smooth_entries(uint64_t* col, int first, int step, int ne, const Thr& th, float R,
+                                               float kap, Entry entry) {
+  for (int e = first; e < ne; e += step) {
+    float h;
+    uint64_t C;
+    entry(e, h, C);
+    const int lo = thr_index<FAST>(h - R, th);
+    const int hi = thr_index<FAST>(next_up(h + R), th);
+    const float cf = (float)(int32_t)(uint32_t)C;
+    int prev = 0;
+    for (int q = lo; q < hi; ++q) {
+      float ex;
+      const float sg = sigmoid2((th.P[q + 1] - h) * kap, ex);
+      const int F = (int)__builtin_rintf(cf * sg);
+      lds_add(&col[q * W], (uint64_t)(int64_t)(F - prev));
+      prev = F;
+    }
+    lds_add(&col[hi * W], C - (uint64_t)(int64_t)prev);
+  }
+}
+
 // Sum over the 64 lanes of a wavefront: rotate-and-add inside each row of 16
 // lanes (DPP row_ror), then add the four row sums.
 __device__ __forceinline__ float wave_sum(float v) {
@@ -407,14 +442,25 @@ struct SimpLayout {
 // largest |w| and C the number of cells, every sum of rounded weights stays
 // below C * (M 2^e + 1/2) < 2^63.  Computed identically by every block from
 // the per-block maxima written by k_absmax.
+//
+// The sigmoid relaxation also rounds every term w sig to this scale in int32
+// arithmetic, so there the scale is capped further to keep M 2^e < 2^30 (unit
+// weights: M = 1).
 __device__ __forceinline__ int fixed_exp(const Params& p) {
   float M = 0.0f;
+  if (p.smooth && p.wmode == WM_ONES) M = 1.0f;
   for (int i = 0; i < p.nabsmax; ++i) M = fmaxf(M, p.absmax[i]);
   const double X = (double)M * p.cells_total;
   if (!(X > 0.0) || !isfinite(X)) return 0;
   int ex = 0;
   (void)frexp(X, &ex);  // X = f 2^ex, f in [0.5, 1): floor(log2 X) = ex - 1
-  return 61 - (ex - 1);
+  int e = 61 - (ex - 1);
+  if (p.smooth) {
+    int em = 0;
+    (void)frexp((double)M, &em);  // M < 2^em
+    e = min(e, 30 - em);
+  }
+  return e;
 }
 
 __device__ __forceinline__ uint64_t to_fixed(float w, int e) {
@@ -463,7 +509,10 @@ struct SimpStager {
     for (int k = L::NV * L::NC; k < L::WOFF; ++k) e[k] = 0.0f;
     e[L::OOFF] = 0.0f;
     if constexpr (WM == WM_ONES) {
-      if constexpr (FWD) put_weight(ACC(1));
+      if constexpr (FWD) {
+        if constexpr (sizeof(ACC) == 8) put_weight(to_fixed(1.0f, fexp));  // relaxation: fixed point
+        else put_weight(ACC(1));
+      }
     } else if constexpr (WM == WM_EXPLICIT) {
       if constexpr (FWD) {
         const WT w = ((const WT*)p.weights[DIM])[row];
@@ -563,7 +612,7 @@ __device__ __forceinline__ void filter_hist(ACC* col, const float* stage, int fi
 // one complex: stage TS simplices at a time, then every wavefront adds its
 // share of them to the LDS histogram.  Indices are prefetched one tile ahead
 // of the coordinate gather, which runs one tile ahead of the histogram.
-template <int N, int DIM, int WM, typename WT, bool FAST>
+template <int N, int DIM, int WM, typename WT, bool FAST, bool SM>
 __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
                                float sx, float sy, float sz, int fcol, typename AccOf<WT>::T* hist, float* stage,
                                const Thr& th, int fexp) {
@@ -609,7 +658,15 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
       for (int j = 0; j < L::NV; ++j) nidx[j] = tmp.idx[j];
     }
     // histogram of tile t: each wavefront takes adjacent pairs of entries
-    if constexpr (N == 0) {
+    // (relaxation: every nw-th entry, each spread over its window)
+    if constexpr (SM) {
+      static_assert(sizeof(ACC) == 8 && N > 0, "relaxation: fixed-point weights and coordinates");
+      smooth_entries<FAST>(hist + lane, wave, nw, cnt, th, p.sm_r, p.sm_k, [&](int e, float& h, uint64_t& C) {
+        const float* E = stage + e * L::STRIDE;
+        h = max_height<N, DIM>(E, sx, sy, sz);
+        C = load_weight<ACC>(E + L::WOFF);
+      });
+    } else if constexpr (N == 0) {
       if (p.vb_bytes == 1)
         filter_hist<DIM, uint8_t, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, (const uint8_t*)p.vbuckets, p.d,
                                           fcol);
@@ -628,15 +685,15 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
   __syncthreads();
 }
 
-template <int N, int WM, typename WT, bool FAST>
+template <int N, int WM, typename WT, bool FAST, bool SM>
 __device__ __forceinline__ void simp_fwd_dim(int dim, const Params& p, int64_t lo, int64_t hi, int64_t voff,
                                              int64_t soff, float sx, float sy, float sz, int fcol,
                                              typename AccOf<WT>::T* hist, float* stage, const Thr& th, int fexp) {
   switch (dim) {
-    case 0: simp_fwd_range<N, 0, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
-    case 1: simp_fwd_range<N, 1, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
-    case 2: simp_fwd_range<N, 2, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
-    default: simp_fwd_range<N, 3, WM, WT, FAST>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    case 0: simp_fwd_range<N, 0, WM, WT, FAST, SM>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    case 1: simp_fwd_range<N, 1, WM, WT, FAST, SM>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    case 2: simp_fwd_range<N, 2, WM, WT, FAST, SM>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
+    default: simp_fwd_range<N, 3, WM, WT, FAST, SM>(p, lo, hi, voff, soff, sx, sy, sz, fcol, hist, stage, th, fexp); break;
   }
 }
 
@@ -764,7 +821,7 @@ __device__ __forceinline__ size_t align_up(size_t x, size_t a) { return (x + a -
 // forward, simplicial
 // ---------------------------------------------------------------------------
 
-template <int N, int WM, typename WT>
+template <int N, int WM, typename WT, bool SM>
 __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
   using ACC = typename AccOf<WT>::T;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -809,11 +866,11 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
       if (lo < hi) {
         const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
         if (th.fast)
-          simp_fwd_dim<N, WM, WT, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, fcol, hist, stage, th,
-                                        fexp);
+          simp_fwd_dim<N, WM, WT, true, SM>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, fcol, hist, stage,
+                                            th, fexp);
         else
-          simp_fwd_dim<N, WM, WT, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, fcol, hist, stage, th,
-                                         fexp);
+          simp_fwd_dim<N, WM, WT, false, SM>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, fcol, hist, stage,
+                                             th, fexp);
       }
       dlo = dhi;
     }
@@ -1422,6 +1479,234 @@ __global__ __launch_bounds__(1024) void k_simp_bwd(Params p) {
 }
 
 // ---------------------------------------------------------------------------
+// adjoint of the sigmoid relaxation
+// ---------------------------------------------------------------------------
+//
+// S[p][q] = sum_c s(c) sig(lam (thr[q] - h_p(c))), s(c) = (-1)^dim w(c), and
+// h_p(c) = <l(a), s_p> for the vertex a of c attaining the maximum height
+// (lowest vertex id among equal heights).  For L = <g, S>, per cell and
+// direction:
+//   u_p  = sum_q g[q] sig_q                      (dL/ds(c) from direction p)
+//   dh_p = -s(c) lam sum_q g[q] sig_q (1 - sig_q) (dL/dh_p(c))
+// Inside the window sig is evaluated; above it sig = 1, so the tail of u is
+// G[hi] = sum_{q >= hi} g[q]; below it sig = 0.  Then
+//   dL/dw(c) = (-1)^dim sum_p u_p, dL/dl(a) += sum_p dh_p s_p,
+//   dL/ds_p += dh_p l(a) (summed over cells in registers, one lane per p).
+// The block holds one direction tile: g and G as [T(+1)][64] columns in LDS
+// and the staged cells ([coordinates, global vertex rows, signed weight,
+// owner]).  The 1 + (dim+1) n per-cell sums over the 64 lanes (u, and dh_p s_p
+// placed in the slot of the lane's argmax vertex) go through the eight-value
+// reduce-scatter; lanes 0..7 then issue the atomic adds.
+
+template <int N, int DIM>
+struct SmLayout {
+  static constexpr int NV = DIM + 1;
+  static constexpr int IDOFF = NV * N;     // global vertex rows
+  static constexpr int COFF = IDOFF + NV;  // signed weight (float)
+  static constexpr int OOFF = COFF + 1;    // owner vertex (vertex-max weights, local id)
+  static constexpr int STRIDE = OOFF + 1;
+};
+constexpr int kSmMaxStride = 18;  // 4 vertices x 3 coordinates + 4 ids + weight + owner
+
+template <int N, int DIM, int WM>
+__device__ __forceinline__ void sm_stage(const Params& p, int64_t row, int64_t lrow, int64_t voff, float* dst) {
+  using L = SmLayout<N, DIM>;
+  int idx[L::NV];
+  if constexpr (DIM == 0) {
+    idx[0] = (int)lrow;
+  } else {
+    const int32_t* sp = p.simp[DIM] + row * L::NV;
+#pragma unroll
+    for (int j = 0; j < L::NV; ++j) idx[j] = sp[j];
+  }
+#pragma unroll
+  for (int j = 0; j < L::NV; ++j) {
+    const int64_t gid = voff + idx[j];
+    const float* c = p.coords + gid * N;
+#pragma unroll
+    for (int k = 0; k < N; ++k) dst[j * N + k] = c[k];
+    dst[L::IDOFF + j] = bitcast<float>((int32_t)gid);
+  }
+  float w = 1.0f;
+  int own = idx[0];
+  if constexpr (WM == WM_EXPLICIT) {
+    w = ((const float*)p.weights[DIM])[row];
+  } else if constexpr (WM == WM_VMAX) {
+    const float* vw = (const float*)p.weights[0];
+    w = vw[voff + idx[0]];
+#pragma unroll
+    for (int j = 1; j < L::NV; ++j) {
+      const float x = vw[voff + idx[j]];
+      if (x > w || (x == w && idx[j] < own)) { w = x; own = idx[j]; }
+    }
+  }
+  dst[L::COFF] = (DIM & 1) ? -w : w;
+  dst[L::OOFF] = bitcast<float>(own);
+}
+
+template <int N, int DIM, int WM, bool FAST>
+__device__ __forceinline__ void sm_bwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
+                                             float sx, float sy, float sz, const float* g, const float* Gs,
+                                             float* stage, const Thr& th, float (&gd)[3]) {
+  using L = SmLayout<N, DIM>;
+  constexpr int NVAL = 1 + L::NV * N;
+  constexpr int NCH = (NVAL + 7) / 8;
+  const int tid = threadIdx.x, lane = tid & (W - 1);
+  const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
+  const int TS = p.stage;
+  const float R = p.sm_r, kap = p.sm_k, lam = p.sm_lam;
+  const float sdir[3] = {sx, sy, sz};
+  for (int64_t t0 = lo; t0 < hi; t0 += TS) {
+    const int cnt = (int)mn64(TS, hi - t0);
+    if (tid < cnt) sm_stage<N, DIM, WM>(p, soff + t0 + tid, t0 + tid, voff, stage + tid * L::STRIDE);
+    __syncthreads();
+    for (int e = wave; e < cnt; e += nw) {
+      const float* E = stage + e * L::STRIDE;
+      // maximum height and the vertex slot attaining it (lowest id on ties)
+      float h = height<N>(E, sx, sy, sz);
+      int a = 0;
+      int id = bitcast<int>(E[L::IDOFF]);
+#pragma unroll
+      for (int j = 1; j < L::NV; ++j) {
+        const float hj = height<N>(E + j * N, sx, sy, sz);
+        const int idj = bitcast<int>(E[L::IDOFF + j]);
+        if (hj > h || (hj == h && idj < id)) { h = hj; a = j; id = idj; }
+      }
+      const float c = E[L::COFF];
+      const int qlo = thr_index<FAST>(h - R, th);
+      const int qhi = thr_index<FAST>(next_up(h + R), th);
+      float u = Gs[qhi * W + lane], v = 0.0f;
+      for (int q = qlo; q < qhi; ++q) {
+        float ex;
+        const float sg = sigmoid2((th.P[q + 1] - h) * kap, ex);
+        const float gq = g[q * W + lane];
+        u = __builtin_fmaf(gq, sg, u);
+        v = __builtin_fmaf(gq, ex * sg * sg, v);
+      }
+      const float dh = -c * lam * v;
+#pragma unroll
+      for (int k = 0; k < N; ++k) gd[k] = __builtin_fmaf(dh, E[a * N + k], gd[k]);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        float v8[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int ix = ch * 8 + i;
+          if (ix == 0) v8[i] = u;
+          else if (ix < NVAL) v8[i] = a == (ix - 1) / N ? dh * sdir[(ix - 1) % N] : 0.0f;
+          else v8[i] = 0.0f;
+        }
+        const float tot = sum_scatter8(v8);
+        const int ix = ch * 8 + lane;
+        if (lane < 8 && ix < NVAL) {
+          if (ix == 0) {
+            const float gw = (DIM & 1) ? -tot : tot;
+            const int64_t row = soff + t0 + e;
+            if constexpr (WM == WM_VMAX) {
+              if (p.grad_vertex) atomicAdd(p.grad_vertex + voff + bitcast<int>(E[L::OOFF]), gw);
+            } else if constexpr (WM == WM_EXPLICIT) {
+              float* gwp = p.grad_w[DIM];
+              if (gwp) {
+                if (p.bwd_atomic) atomicAdd(gwp + row, gw);
+                else gwp[row] = gw;
+              }
+            }
+          } else if (p.grad_coords) {
+            const int j = (ix - 1) / N, k = (ix - 1) - j * N;
+            atomicAdd(p.grad_coords + (int64_t)bitcast<int>(E[L::IDOFF + j]) * N + k, tot);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, int WM, bool FAST>
+__device__ __forceinline__ void sm_bwd_dim(int dim, const Params& p, int64_t lo, int64_t hi, int64_t voff,
+                                           int64_t soff, float sx, float sy, float sz, const float* g,
+                                           const float* Gs, float* stage, const Thr& th, float (&gd)[3]) {
+  switch (dim) {
+    case 0: sm_bwd_range<N, 0, WM, FAST>(p, lo, hi, voff, soff, sx, sy, sz, g, Gs, stage, th, gd); break;
+    case 1: sm_bwd_range<N, 1, WM, FAST>(p, lo, hi, voff, soff, sx, sy, sz, g, Gs, stage, th, gd); break;
+    case 2: sm_bwd_range<N, 2, WM, FAST>(p, lo, hi, voff, soff, sx, sy, sz, g, Gs, stage, th, gd); break;
+    default: sm_bwd_range<N, 3, WM, FAST>(p, lo, hi, voff, soff, sx, sy, sz, g, Gs, stage, th, gd); break;
+  }
+}
+
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_smooth_bwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T, T1 = T + 1;
+  float* g = (float*)smem;                        // [T][64]
+  float* Gs = g + (size_t)T * W;                  // [T+1][64]
+  float* P = Gs + (size_t)T1 * W;                 // [T+1]
+  float* stage = (float*)((unsigned char*)P + align_up((size_t)T1 * 4, 16));
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  __syncthreads();
+
+  const int k = blockIdx.x;
+  int64_t pos = block_start(k, p.S, p.G);
+  const int64_t end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return;
+  const int gpc = p.ntiles;
+  int b = find_complex(p, pos, gpc);
+  const int tid = threadIdx.x, lane = tid & (W - 1), wave = tid >> 6;
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int t = (int)((pos - base) / nb);  // direction tile
+    const int64_t e0 = (pos - base) - (int64_t)t * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    const int gp = t * W + lane;
+    float sx, sy, sz;
+    load_dir(p, gp, sx, sy, sz);
+    // the tile's rows of grad_out (read along q by the whole block), then the
+    // reverse scan G[j] = sum_{q >= j} g[q] (G[T] = 0) by wavefront 0, in float64
+    __syncthreads();
+    for (int i = tid; i < W * T; i += blockDim.x) {
+      const int r = i / T, q = i - r * T;
+      const int dir = t * W + r;
+      g[(size_t)q * W + r] = dir < p.d ? p.grad_out[((int64_t)b * p.d + dir) * T + q] : 0.0f;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      Gs[(size_t)T * W + lane] = 0.0f;
+      double acc = 0.0;
+      for (int q = T - 1; q >= 0; --q) {
+        acc += (double)g[(size_t)q * W + lane];
+        Gs[(size_t)q * W + lane] = (float)acc;
+      }
+    }
+    __syncthreads();
+    float gd[3] = {0.0f, 0.0f, 0.0f};
+    const int64_t voff = off_or(p.vert_off, b, p.count[0]);
+    int64_t dlo = 0;
+    for (int dim = 0; dim <= p.top_dim; ++dim) {
+      int64_t kd = (dim == 0) ? (off_or(p.vert_off, b + 1, p.count[0]) - voff)
+                              : (off_or(p.simp_off[dim], b + 1, p.count[dim]) - off_or(p.simp_off[dim], b, p.count[dim]));
+      const int64_t dhi = dlo + kd;
+      const int64_t lo = mx64(e0, dlo), hi = mn64(e1, dhi);
+      if (lo < hi) {
+        const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
+        if (th.fast) sm_bwd_dim<N, WM, true>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, g, Gs, stage, th, gd);
+        else sm_bwd_dim<N, WM, false>(dim, p, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, g, Gs, stage, th, gd);
+      }
+      dlo = dhi;
+    }
+    if (p.grad_dirs && gp < p.d) {
+#pragma unroll
+      for (int kk = 0; kk < N; ++kk) atomicAdd(p.grad_dirs + (int64_t)gp * N + kk, gd[kk]);
+    }
+    pos += e1 - e0;
+    if (e1 == nb && t == gpc - 1) ++b;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
 
@@ -1877,16 +2162,22 @@ size_t backward_lds_bytes(int T, int stage, int dg) {
   return g + pairs + (size_t)stage * kMaxStride * 4;
 }
 
+size_t smooth_backward_lds_bytes(int T, int stage) {
+  size_t cols = (size_t)(2 * T + 1) * W * 4;
+  size_t pairs = ((size_t)(T + 1) * 4 + 15) / 16 * 16;
+  return cols + pairs + (size_t)stage * kSmMaxStride * 4;
+}
+
 static size_t reduce_lds_bytes(int T) {
   size_t lsz = (size_t)W * (T + 1) * 4;
   lsz = (lsz + 15) / 16 * 16;
   return lsz + (size_t)16 * W * 8;
 }
 
-template <int N, int WM, typename WT>
+template <int N, int WM, typename WT, bool SM = false>
 static hipError_t launch_simp_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
-  if (hipError_t e = set_lds_limit(k_simp_fwd<N, WM, WT>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_simp_fwd<N, WM, WT>), dim3(p.G), dim3(block), lds, s, p);
+  if (hipError_t e = set_lds_limit(k_simp_fwd<N, WM, WT, SM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_simp_fwd<N, WM, WT, SM>), dim3(p.G), dim3(block), lds, s, p);
   return hipGetLastError();
 }
 
@@ -1899,6 +2190,13 @@ static hipError_t launch_cub_fwd_t(const Params& p, int block, size_t lds, hipSt
 
 template <int N>
 static hipError_t launch_simp_fwd_n(const Params& p, int block, size_t lds, hipStream_t s) {
+  if constexpr (N > 0) {
+    if (p.smooth) {
+      if (p.wmode == WM_ONES) return launch_simp_fwd_t<N, WM_ONES, float, true>(p, block, lds, s);
+      if (p.wmode == WM_EXPLICIT) return launch_simp_fwd_t<N, WM_EXPLICIT, float, true>(p, block, lds, s);
+      return launch_simp_fwd_t<N, WM_VMAX, float, true>(p, block, lds, s);
+    }
+  }
   if (p.wmode == WM_ONES) return launch_simp_fwd_t<N, WM_ONES, uint32_t>(p, block, lds, s);
   if (p.wmode == WM_EXPLICIT) {
     if (p.dtype == 0) return launch_simp_fwd_t<N, WM_EXPLICIT, uint32_t>(p, block, lds, s);
@@ -1959,6 +2257,28 @@ hipError_t launch_backward_main(const Params& p, int block, size_t lds, hipStrea
     case 1: return vm ? launch_bwd_t<1, WM_VMAX>(p, block, lds, s) : launch_bwd_t<1, WM_EXPLICIT>(p, block, lds, s);
     case 2: return vm ? launch_bwd_t<2, WM_VMAX>(p, block, lds, s) : launch_bwd_t<2, WM_EXPLICIT>(p, block, lds, s);
     default: return vm ? launch_bwd_t<3, WM_VMAX>(p, block, lds, s) : launch_bwd_t<3, WM_EXPLICIT>(p, block, lds, s);
+  }
+}
+
+template <int N, int WM>
+static hipError_t launch_sm_bwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_smooth_bwd<N, WM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_smooth_bwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_sm_bwd_n(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (p.wmode == WM_ONES) return launch_sm_bwd_t<N, WM_ONES>(p, block, lds, s);
+  if (p.wmode == WM_EXPLICIT) return launch_sm_bwd_t<N, WM_EXPLICIT>(p, block, lds, s);
+  return launch_sm_bwd_t<N, WM_VMAX>(p, block, lds, s);
+}
+
+hipError_t launch_smooth_backward(const Params& p, int block, size_t lds, hipStream_t s) {
+  switch (p.n) {
+    case 1: return launch_sm_bwd_n<1>(p, block, lds, s);
+    case 2: return launch_sm_bwd_n<2>(p, block, lds, s);
+    default: return launch_sm_bwd_n<3>(p, block, lds, s);
   }
 }
 

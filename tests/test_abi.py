@@ -252,3 +252,34 @@ def test_freudenthal_counts():
         W.freudenthal_counts([[0, 3, 1]])
     with pytest.raises(L.WectError):
         W.freudenthal_counts([[3, 3, 2]])   # a volume
+
+
+def test_smooth_metadata(lib):
+    """Relaxation: lam must be finite and >= 0; simplicial only; explicit
+    weights must be float32.  Every failing call returns before any launch."""
+    g = _grid()
+    ok = _simplicial()
+    nb = lib.wect_smooth_workspace_bytes(ctypes.byref(ok), ctypes.byref(g), 2.0)
+    assert nb > 0  # fixed-point partial histograms
+    for lam in (-1.0, float("inf"), float("nan")):
+        assert lib.wect_smooth_forward(ctypes.byref(ok), ctypes.byref(g), lam, FAKE, FAKE, 1 << 30, None) == \
+            L.WECT_ERR_ARG
+        assert lib.wect_smooth_backward(ctypes.byref(ok), ctypes.byref(g), lam, FAKE, None, None, None, None,
+                                        None) == L.WECT_ERR_ARG
+    cub = L.WectComplex()
+    cub.kind, cub.n, cub.B, cub.wmode, cub.dtype = L.WECT_CUBICAL, 2, 1, L.WECT_W_ONES, L.WECT_I32
+    assert lib.wect_smooth_forward(ctypes.byref(cub), ctypes.byref(g), 1.0, FAKE, FAKE, 1 << 30, None) == \
+        L.WECT_ERR_UNSUPPORTED
+    exi = _simplicial(wmode=L.WECT_W_EXPLICIT, dtype=L.WECT_I32)
+    for i in range(3):
+        exi.weights[i] = FAKE
+    assert lib.wect_smooth_forward(ctypes.byref(exi), ctypes.byref(g), 1.0, FAKE, FAKE, 1 << 30, None) == \
+        L.WECT_ERR_UNSUPPORTED
+    # a too small workspace is refused before any launch
+    assert lib.wect_smooth_forward(ctypes.byref(ok), ctypes.byref(g), 1.0, FAKE, FAKE, nb - 1, None) == \
+        L.WECT_ERR_WORKSPACE
+    # unit weights need no maximum-|w| pass: less workspace than float32 weights
+    exf = _simplicial(wmode=L.WECT_W_EXPLICIT, dtype=L.WECT_F32)
+    for i in range(3):
+        exf.weights[i] = FAKE
+    assert lib.wect_smooth_workspace_bytes(ctypes.byref(exf), ctypes.byref(g), 1.0) > nb

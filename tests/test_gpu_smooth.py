@@ -1,0 +1,263 @@
+"""Parity of the sigmoid relaxation (forward and adjoint) with the float64 oracle.
+
+Forward bound, per output entry of a complex with cells c and weights w:
+    16 u sum_c |w(c)| + 2 C M 2^-30     (u = 2^-24, C cells, M = max |w|)
+Each term's error is at most about 6 u |w|: the float32 exponent argument
+(three roundings, weighted by sig(1 - sig)|x| <= 0.224), exp2 and reciprocal
+(one ulp each), 1 + e, the product w sig, and the window cut-off exp(-17) <
+0.7 u; every term is rounded to the fixed-point grid 2^-e with 2^-e <= 2M 2^-30
+and the terms are summed exactly.
+
+Adjoint bound, per gradient entry: (n + 16) u times the same gradient with every
+factor replaced by its absolute value (oracle ``absolute=True``), where n is the
+number of float32 additions along the longest chain into that entry (window
+terms, lane reduction, atomic adds)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import smooth as osm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+U = 2.0 ** -24
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_03909_amd import api
+    api.set_launch()
+    return api
+
+
+# ---------------------------------------------------------------------------
+# inputs
+# ---------------------------------------------------------------------------
+
+def _weights(wmode, counts, g):
+    if wmode == "ones":
+        return []
+    if wmode == "vertex_max":
+        return [g.normal(1.0, 0.3, size=counts[0]).astype(np.float32)]
+    return [g.lognormal(0.0, 0.5, size=k).astype(np.float32) for k in counts]
+
+
+def tri2d(nx, ny, wmode, seed, n=2):
+    g = synth.rng(50, seed, 0)
+    coords, edges, tris = synth.freudenthal_grid(nx, ny, 0.3 / nx, g)
+    if n == 1:
+        coords = np.ascontiguousarray(coords[:, :1])
+    counts = [coords.shape[0], edges.shape[0], tris.shape[0]]
+    return synth.Simplicial(coords, [None, edges, tris], wmode, _weights(wmode, counts, g))
+
+
+def tet3d(m, wmode, seed):
+    g = synth.rng(51, seed, 0)
+    coords, edges, tris, tets = synth.kuhn_grid(m, 0.3 / m, g)
+    counts = [coords.shape[0], edges.shape[0], tris.shape[0], tets.shape[0]]
+    return synth.Simplicial(coords, [None, edges, tris, tets], wmode, _weights(wmode, counts, g))
+
+
+def dirs_for(n, d):
+    if n == 1:
+        return np.array([[1.0], [-1.0], [0.5], [-2.0]][:d], np.float32) if d <= 4 else \
+            np.linspace(-2, 2, d).astype(np.float32).reshape(d, 1)
+    return synth.s1_directions(d) if n == 2 else synth.fibonacci_directions(d)
+
+
+def _cells(K):
+    return sum(K.counts())
+
+
+def _maxw(K):
+    if K.wmode == "ones":
+        return 1.0
+    return float(max(np.abs(np.asarray(w, np.float64)).max() for w in K.weights if len(w)))
+
+
+def fwd_tol(K):
+    return 16 * U * oracle.total_abs_weight(K) + 2 * _cells(K) * _maxw(K) * 2.0 ** -30
+
+
+def gpu_smooth(W, Ks, dirs, thr, lam):
+    cx = W.SimplicialBatch.from_host(Ks)
+    out = W.smooth_forward(cx, W.Grid(dirs, thr), lam)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# forward
+# ---------------------------------------------------------------------------
+
+FWD_CASES = [
+    # name, complexes, d, T, R, lam
+    ("tri2d ones d70 T50 lam4", lambda: [tri2d(40, 30, "ones", 0)], 70, 50, 1.6, 4.0),
+    ("tri2d explicit d64 T37 lam40", lambda: [tri2d(13, 11, "explicit", 1)], 64, 37, 1.6, 40.0),
+    ("tri2d vmax d5 T64 lam1e4", lambda: [tri2d(12, 12, "vertex_max", 2)], 5, 64, 1.6, 1e4),
+    ("tri2d vmax lam0 (whole window)", lambda: [tri2d(9, 8, "vertex_max", 3)], 9, 21, 1.6, 0.0),
+    ("tet3d explicit d64 T33 lam6", lambda: [tet3d(8, "explicit", 4)], 64, 33, 2.0, 6.0),
+    ("tet3d ones d100 T20 lam2", lambda: [tet3d(4, "ones", 5)], 100, 20, 2.0, 2.0),
+    ("line1d explicit d4 T40 lam8", lambda: [tri2d(10, 9, "explicit", 6, n=1)], 4, 40, 2.5, 8.0),
+    ("batch vmax ragged d70 T40 lam5", lambda: [tri2d(9, 7, "vertex_max", 7), tri2d(15, 13, "vertex_max", 8),
+                                               tri2d(4, 3, "vertex_max", 9)], 70, 40, 1.6, 5.0),
+]
+
+
+@pytest.mark.parametrize("case", FWD_CASES, ids=[c[0] for c in FWD_CASES])
+@pytest.mark.parametrize("decomposition", [0, 1, 2])
+def test_smooth_forward_parity(W, case, decomposition):
+    name, make, d, T, R, lam = case
+    _say(f"smooth forward {name} decomposition={decomposition}")
+    Ks = make()
+    n = Ks[0].n
+    dirs = dirs_for(n, d)
+    thr = synth.uniform_thresholds(T, R)
+    W.set_launch(decomposition=decomposition)
+    try:
+        got = gpu_smooth(W, Ks, dirs, thr, lam)
+    finally:
+        W.set_launch()
+    assert got.shape == (len(Ks), d, T)
+    for b, K in enumerate(Ks):
+        ref = osm.smooth_wect(K, dirs, thr, lam)
+        err = np.abs(got[b].astype(np.float64) - ref).max()
+        assert err <= fwd_tol(K), f"{name} complex {b}: error {err} > {fwd_tol(K)}"
+
+
+def test_smooth_large_lam_tends_to_the_wect(W):
+    """At lam = 1e6 with every threshold at least 1e-3 from every height, each
+    relaxed term is the step up to exp(-1000): the output equals the WECT."""
+    K = tri2d(11, 10, "explicit", 10)
+    dirs = synth.s1_directions(6)
+    h = oracle.heights(K.coords, dirs).astype(np.float64).ravel()
+    thr = np.array([t for t in np.linspace(-1.6, 1.6, 57) if np.min(np.abs(h - t)) >= 1e-3], np.float32)
+    got = gpu_smooth(W, [K], dirs, thr, 1e6)[0]
+    ref = oracle.wect(K, dirs, thr).astype(np.float64)
+    assert np.abs(got - ref).max() <= fwd_tol(K)
+
+
+def test_smooth_duplicate_thresholds_and_empty_complex(W):
+    """Non-decreasing thresholds with repeats (binary-search index), and a
+    batch with an empty complex (all-zero rows)."""
+    K = tri2d(8, 8, "vertex_max", 11)
+    E = synth.Simplicial(np.zeros((0, 2), np.float32), [None, np.zeros((0, 2), np.int32), np.zeros((0, 3), np.int32)],
+                         "vertex_max", [np.zeros(0, np.float32)])
+    dirs = synth.s1_directions(7)
+    thr = np.sort(np.concatenate([synth.uniform_thresholds(12, 1.5), synth.uniform_thresholds(6, 1.5)]))
+    got = gpu_smooth(W, [K, E], dirs, thr, 3.0)
+    ref = osm.smooth_wect(K, dirs, thr, 3.0)
+    assert np.abs(got[0] - ref).max() <= fwd_tol(K)
+    assert np.all(got[1] == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+
+def _max_degree(K):
+    deg = np.ones(K.coords.shape[0], np.int64)
+    for s in K.simplices[1:]:
+        deg += np.bincount(np.asarray(s).ravel(), minlength=K.coords.shape[0])
+    return int(deg.max())
+
+
+BWD_CASES = [
+    ("tri2d explicit d70 T40 lam5", lambda: [tri2d(12, 10, "explicit", 20)], 70, 40, 1.6, 5.0),
+    ("tri2d vmax d64 T64 lam12", lambda: [tri2d(36, 30, "vertex_max", 21)], 64, 64, 1.6, 12.0),
+    ("tet3d ones d33 T30 lam4", lambda: [tet3d(4, "ones", 22)], 33, 30, 2.0, 4.0),
+    ("tet3d explicit d64 T24 lam0", lambda: [tet3d(3, "explicit", 23)], 64, 24, 2.0, 0.0),
+    ("line1d vmax d4 T30 lam3", lambda: [tri2d(9, 9, "vertex_max", 24, n=1)], 4, 30, 2.5, 3.0),
+    ("batch explicit ragged d130 T32 lam6", lambda: [tri2d(20, 17, "explicit", 25), tri2d(31, 29, "explicit", 26)],
+     130, 32, 1.6, 6.0),
+]
+
+
+@pytest.mark.parametrize("case", BWD_CASES, ids=[c[0] for c in BWD_CASES])
+def test_smooth_backward_parity(W, case):
+    name, make, d, T, R, lam = case
+    _say(f"smooth backward {name}")
+    Ks = make()
+    n = Ks[0].n
+    dirs = dirs_for(n, d)
+    thr = synth.uniform_thresholds(T, R)
+    B = len(Ks)
+    g = synth.rng(52, len(name), 0).normal(size=(B, d, T)).astype(np.float32)
+    cx = W.SimplicialBatch.from_host(Ks)
+    res = W.smooth_backward(cx, W.Grid(dirs, thr), lam, torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    gx = res["coords"].cpu().numpy()
+    gd = res["dirs"].cpu().numpy()
+    gw = res["weights"]
+    ntiles = (d + 63) // 64
+    vo = np.concatenate([[0], np.cumsum([K.coords.shape[0] for K in Ks])])
+    ref_dirs = np.zeros((d, n))
+    abs_dirs = np.zeros((d, n))
+    for b, K in enumerate(Ks):
+        ref = osm.smooth_wect_vjp(K, dirs, thr, lam, g[b])
+        mag = osm.smooth_wect_vjp(K, dirs, thr, lam, g[b], absolute=True)
+        ref_dirs += ref["dirs"]
+        abs_dirs += mag["dirs"]
+        chain = T + 48 + _max_degree(K) * ntiles
+        e = np.abs(gx[vo[b]:vo[b + 1]] - ref["coords"])
+        assert np.all(e <= (chain + 16) * U * mag["coords"] + 1e-30), f"{name} coords, complex {b}: {e.max()}"
+        if K.wmode == "vertex_max":
+            e = np.abs(gw.cpu().numpy()[vo[b]:vo[b + 1]] - ref["weights"])
+            assert np.all(e <= (chain + 16) * U * mag["weights"] + 1e-30), f"{name} vertex weights {b}"
+        elif K.wmode == "explicit":
+            for dim in range(K.top_dim + 1):
+                lo = sum(Kk.counts()[dim] for Kk in Ks[:b])
+                got = gw[dim].cpu().numpy()[lo:lo + K.counts()[dim]]
+                e = np.abs(got - ref["weights"][dim])
+                bound = (T + 48 + 64 * ntiles) * U * mag["weights"][dim] + 1e-30
+                assert np.all(e <= bound), f"{name} weights dim {dim}, complex {b}: {e.max()}"
+        else:
+            assert gw is None
+    chain_d = sum(_cells(K) for K in Ks) + T + 1024
+    e = np.abs(gd - ref_dirs)
+    assert np.all(e <= (chain_d + 16) * U * abs_dirs + 1e-30), f"{name} dirs: {e.max()}"
+
+
+def test_smooth_backward_optional_outputs(W):
+    """Gradients that are not asked for are not written; the others match a full call."""
+    K = tri2d(9, 8, "explicit", 30)
+    dirs, thr = synth.s1_directions(16), synth.uniform_thresholds(24, 1.6)
+    cx = W.SimplicialBatch.from_host([K])
+    grid = W.Grid(dirs, thr)
+    g = torch.from_numpy(synth.rng(53, 0, 0).normal(size=(1, 16, 24)).astype(np.float32)).cuda()
+    full = W.smooth_backward(cx, grid, 7.0, g)
+    part = W.smooth_backward(cx, grid, 7.0, g, coords=False, weights=False)
+    torch.cuda.synchronize()
+    assert part["coords"] is None and part["weights"] is None
+    np.testing.assert_allclose(part["dirs"].cpu().numpy(), full["dirs"].cpu().numpy(), rtol=1e-5, atol=1e-6)
+
+
+def test_smooth_autograd_layer(W):
+    """torch.autograd through SmoothWECT equals the direct adjoint calls."""
+    K = tri2d(10, 9, "vertex_max", 31)
+    dirs, thr = synth.s1_directions(12), synth.uniform_thresholds(30, 1.6)
+    cx = W.SimplicialBatch.from_host([K])
+    layer = W.SmoothWECT(torch.from_numpy(dirs), torch.from_numpy(thr), lam=9.0).cuda()
+    coords = cx.coords.clone().requires_grad_(True)
+    w = cx.weights[0].clone().requires_grad_(True)
+    out = layer(cx, coords, w)
+    target = torch.zeros_like(out)
+    loss = ((out - target) ** 2).sum()
+    loss.backward()
+    g = 2.0 * out.detach()
+    ref = W.smooth_backward(cx, W.Grid(dirs, thr), 9.0, g)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(coords.grad.cpu().numpy(), ref["coords"].cpu().numpy(), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(layer.dirs.grad.cpu().numpy(), ref["dirs"].cpu().numpy(), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(w.grad.cpu().numpy(), ref["weights"].cpu().numpy(), rtol=1e-5, atol=1e-5)
