@@ -274,7 +274,31 @@ def main(argv=None):
         extras["differentiation_batch64"]["wecf_filter_array_m128"] = {
             "fwd_ms": t_w * 1e3, "items_per_s": it5 / t_w,
             "note": "filter values read from a [V, 128] array instead of formed from coordinates"}
-        del cx5, o5, gv5, ws5, gout, singles5, o5s, gv5s, go5, ws5s, F5, o5w, ws5w
+        del singles5, o5s, gv5s, go5, ws5s, F5, o5w, ws5w
+        # sigmoid relaxation of the same batch (lam x threshold spacing = 2): forward, and
+        # the adjoint to coordinates, directions and vertex weights
+        thr5 = w5.thr.astype(np.float64)
+        lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
+        wss = torch.empty(max(1, W.smooth_workspace_bytes(cx5, g5, lam5)), dtype=torch.uint8, device=dev)
+        os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device=dev)
+        t_sf = timed(lambda: W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss), 5, 1)
+        t_sb = timed(lambda: W.smooth_backward(cx5, g5, lam5, gout), 5, 1)
+        W.profile_enable(True)
+        W.profile_read(reset=True)
+        for _ in range(5):
+            W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss)
+            W.smooth_backward(cx5, g5, lam5, gout)
+        torch.cuda.synchronize()
+        ps = W.profile_read(reset=True)
+        W.profile_enable(False)
+        extras["differentiation_batch64"]["relaxation_lam_spacing2"] = {
+            "lam": lam5, "fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3,
+            "fwd_kernel_ms": ps["fwd_ms"] / max(1, ps["fwd_launches"]),
+            "bwd_kernel_ms": ps["bwd_ms"] / max(1, ps["bwd_launches"]),
+            "fwd_items_per_s": it5 / t_sf, "bwd_items_per_s": it5 / t_sb,
+            "note": "sigmoid window of |lam (t - h)| <= 17, about 17 thresholds per cell and direction; "
+                    "adjoint to coordinates [V,2], directions [128,2] and vertex weights"}
+        del cx5, o5, gv5, ws5, gout, wss, os5
         # 3D simplicial, float32 weights
         w3 = synth.cfg3()
         cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)

@@ -42,6 +42,8 @@ from . import heights, owner_vertex, simplicial_cells
 
 __all__ = ["sigmoid", "smooth_wect", "smooth_wect_vjp", "fd_smooth"]
 
+_CHUNK = 1 << 16   # simplices per block of the dense [simplices, T] evaluation
+
 
 def sigmoid(x):
     """1 / (1 + exp(-x)) in float64, without overflow for large |x|."""
@@ -74,7 +76,8 @@ def smooth_wect(K, dirs, thr, lam, absolute: bool = False) -> np.ndarray:
                 continue
             hm = h[v].max(axis=1)
             c = np.abs(cells.weights[dim]) if absolute else cells.signed(dim)
-            out[p] += c @ sigmoid(lam * (t[None, :] - hm[:, None]))
+            for i in range(0, hm.shape[0], _CHUNK):   # rows in chunks: bounded memory
+                out[p] += c[i:i + _CHUNK] @ sigmoid(lam * (t[None, :] - hm[i:i + _CHUNK, None]))
     return out
 
 
@@ -108,18 +111,20 @@ def smooth_wect_vjp(K, dirs, thr, lam, g, absolute: bool = False) -> Dict[str, o
             if v.shape[0] == 0:
                 continue
             hm, a = _argmax_vertex(h, v)
-            sg = sigmoid(lam * (t[None, :] - hm[:, None]))          # [k, T]
             sign = -1.0 if dim % 2 else 1.0
             w = cells.weights[dim]
             if absolute:
                 sign, w = 1.0, np.abs(w)
-            gw[dim] += sign * (sg @ G[p])
-            # d sig(lam (t - h)) / d h = -lam sig (1 - sig)
-            dh = -(sign * w) * lam * ((sg * (1.0 - sg)) @ G[p])
-            if absolute:
-                dh = np.abs(dh)
-            np.add.at(gx, a, dh[:, None] * D[p][None, :])
-            gd[p] += (dh[:, None] * X[a]).sum(axis=0)
+            for i in range(0, hm.shape[0], _CHUNK):
+                r = slice(i, i + _CHUNK)
+                sg = sigmoid(lam * (t[None, :] - hm[r, None]))          # [rows, T]
+                gw[dim][r] += sign * (sg @ G[p])
+                # d sig(lam (t - h)) / d h = -lam sig (1 - sig)
+                dh = -(sign * w[r]) * lam * ((sg * (1.0 - sg)) @ G[p])
+                if absolute:
+                    dh = np.abs(dh)
+                np.add.at(gx, a[r], dh[:, None] * D[p][None, :])
+                gd[p] += (dh[:, None] * X[a[r]]).sum(axis=0)
     if K.wmode == "vertex_max":
         gv = np.zeros(V)
         for dim, own in enumerate(owner_vertex(K)):
