@@ -59,6 +59,35 @@ def included_vertices(C) -> int:
     return int((np.asarray(C.intensity) > C.include_above).sum())
 
 
+def relaxation_terms(cx, grid, lam: float, chunk: int = 1 << 20) -> int:
+    """Number of sigmoid window terms of the relaxation: over every simplex and
+    direction, the thresholds within 17 / lam of the simplex's maximum height
+    (bookkeeping on the device with torch; heights from a float32 matmul)."""
+    import torch
+    R = 17.0 / lam
+    thr = grid.thr
+    h = cx.coords @ grid.dirs.t()                     # [V, d]
+    total = 0
+    offs = [0] + [int(v) for v in (cx.vert_off[1:].tolist() if cx.vert_off is not None else [h.shape[0]])]
+    for dim in range(cx.top_dim + 1):
+        if dim == 0:
+            rows = h
+        else:
+            simp = cx.simplices[dim].long()
+            if cx.simp_off is not None and cx.simp_off[dim] is not None:
+                so = cx.simp_off[dim]
+                base = torch.repeat_interleave(torch.tensor(offs[:-1], device=h.device), so[1:] - so[:-1])
+                simp = simp + base[:, None]
+            rows = None
+        n = h.shape[0] if dim == 0 else simp.shape[0]
+        for i in range(0, n, chunk):
+            hm = rows[i:i + chunk] if dim == 0 else h[simp[i:i + chunk]].amax(dim=1)
+            lo = torch.searchsorted(thr, (hm - R).contiguous(), right=False)
+            hi = torch.searchsorted(thr, (hm + R).contiguous(), right=True)
+            total += int((hi - lo).sum())
+    return total
+
+
 def timed(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -291,13 +320,33 @@ def main(argv=None):
         torch.cuda.synchronize()
         ps = W.profile_read(reset=True)
         W.profile_enable(False)
-        extras["differentiation_batch64"]["relaxation_lam_spacing2"] = {
-            "lam": lam5, "fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3,
-            "fwd_kernel_ms": ps["fwd_ms"] / max(1, ps["fwd_launches"]),
-            "bwd_kernel_ms": ps["bwd_ms"] / max(1, ps["bwd_launches"]),
-            "fwd_items_per_s": it5 / t_sf, "bwd_items_per_s": it5 / t_sb,
+        kf_ms = ps["fwd_ms"] / max(1, ps["fwd_launches"])
+        kb_ms = ps["bwd_ms"] / max(1, ps["bwd_launches"])
+        terms = relaxation_terms(cx5, g5, lam5)
+        # algorithmic lane-ops per window term: forward sub, mul, exp2, add, reciprocal, weight
+        # product, rounding to the fixed-point grid, accumulate = 8; adjoint the same up to the
+        # reciprocal, then two products and two accumulations (value and derivative sums) = 9
+        relax = {
+            "lam": lam5, "fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3, "fwd_kernel_ms": kf_ms, "bwd_kernel_ms": kb_ms,
+            "fwd_items_per_s": it5 / t_sf, "bwd_items_per_s": it5 / t_sb, "window_terms": terms,
+            "roofline_fwd": {"bound": "alu", "achieved": 8 * terms / (kf_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
+                             "unit": "TOP/s", "frac": 8 * terms / (kf_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
+            "roofline_bwd": {"bound": "alu", "achieved": 9 * terms / (kb_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
+                             "unit": "TOP/s", "frac": 9 * terms / (kb_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
             "note": "sigmoid window of |lam (t - h)| <= 17, about 17 thresholds per cell and direction; "
                     "adjoint to coordinates [V,2], directions [128,2] and vertex weights"}
+        if not a.no_cpu:
+            # the float64 oracle on a bounded sample: the smallest complex, 8 directions
+            from oracle import smooth as osm
+            b0 = int(np.argmin([K.coords.shape[0] for K in w5.complexes]))
+            t0 = time.perf_counter()
+            osm.smooth_wect(w5.complexes[b0], w5.dirs[:8], w5.thr, lam5)
+            tc = time.perf_counter() - t0
+            relax["cpu_oracle"] = {"value": 8 * sum(w5.complexes[b0].counts()) / tc, "unit": "simplex·directions/s",
+                                   "cores": 1, "kind": "oracle",
+                                   "sample": f"complex {b0} ({sum(w5.complexes[b0].counts())} simplices), "
+                                             f"8 directions, {tc:.1f} s"}
+        extras["differentiation_batch64"]["relaxation_lam_spacing2"] = relax
         del cx5, o5, gv5, ws5, gout, wss, os5
         # 3D simplicial, float32 weights
         w3 = synth.cfg3()
