@@ -284,9 +284,18 @@ __device__ __forceinline__ float sigmoid2(float x, float& e) {
   return __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// floor(x + 1/2) as an int32 in one instruction (|x| < 2^31): rounding to
+// the nearest integer, halves upwards.
+__device__ __forceinline__ int round_half_up(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // Relaxation: the entry's signed fixed-point weight C is spread over the
 // thresholds.  Inside its window [lo, hi) = {q : |thr[q] - h| <= R} the entry
-// contributes F_q = round(C sig(lam (thr[q] - h))) at threshold q, and from hi
+// contributes F_q = round(C sig(lam (thr[q] - h))) at threshold q (nearest
+// integer, halves upwards), and from hi
 // on all of C.  The histogram holds differences (F_lo at lo, F_q - F_{q-1} at
 // q, C - F_{hi-1} at hi), so the threshold scan that follows returns exactly
 // these values.  |C| < 2^30, so every F_q and difference fits in int32.
@@ -300,11 +309,20 @@ __device__ __forceinline__ void smooth_entries(uint64_t* col, int first, int ste
     const int lo = thr_index<FAST>(h - R, th);
     const int hi = thr_index<FAST>(next_up(h + R), th);
     const float cf = (float)(int32_t)(uint32_t)C;
-    int prev = 0;
-    for (int q = lo; q < hi; ++q) {
+    auto term = [&](int q) {
       float ex;
-      const float sg = sigmoid2((th.P[q + 1] - h) * kap, ex);
-      const int F = (int)__builtin_rintf(cf * sg);
+      return round_half_up(cf * sigmoid2((th.P[q + 1] - h) * kap, ex));
+    };
+    // two terms per iteration: half the loop control, and no register copy
+    int prev = 0, q = lo;
+    for (; q + 1 < hi; q += 2) {
+      const int F0 = term(q), F1 = term(q + 1);
+      lds_add(&col[q * W], (uint64_t)(int64_t)(F0 - prev));
+      lds_add(&col[(q + 1) * W], (uint64_t)(int64_t)(F1 - F0));
+      prev = F1;
+    }
+    if (q < hi) {
+      const int F = term(q);
       lds_add(&col[q * W], (uint64_t)(int64_t)(F - prev));
       prev = F;
     }
@@ -1575,14 +1593,23 @@ __device__ __forceinline__ void sm_bwd_range(const Params& p, int64_t lo, int64_
       const float c = E[L::COFF];
       const int qlo = thr_index<FAST>(h - R, th);
       const int qhi = thr_index<FAST>(next_up(h + R), th);
-      float u = Gs[qhi * W + lane], v = 0.0f;
-      for (int q = qlo; q < qhi; ++q) {
+      float u = Gs[qhi * W + lane], v = 0.0f, u1 = 0.0f, v1 = 0.0f;
+      auto term = [&](int q, float& uu, float& vv) {
         float ex;
         const float sg = sigmoid2((th.P[q + 1] - h) * kap, ex);
         const float gq = g[q * W + lane];
-        u = __builtin_fmaf(gq, sg, u);
-        v = __builtin_fmaf(gq, ex * sg * sg, v);
+        uu = __builtin_fmaf(gq, sg, uu);
+        vv = __builtin_fmaf(gq, ex * sg * sg, vv);
+      };
+      // two terms per iteration into two pairs of sums
+      int q = qlo;
+      for (; q + 1 < qhi; q += 2) {
+        term(q, u, v);
+        term(q + 1, u1, v1);
       }
+      if (q < qhi) term(q, u, v);
+      u += u1;
+      v += v1;
       const float dh = -c * lam * v;
 #pragma unroll
       for (int k = 0; k < N; ++k) gd[k] = __builtin_fmaf(dh, E[a * N + k], gd[k]);
