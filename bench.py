@@ -59,17 +59,18 @@ def included_vertices(C) -> int:
     return int((np.asarray(C.intensity) > C.include_above).sum())
 
 
-def relaxation_terms(cx, grid, lam: float, chunk: int = 1 << 20) -> int:
-    """Number of sigmoid window terms of the relaxation: over every simplex and
-    direction, the thresholds within 17 / lam of the simplex's maximum height
-    (bookkeeping on the device with torch; heights from a float32 matmul)."""
+def relaxation_terms(cx, grid, lam: float, chunk: int = 1 << 20, vertices_only: bool = False) -> int:
+    """Number of sigmoid window terms of the relaxation: over every simplex (or,
+    for the vertex-centric kernels, every vertex) and direction, the thresholds
+    within 17 / lam of its maximum height (bookkeeping on the device with torch;
+    heights from a float32 matmul)."""
     import torch
     R = 17.0 / lam
     thr = grid.thr
     h = cx.coords @ grid.dirs.t()                     # [V, d]
     total = 0
     offs = [0] + [int(v) for v in (cx.vert_off[1:].tolist() if cx.vert_off is not None else [h.shape[0]])]
-    for dim in range(cx.top_dim + 1):
+    for dim in range(1 if vertices_only else cx.top_dim + 1):
         if dim == 0:
             rows = h
         else:
@@ -305,36 +306,49 @@ def main(argv=None):
             "note": "filter values read from a [V, 128] array instead of formed from coordinates"}
         del singles5, o5s, gv5s, go5, ws5s, F5, o5w, ws5w
         # sigmoid relaxation of the same batch (lam x threshold spacing = 2): forward, and
-        # the adjoint to coordinates, directions and vertex weights
+        # the adjoint to coordinates, directions and vertex weights; per-cell kernels and the
+        # vertex-centric kernels over the lower-star index (built once per topology)
         thr5 = w5.thr.astype(np.float64)
         lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
-        wss = torch.empty(max(1, W.smooth_workspace_bytes(cx5, g5, lam5)), dtype=torch.uint8, device=dev)
         os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device=dev)
-        t_sf = timed(lambda: W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss), 5, 1)
-        t_sb = timed(lambda: W.smooth_backward(cx5, g5, lam5, gout), 5, 1)
-        W.profile_enable(True)
-        W.profile_read(reset=True)
-        for _ in range(5):
-            W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss)
-            W.smooth_backward(cx5, g5, lam5, gout)
-        torch.cuda.synchronize()
-        ps = W.profile_read(reset=True)
-        W.profile_enable(False)
-        kf_ms = ps["fwd_ms"] / max(1, ps["fwd_launches"])
-        kb_ms = ps["bwd_ms"] / max(1, ps["bwd_launches"])
-        terms = relaxation_terms(cx5, g5, lam5)
-        # algorithmic lane-ops per window term: forward sub, mul, exp2, add, reciprocal, weight
-        # product, rounding to the fixed-point grid, accumulate = 8; adjoint the same up to the
-        # reciprocal, then two products and two accumulations (value and derivative sums) = 9
-        relax = {
-            "lam": lam5, "fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3, "fwd_kernel_ms": kf_ms, "bwd_kernel_ms": kb_ms,
-            "fwd_items_per_s": it5 / t_sf, "bwd_items_per_s": it5 / t_sb, "window_terms": terms,
-            "roofline_fwd": {"bound": "alu", "achieved": 8 * terms / (kf_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
-                             "unit": "TOP/s", "frac": 8 * terms / (kf_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
-            "roofline_bwd": {"bound": "alu", "achieved": 9 * terms / (kb_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
-                             "unit": "TOP/s", "frac": 9 * terms / (kb_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
-            "note": "sigmoid window of |lam (t - h)| <= 17, about 17 thresholds per cell and direction; "
-                    "adjoint to coordinates [V,2], directions [128,2] and vertex weights"}
+        t_build = timed(lambda: W.lower_star_index(cx5, cache=False), 3, 1)
+        index5 = W.lower_star_index(cx5)
+        # algorithmic lane-ops: per sigmoid window term, forward sub, mul, exp2, add, reciprocal,
+        # weight product, rounding to the fixed-point grid, accumulate = 8; adjoint the same up to
+        # the reciprocal, then two products and two accumulations = 9.  Per coface row and direction
+        # (vertex-centric kernels): the other vertices' heights (2n - 1 each), one comparison each,
+        # one accumulation.
+        nrow_ops = sum((dm + 1) * cx5.counts[dm] * (dm * (2 * cx5.n - 1) + dm + 1)
+                       for dm in range(1, cx5.top_dim + 1)) * g5.d
+        terms_cells = relaxation_terms(cx5, g5, lam5)
+        terms_verts = relaxation_terms(cx5, g5, lam5, vertices_only=True)
+        relax = {"lam": lam5, "index_build_ms": t_build * 1e3, "index_bytes": int(index5.numel()),
+                 "note": "sigmoid window of |lam (t - h)| <= 17, about 17 thresholds per window; adjoint to "
+                         "coordinates [V,2], directions [128,2] and vertex weights"}
+        for name, index, terms, extra_ops in (("cells", None, terms_cells, 0),
+                                              ("lower_star", index5, terms_verts, nrow_ops)):
+            wss = torch.empty(max(1, W.smooth_workspace_bytes(cx5, g5, lam5, index)), dtype=torch.uint8, device=dev)
+            t_sf = timed(lambda: W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss, index=index), 5, 1)
+            t_sb = timed(lambda: W.smooth_backward(cx5, g5, lam5, gout, index=index), 5, 1)
+            W.profile_enable(True)
+            W.profile_read(reset=True)
+            for _ in range(5):
+                W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss, index=index)
+                W.smooth_backward(cx5, g5, lam5, gout, index=index)
+            torch.cuda.synchronize()
+            ps = W.profile_read(reset=True)
+            W.profile_enable(False)
+            kf_ms = ps["fwd_ms"] / max(1, ps["fwd_launches"])
+            kb_ms = ps["bwd_ms"] / max(1, ps["bwd_launches"])
+            of, ob = 8 * terms + extra_ops, 9 * terms + extra_ops
+            relax[name] = {
+                "fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3, "fwd_kernel_ms": kf_ms, "bwd_kernel_ms": kb_ms,
+                "fwd_items_per_s": it5 / t_sf, "bwd_items_per_s": it5 / t_sb, "window_terms": terms,
+                "roofline_fwd": {"bound": "alu", "achieved": of / (kf_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
+                                 "unit": "TOP/s", "frac": of / (kf_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
+                "roofline_bwd": {"bound": "alu", "achieved": ob / (kb_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
+                                 "unit": "TOP/s", "frac": ob / (kb_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS}}
+            del wss
         if not a.no_cpu:
             # the float64 oracle on a bounded sample: the smallest complex, 8 directions
             from oracle import smooth as osm
@@ -347,7 +361,7 @@ def main(argv=None):
                                    "sample": f"complex {b0} ({sum(w5.complexes[b0].counts())} simplices), "
                                              f"8 directions, {tc:.1f} s"}
         extras["differentiation_batch64"]["relaxation_lam_spacing2"] = relax
-        del cx5, o5, gv5, ws5, gout, wss, os5
+        del cx5, o5, gv5, ws5, gout, os5, index5
         # 3D simplicial, float32 weights
         w3 = synth.cfg3()
         cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)

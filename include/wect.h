@@ -308,6 +308,46 @@ wect_status wect_smooth_backward(const wect_complex* c, const wect_grid* g, floa
                                  float* grad_vertex, void* hip_stream);
 
 /*
+ * Lower-star index of a simplicial complex (or CSR batch): for every vertex,
+ * the simplices of dimension >= 1 that contain it.  Every cell has, for each
+ * direction, one vertex attaining its maximum height (lowest id among equal
+ * heights), and the cells a vertex tops form its lower star (Definition
+ * "Lower-Star Filtrations"); with the index, the relaxation combines those
+ * cells' weights per vertex and direction and evaluates one sigmoid window per
+ * vertex instead of one per cell (wect_smooth_ls_forward / _backward).
+ *
+ * wect_lower_star_bytes: size of the index for the complex's counts (0 on
+ *   invalid metadata).  It depends only on the counts.
+ * wect_lower_star_build: writes the index into `index` (device memory, at
+ *   least wect_lower_star_bytes(c) bytes, 16-byte aligned, owned by the
+ *   caller).  Reads the simplex lists and offsets only, so one build serves
+ *   every call with the same topology (coordinates and weights may change).
+ *   Asynchronous and capture-safe: six kernels, no allocation.  Vertex ids must
+ *   be valid (wect_validate).
+ */
+size_t wect_lower_star_bytes(const wect_complex* c);
+wect_status wect_lower_star_build(const wect_complex* c, void* index, size_t index_bytes, void* hip_stream);
+
+/*
+ * wect_smooth_forward / wect_smooth_backward through the lower-star index:
+ * same arguments and results, plus the index built for the same complex
+ * (index_bytes >= wect_lower_star_bytes(c)); the workspace size is
+ * wect_smooth_ls_workspace_bytes.  Work per direction is one window per
+ * vertex (float64 sum of the combined cell weights, then the fixed-point grid
+ * of the forward with |combined weight| 2^e < 2^30) plus the argmax test of
+ * each vertex's cofaces.  The adjoint writes each vertex's coordinate
+ * gradient from its own combined weight, and adds each cell's weight
+ * gradient from the vertices that top it (float32 atomics).
+ */
+size_t wect_smooth_ls_workspace_bytes(const wect_complex* c, const wect_grid* g, float lam);
+wect_status wect_smooth_ls_forward(const wect_complex* c, const wect_grid* g, float lam, const void* index,
+                                   size_t index_bytes, float* out, void* ws, size_t ws_bytes, void* hip_stream);
+wect_status wect_smooth_ls_backward(const wect_complex* c, const wect_grid* g, float lam, const void* index,
+                                    size_t index_bytes, const float* grad_out, float* grad_coords,
+                                    float* grad_dirs, float* const grad_w[4], float* grad_vertex,
+                                    void* hip_stream);
+
+/*
  * Synchronous data check on `hip_stream`: CSR offsets and shapes consistent
  * with the counts, vertex ids in range, thresholds non-decreasing, axes
  * strictly increasing, no NaN/Inf in coordinates, directions, thresholds or

@@ -107,6 +107,18 @@ def lib() -> ctypes.CDLL:
     L.wect_smooth_backward.argtypes = [P(WectComplex), P(WectGrid), c_float, c_void_p, c_void_p, c_void_p,
                                        P(c_void_p), c_void_p, c_void_p]
     L.wect_smooth_backward.restype = c_int
+    L.wect_lower_star_bytes.argtypes = [P(WectComplex)]
+    L.wect_lower_star_bytes.restype = c_size_t
+    L.wect_lower_star_build.argtypes = [P(WectComplex), c_void_p, c_size_t, c_void_p]
+    L.wect_lower_star_build.restype = c_int
+    L.wect_smooth_ls_workspace_bytes.argtypes = [P(WectComplex), P(WectGrid), c_float]
+    L.wect_smooth_ls_workspace_bytes.restype = c_size_t
+    L.wect_smooth_ls_forward.argtypes = [P(WectComplex), P(WectGrid), c_float, c_void_p, c_size_t, c_void_p,
+                                         c_void_p, c_size_t, c_void_p]
+    L.wect_smooth_ls_forward.restype = c_int
+    L.wect_smooth_ls_backward.argtypes = [P(WectComplex), P(WectGrid), c_float, c_void_p, c_size_t, c_void_p,
+                                          c_void_p, c_void_p, P(c_void_p), c_void_p, c_void_p]
+    L.wect_smooth_ls_backward.restype = c_int
     _lib = L
     return L
 

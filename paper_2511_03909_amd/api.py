@@ -18,7 +18,7 @@ __all__ = [
     "Grid", "SimplicialBatch", "CubicalBatch", "wect_workspace_bytes", "wect_forward", "wect_backward",
     "wect_batched", "wect_validate", "set_launch", "get_launch", "profile_enable", "profile_read",
     "WECTFunction", "wect", "WECT", "smooth_workspace_bytes", "smooth_forward", "smooth_backward",
-    "SmoothWECTFunction", "smooth_wect", "SmoothWECT",
+    "SmoothWECTFunction", "smooth_wect", "SmoothWECT", "lower_star_index",
 ]
 
 _WMODES = {"ones": L.WECT_W_ONES, "explicit": L.WECT_W_EXPLICIT, "vertex_max": L.WECT_W_VERTEX_MAX}
@@ -504,34 +504,67 @@ def _lam(lam) -> float:
     return lam
 
 
-def smooth_workspace_bytes(cx, grid: Grid, lam: float) -> int:
+def lower_star_index(cx, cache: bool = True) -> torch.Tensor:
+    """Device buffer holding the lower-star index of a simplicial batch (see
+    wect_lower_star_build); built once and kept on the batch object."""
+    idx = getattr(cx, "_lower_star", None) if cache else None
+    if idx is not None:
+        return idx
+    c = cx.struct()
+    nbytes = int(L.lib().wect_lower_star_bytes(ctypes.byref(c)))
+    if nbytes == 0:
+        raise L.WectError(L.WECT_ERR_ARG, "wect_lower_star_bytes")
+    idx = torch.empty(nbytes, dtype=torch.uint8, device=cx.device)
+    L.check(L.lib().wect_lower_star_build(ctypes.byref(c), _ptr(idx), ctypes.c_size_t(nbytes), _stream(cx.device)),
+            "wect_lower_star_build")
+    if cache:
+        cx._lower_star = idx
+    return idx
+
+
+def _index_arg(index):
+    if index is None:
+        return None, 0
+    return _ptr(index), int(index.numel()) * index.element_size()
+
+
+def smooth_workspace_bytes(cx, grid: Grid, lam: float, index: Optional[torch.Tensor] = None) -> int:
     c, g = cx.struct(), grid.struct()
-    return int(L.lib().wect_smooth_workspace_bytes(ctypes.byref(c), ctypes.byref(g), _lam(lam)))
+    fn = L.lib().wect_smooth_ls_workspace_bytes if index is not None else L.lib().wect_smooth_workspace_bytes
+    return int(fn(ctypes.byref(c), ctypes.byref(g), _lam(lam)))
 
 
 def smooth_forward(cx, grid: Grid, lam: float, out: Optional[torch.Tensor] = None,
-                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Sigmoid relaxation S [B, d, T] float32; see wect_smooth_forward in wect.h."""
+                   ws: Optional[torch.Tensor] = None, index: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Sigmoid relaxation S [B, d, T] float32; see wect_smooth_forward in wect.h.
+    With ``index`` (from ``lower_star_index``) the vertex-centric kernels run."""
     lam = _lam(lam)
     shape = (cx.B, grid.d, grid.T)
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=cx.device)
     else:
         _check_tensor(out, "out", cx.device, torch.float32, shape)
-    need = smooth_workspace_bytes(cx, grid, lam)
+    need = smooth_workspace_bytes(cx, grid, lam, index)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
     else:
         _check_tensor(ws, "ws", cx.device)
     c, g = cx.struct(), grid.struct()
-    st = L.lib().wect_smooth_forward(ctypes.byref(c), ctypes.byref(g), lam, _ptr(out), _ptr(ws),
-                                     ctypes.c_size_t(int(ws.numel()) * ws.element_size()), _stream(cx.device))
+    nws = ctypes.c_size_t(int(ws.numel()) * ws.element_size())
+    if index is None:
+        st = L.lib().wect_smooth_forward(ctypes.byref(c), ctypes.byref(g), lam, _ptr(out), _ptr(ws), nws,
+                                         _stream(cx.device))
+    else:
+        _check_tensor(index, "index", cx.device, torch.uint8)
+        ip, ib = _index_arg(index)
+        st = L.lib().wect_smooth_ls_forward(ctypes.byref(c), ctypes.byref(g), lam, ip, ctypes.c_size_t(ib),
+                                            _ptr(out), _ptr(ws), nws, _stream(cx.device))
     L.check(st, "wect_smooth_forward")
     return out
 
 
 def smooth_backward(cx, grid: Grid, lam: float, grad_out: torch.Tensor, coords: bool = True, dirs: bool = True,
-                    weights: bool = True) -> dict:
+                    weights: bool = True, index: Optional[torch.Tensor] = None) -> dict:
     """Adjoint of ``smooth_forward``: {"coords": [V, n] or None, "dirs": [d, n] or None,
     "weights": list per dimension (explicit) / [V] (vertex_max) / None}."""
     lam = _lam(lam)
@@ -543,8 +576,15 @@ def smooth_backward(cx, grid: Grid, lam: float, grad_out: torch.Tensor, coords: 
     if weights and cx.wmode != "ones":
         gw, gv = _grad_outputs(cx)
     c, g = cx.struct(), grid.struct()
-    st = L.lib().wect_smooth_backward(ctypes.byref(c), ctypes.byref(g), lam, _ptr(grad_out), _ptr(gx), _ptr(gd),
-                                      _gw_array(gw), _ptr(gv), _stream(dev))
+    if index is None:
+        st = L.lib().wect_smooth_backward(ctypes.byref(c), ctypes.byref(g), lam, _ptr(grad_out), _ptr(gx),
+                                          _ptr(gd), _gw_array(gw), _ptr(gv), _stream(dev))
+    else:
+        _check_tensor(index, "index", dev, torch.uint8)
+        ip, ib = _index_arg(index)
+        st = L.lib().wect_smooth_ls_backward(ctypes.byref(c), ctypes.byref(g), lam, ip, ctypes.c_size_t(ib),
+                                             _ptr(grad_out), _ptr(gx), _ptr(gd), _gw_array(gw), _ptr(gv),
+                                             _stream(dev))
     L.check(st, "wect_smooth_backward")
     return {"coords": gx, "dirs": gd, "weights": gv if gv is not None else gw}
 
@@ -558,14 +598,15 @@ class SmoothWECTFunction(torch.autograd.Function):
         cxw = SimplicialBatch(coords.detach().contiguous(), cx.simplices, cx.wmode, ws, cx.vert_off,
                               cx.simp_off, cx.B)
         grid = Grid(dirs.detach(), thr, device=coords.device)
-        ctx.cx, ctx.grid, ctx.lam, ctx.nw = cxw, grid, lam, len(weights)
-        return smooth_forward(cxw, grid, lam)
+        index = lower_star_index(cx)  # depends on the topology only: built once per batch object
+        ctx.cx, ctx.grid, ctx.lam, ctx.nw, ctx.index = cxw, grid, lam, len(weights), index
+        return smooth_forward(cxw, grid, lam, index=index)
 
     @staticmethod
     def backward(ctx, grad_out):
         need = ctx.needs_input_grad
         r = smooth_backward(ctx.cx, ctx.grid, ctx.lam, grad_out, coords=need[3], dirs=need[4],
-                            weights=any(need[5:]))
+                            weights=any(need[5:]), index=ctx.index)
         gw = r["weights"]
         if gw is None:
             gw = [None] * ctx.nw

@@ -133,11 +133,21 @@ int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only, bool sm
   return best;
 }
 
+// Largest block whose vertex-centric relaxation kernel fits in LDS (the
+// coface rows grow with the block).
+int ls_block(int T, bool bwd) {
+  for (int b : {1024, 512, 256}) {
+    const size_t lds = bwd ? wect::smooth_ls_backward_lds_bytes(T, b) : wect::smooth_ls_forward_lds_bytes(T, b);
+    if (lds <= kLdsLimit) return b;
+  }
+  return 256;
+}
+
 // Check host metadata and build the plan.  need_bwd: backward requested.
 // smooth: forward of the sigmoid relaxation (fixed-point accumulation for
 // every weight mode, float32 output); its adjoint is planned by smooth_plan.
 wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl,
-                      bool smooth = false) {
+                      bool smooth = false, bool ls = false) {
   if (!c || !g) return WECT_ERR_ARG;
   if (c->kind != WECT_SIMPLICIAL && c->kind != WECT_CUBICAL) return WECT_ERR_ARG;
   if (c->B < 1) return WECT_ERR_ARG;
@@ -217,6 +227,8 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     p.include_above = c->include_above;
     elems = c->total_voxels;
   }
+  const int64_t cells = elems;
+  if (ls) elems = c->count[0];  // vertex-centric kernels: one stream element per vertex
   if (need_bwd) {
     if (c->kind != WECT_SIMPLICIAL) return WECT_ERR_UNSUPPORTED;
     if (c->dtype != WECT_F32 || c->wmode == WECT_W_ONES) return WECT_ERR_ARG;
@@ -237,7 +249,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   const bool auto_group = need_fwd && decomp == 0 && g->T > 0 && S_fwd > 0 && groups_fwd >= cus &&
                           S_fwd >= groups_fwd * 8 * 1024;
   int block = g_block.load();
-  if (!block) block = auto_group ? 1024 : auto_block(c, g, need_bwd && !need_fwd, smooth);
+  if (!block) block = auto_group ? 1024 : ls ? ls_block(g->T, false) : auto_block(c, g, need_bwd && !need_fwd, smooth);
   pl->block = block;
   pl->elems = elems;
   p.ntiles = ntiles;
@@ -257,7 +269,13 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     const int acc_bytes = acc_bytes_of(c, smooth);
     int stage = 0;
     size_t lds = 0;
-    fwd_stage_lds(c, g, block, &stage, &lds, smooth);
+    if (ls) {  // per-wavefront coface rows instead of a block staging tile
+      stage = block;
+      lds = wect::smooth_ls_forward_lds_bytes(g->T, block);
+      if (lds > kLdsLimit) stage = 0;
+    } else {
+      fwd_stage_lds(c, g, block, &stage, &lds, smooth);
+    }
     if (stage == 0) return WECT_ERR_UNSUPPORTED;
     p.stage = stage;
     pl->lds_fwd = lds;
@@ -286,7 +304,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->absmax_bytes = absmax ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
     pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes;
     p.nabsmax = absmax ? wect::kAbsmaxSlots : 0;
-    p.cells_total = (double)std::max<int64_t>(elems, 1);
+    p.cells_total = (double)std::max<int64_t>(cells, 1);
   }
   if (need_bwd && g->d > 0 && g->T > 0) {
     int dg = std::min(ntiles, 4);
@@ -354,8 +372,9 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   }
   if (p.S > 0) {
     if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
-    if (hipError_t e = wect::launch_forward_main(p, pl.block, pl.lds_fwd, s); e != hipSuccess)
-      return device_error(e, "forward kernel");
+    const hipError_t le = p.ls ? wect::launch_smooth_ls_forward(p, pl.block, pl.lds_fwd, s)
+                               : wect::launch_forward_main(p, pl.block, pl.lds_fwd, s);
+    if (le != hipSuccess) return device_error(le, "forward kernel");
     if (prof) {
       if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
       std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -439,12 +458,13 @@ wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, cons
 // fixed-point accumulation; the adjoint takes one direction tile per block
 // pass (g and its reverse scan in LDS) over the stream of ntiles x cells.
 wect_status smooth_plan(const wect_complex* c, const wect_grid* g, float lam, bool need_fwd, bool need_bwd,
-                        Plan* pl) {
+                        Plan* pl, bool ls = false) {
   if (!c || !g) return WECT_ERR_ARG;
   if (!(lam >= 0.0f) || !std::isfinite(lam)) return WECT_ERR_ARG;
   if (c->kind != WECT_SIMPLICIAL) return WECT_ERR_UNSUPPORTED;
   if (c->wmode == WECT_W_EXPLICIT && c->dtype != WECT_F32) return WECT_ERR_UNSUPPORTED;
-  if (wect_status st = make_plan(c, g, need_fwd, false, pl, true); st != WECT_OK) return st;
+  if (wect_status st = make_plan(c, g, need_fwd, false, pl, true, ls); st != WECT_OK) return st;
+  pl->p.ls = ls ? 1 : 0;
   Params& p = pl->p;
   p.smooth = 1;
   p.dtype = WECT_F32;  // float32 output from 64-bit fixed point
@@ -454,11 +474,16 @@ wect_status smooth_plan(const wect_complex* c, const wect_grid* g, float lam, bo
   p.sm_r = (float)std::min(r, (double)FLT_MAX);
   if (need_bwd && g->d > 0 && g->T > 0) {
     int block = g_block.load();
-    if (!block) block = 1024;
+    if (!block) block = ls ? ls_block(g->T, true) : 1024;
     int stage = block;
-    while (stage > 64 && wect::smooth_backward_lds_bytes(g->T, stage) > kLdsLimit) stage /= 2;
-    if (wect::smooth_backward_lds_bytes(g->T, stage) > kLdsLimit) return WECT_ERR_UNSUPPORTED;
-    const size_t lds = wect::smooth_backward_lds_bytes(g->T, stage);
+    size_t lds = 0;
+    if (ls) {
+      lds = wect::smooth_ls_backward_lds_bytes(g->T, block);
+    } else {
+      while (stage > 64 && wect::smooth_backward_lds_bytes(g->T, stage) > kLdsLimit) stage /= 2;
+      lds = wect::smooth_backward_lds_bytes(g->T, stage);
+    }
+    if (lds > kLdsLimit) return WECT_ERR_UNSUPPORTED;
     DeviceInfo di;
     const int cus = device_info(&di) ? di.cus : 256;
     const int user = g_bpc.load();
@@ -498,7 +523,8 @@ wect_status run_smooth_backward(const Plan& pl0, const float* grad_out, float* g
   if (zero(grad_coords, p.count[0] * (int64_t)p.n) != hipSuccess) return WECT_ERR_DEVICE;
   if (zero(grad_dirs, (int64_t)p.d * p.n) != hipSuccess) return WECT_ERR_DEVICE;
   if (p.wmode == WECT_W_VERTEX_MAX && zero(grad_vertex, p.count[0]) != hipSuccess) return WECT_ERR_DEVICE;
-  if (p.wmode == WECT_W_EXPLICIT && (p.bwd_atomic || !work)) {
+  // the vertex-centric adjoint adds a cell's gradient from each of its vertices
+  if (p.wmode == WECT_W_EXPLICIT && (p.bwd_atomic || p.ls || !work)) {
     for (int i = 0; i <= p.top_dim; ++i)
       if (zero(p.grad_w[i], p.count[i]) != hipSuccess) return WECT_ERR_DEVICE;
   }
@@ -506,13 +532,33 @@ wect_status run_smooth_backward(const Plan& pl0, const float* grad_out, float* g
   const bool prof = g_profile.load() != 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
-  if (hipError_t e = wect::launch_smooth_backward(p, pl.sm_block, pl.lds_bwd, s); e != hipSuccess)
-    return device_error(e, "relaxation adjoint kernel");
+  const hipError_t le = p.ls ? wect::launch_smooth_ls_backward(p, pl.sm_block, pl.lds_bwd, s)
+                            : wect::launch_smooth_backward(p, pl.sm_block, pl.lds_bwd, s);
+  if (le != hipSuccess) return device_error(le, "relaxation adjoint kernel");
   if (prof) {
     if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back({e0, e1, 1});
   }
+  return WECT_OK;
+}
+
+// Lower-star index of a simplicial complex: layout from host counts.
+wect_status ls_check(const wect_complex* c, wect::LsLayout* L) {
+  if (!c || c->kind != WECT_SIMPLICIAL) return WECT_ERR_ARG;
+  const wect_grid g0 = {nullptr, 0, 0, nullptr};
+  Plan pl;
+  if (wect_status st = make_plan(c, &g0, false, false, &pl); st != WECT_OK) return st;
+  *L = wect::ls_layout(c->count[0], c->count, c->top_dim);
+  return WECT_OK;
+}
+
+// Binds a caller's index to a relaxation plan (vertex-centric kernels).
+wect_status ls_attach(const wect_complex* c, const void* index, size_t index_bytes, Plan* pl) {
+  wect::LsLayout L;
+  if (wect_status st = ls_check(c, &L); st != WECT_OK) return st;
+  if (!index || index_bytes < L.total || (reinterpret_cast<uintptr_t>(index) & 15)) return WECT_ERR_ARG;
+  wect::ls_bind(pl->p, const_cast<void*>(index), L);
   return WECT_OK;
 }
 
@@ -765,6 +811,48 @@ wect_status wect_smooth_backward(const wect_complex* c, const wect_grid* g, floa
                                  void* hip_stream) {
   Plan pl;
   if (wect_status st = smooth_plan(c, g, lam, false, true, &pl); st != WECT_OK) return st;
+  return run_smooth_backward(pl, grad_out, grad_coords, grad_dirs, grad_w, grad_vertex, (hipStream_t)hip_stream);
+}
+
+size_t wect_lower_star_bytes(const wect_complex* c) {
+  wect::LsLayout L;
+  if (ls_check(c, &L) != WECT_OK) return 0;
+  return L.total;
+}
+
+wect_status wect_lower_star_build(const wect_complex* c, void* index, size_t index_bytes, void* hip_stream) {
+  wect::LsLayout L;
+  if (wect_status st = ls_check(c, &L); st != WECT_OK) return st;
+  if (!index || index_bytes < L.total || (reinterpret_cast<uintptr_t>(index) & 15)) return WECT_ERR_ARG;
+  const wect_grid g0 = {nullptr, 0, 0, nullptr};
+  Plan pl;
+  if (wect_status st = make_plan(c, &g0, false, false, &pl); st != WECT_OK) return st;
+  wect::ls_bind(pl.p, index, L);
+  if (hipError_t e = wect::launch_lower_star_build(pl.p, L, static_cast<hipStream_t>(hip_stream)); e != hipSuccess)
+    return device_error(e, "lower-star index build");
+  return WECT_OK;
+}
+
+size_t wect_smooth_ls_workspace_bytes(const wect_complex* c, const wect_grid* g, float lam) {
+  Plan pl;
+  if (smooth_plan(c, g, lam, true, false, &pl, true) != WECT_OK) return 0;
+  return pl.ws_fwd;
+}
+
+wect_status wect_smooth_ls_forward(const wect_complex* c, const wect_grid* g, float lam, const void* index,
+                                   size_t index_bytes, float* out, void* ws, size_t ws_bytes, void* hip_stream) {
+  Plan pl;
+  if (wect_status st = smooth_plan(c, g, lam, true, false, &pl, true); st != WECT_OK) return st;
+  if (wect_status st = ls_attach(c, index, index_bytes, &pl); st != WECT_OK) return st;
+  return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
+wect_status wect_smooth_ls_backward(const wect_complex* c, const wect_grid* g, float lam, const void* index,
+                                    size_t index_bytes, const float* grad_out, float* grad_coords, float* grad_dirs,
+                                    float* const grad_w[4], float* grad_vertex, void* hip_stream) {
+  Plan pl;
+  if (wect_status st = smooth_plan(c, g, lam, false, true, &pl, true); st != WECT_OK) return st;
+  if (wect_status st = ls_attach(c, index, index_bytes, &pl); st != WECT_OK) return st;
   return run_smooth_backward(pl, grad_out, grad_coords, grad_dirs, grad_w, grad_vertex, (hipStream_t)hip_stream);
 }
 

@@ -61,6 +61,14 @@ struct Params {
   float sm_r;                    // window half-width in height units (kSmoothW / lam, capped at FLT_MAX)
   float* grad_coords;            // smooth adjoint: [count0, n], accumulated (pre-zeroed); may be null
   float* grad_dirs;              // smooth adjoint: [d, n], accumulated (pre-zeroed); may be null
+  // lower-star index (relaxation, vertex-centric kernels): the stream runs over vertices
+  int32_t ls;                    // 1: stream elements are vertices, cofaces read from the index
+  int64_t* ls_hdr;               // [4]: [0] entries, [1] largest vertex degree (device-written)
+  int64_t* ls_off;               // [V+1] CSR offsets of each vertex's cofaces
+  int64_t* ls_cur;               // [V] build: counts, then fill cursors
+  int64_t* ls_part;              // build: scan partial sums
+  int32_t* ls_ent;               // [entries][4]: dim, then the other vertices' global rows (-1 pad)
+  int64_t* ls_row;               // [entries]: the coface's row within its dimension
 };
 
 // Sigmoid terms with |lam (thr - h)| > kSmoothW are taken as 0 (below) or 1
@@ -87,6 +95,22 @@ constexpr int kEcfRowBytes = 256 * 4;  // one image's sums over the intensity va
 hipError_t launch_absmax(const Params& p, hipStream_t s);
 // n = 0: threshold index of every filter value (first pass of the general-filter WECF).
 hipError_t launch_vertex_buckets(const Params& p, int64_t nvals, hipStream_t s);
+
+// Lower-star index: layout inside one caller buffer, and its build (count,
+// scan, fill: five kernels, no allocation).
+struct LsLayout {
+  size_t hdr, off, cur, part, ent, row, total;
+  int64_t nent, nparts;
+};
+LsLayout ls_layout(int64_t V, const int64_t count[4], int top_dim);
+void ls_bind(Params& p, void* base, const LsLayout& L);
+hipError_t launch_lower_star_build(const Params& p, const LsLayout& L, hipStream_t s);
+// Vertex-centric relaxation kernels (p.ls = 1).
+hipError_t launch_smooth_ls_forward(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+hipError_t launch_smooth_ls_backward(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+size_t smooth_ls_forward_lds_bytes(int T, int block);
+size_t smooth_ls_backward_lds_bytes(int T, int block);
+constexpr int kLsChunk = 8192;  // elements per block of the build's scan
 
 // LDS bytes of the forward kernels: fixed part (histogram, thresholds) plus
 // forward_entry_bytes per staged entry; of the backward kernel in total.

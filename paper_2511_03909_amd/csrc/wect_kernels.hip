@@ -27,6 +27,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include <atomic>
 
 #pragma clang fp contract(off)
@@ -299,6 +301,31 @@ __device__ __forceinline__ int round_half_up(float x) {
 // on all of C.  The histogram holds differences (F_lo at lo, F_q - F_{q-1} at
 // q, C - F_{hi-1} at hi), so the threshold scan that follows returns exactly
 // these values.  |C| < 2^30, so every F_q and difference fits in int32.
+template <bool FAST>
+__device__ __forceinline__ void smooth_add(uint64_t* col, float h, uint64_t C, const Thr& th, float R, float kap) {
+  const int lo = thr_index<FAST>(h - R, th);
+  const int hi = thr_index<FAST>(next_up(h + R), th);
+  const float cf = (float)(int32_t)(uint32_t)C;
+  auto term = [&](int q) {
+    float ex;
+    return round_half_up(cf * sigmoid2((th.P[q + 1] - h) * kap, ex));
+  };
+  // two terms per iteration: half the loop control, and no register copy
+  int prev = 0, q = lo;
+  for (; q + 1 < hi; q += 2) {
+    const int F0 = term(q), F1 = term(q + 1);
+    lds_add(&col[q * W], (uint64_t)(int64_t)(F0 - prev));
+    lds_add(&col[(q + 1) * W], (uint64_t)(int64_t)(F1 - F0));
+    prev = F1;
+  }
+  if (q < hi) {
+    const int F = term(q);
+    lds_add(&col[q * W], (uint64_t)(int64_t)(F - prev));
+    prev = F;
+  }
+  lds_add(&col[hi * W], C - (uint64_t)(int64_t)prev);
+}
+
 template <bool FAST, typename Entry>
 __device__ __forceinline__ void smooth_entries(uint64_t* col, int first, int step, int ne, const Thr& th, float R,
                                                float kap, Entry entry) {
@@ -306,27 +333,7 @@ __device__ __forceinline__ void smooth_entries(uint64_t* col, int first, int ste
     float h;
     uint64_t C;
     entry(e, h, C);
-    const int lo = thr_index<FAST>(h - R, th);
-    const int hi = thr_index<FAST>(next_up(h + R), th);
-    const float cf = (float)(int32_t)(uint32_t)C;
-    auto term = [&](int q) {
-      float ex;
-      return round_half_up(cf * sigmoid2((th.P[q + 1] - h) * kap, ex));
-    };
-    // two terms per iteration: half the loop control, and no register copy
-    int prev = 0, q = lo;
-    for (; q + 1 < hi; q += 2) {
-      const int F0 = term(q), F1 = term(q + 1);
-      lds_add(&col[q * W], (uint64_t)(int64_t)(F0 - prev));
-      lds_add(&col[(q + 1) * W], (uint64_t)(int64_t)(F1 - F0));
-      prev = F1;
-    }
-    if (q < hi) {
-      const int F = term(q);
-      lds_add(&col[q * W], (uint64_t)(int64_t)(F - prev));
-      prev = F;
-    }
-    lds_add(&col[hi * W], C - (uint64_t)(int64_t)prev);
+    smooth_add<FAST>(col, h, C, th, R, kap);
   }
 }
 
@@ -393,6 +400,10 @@ __device__ __forceinline__ float sum_scatter8(const float (&v)[8]) {
 // Number of stream elements (cells handled one by one) of the complexes
 // before complex b: all simplices of all dimensions, or all voxels.
 __device__ __forceinline__ int64_t cum_elems(const Params& p, int b) {
+  if (p.ls) {  // vertex-centric kernels: one stream element per vertex
+    if (!p.vert_off) return b == 0 ? 0 : p.count[0];
+    return p.vert_off[b];
+  }
   if (p.kind == 1) {
     if (p.grid_off) return p.grid_off[b];
     return b == 0 ? 0 : p.total_voxels;
@@ -474,8 +485,11 @@ __device__ __forceinline__ int fixed_exp(const Params& p) {
   (void)frexp(X, &ex);  // X = f 2^ex, f in [0.5, 1): floor(log2 X) = ex - 1
   int e = 61 - (ex - 1);
   if (p.smooth) {
+    // vertex-centric kernels combine a vertex's weight with those of its
+    // cofaces: at most (1 + largest degree) M
+    const double Mc = p.ls ? (double)M * (double)(1 + p.ls_hdr[1]) : (double)M;
     int em = 0;
-    (void)frexp((double)M, &em);  // M < 2^em
+    (void)frexp(Mc, &em);  // Mc < 2^em
     e = min(e, 30 - em);
   }
   return e;
@@ -1734,6 +1748,570 @@ __global__ __launch_bounds__(1024) void k_smooth_bwd(Params p) {
 }
 
 // ---------------------------------------------------------------------------
+// lower-star index and the vertex-centric relaxation
+// ---------------------------------------------------------------------------
+//
+// Every cell c has one vertex a_p(c) attaining its maximum height for
+// direction p (lowest id among equal heights), and its relaxed term is
+// sig(lam (t - h_p(a))).  Grouping the cells by that vertex, the relaxation is
+//   S[p][q] = sum over vertices v of W_p(v) sig(lam (thr[q] - h_p(v))),
+//   W_p(v) = sum of the signed weights of the cells c with a_p(c) = v,
+// so one sigmoid window per vertex and direction replaces one per cell and
+// direction.  W_p(v) needs the cells that contain v (the lower star of v is
+// the part of them that v tops): the index lists, for every vertex (global
+// row), the simplices of dimension >= 1 that contain it, as {dim, the other
+// vertices' global rows (-1 padded)} and the simplex's row.  It depends on the
+// simplex lists only, so one build serves every call on the same topology.
+// Build: one atomic count per incidence, an exclusive scan of the counts
+// (per-chunk sums, one-block scan of the sums, per-chunk scan), and a fill
+// through per-vertex cursors.  The order of a vertex's entries follows the
+// atomics; no result depends on it.
+
+// complex of simplex row r of dimension dim: largest b with simp_off[dim][b] <= r
+__device__ __forceinline__ int complex_of_row(const Params& p, int dim, int64_t r) {
+  const int64_t* so = p.simp_off[dim];
+  if (!so) return 0;
+  int lo = 0, hi = p.B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (so[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Global rows of the dim+1 vertices of simplex (dim, r); entries past dim are 0.
+__device__ __forceinline__ void simplex_rows(const Params& p, int dim, int64_t r, int32_t (&g)[4]) {
+  const int b = complex_of_row(p, dim, r);
+  const int32_t voff = (int32_t)off_or(p.vert_off, b, p.count[0]);
+  const int32_t* sp = p.simp[dim] + r * (dim + 1);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) g[j] = j <= dim ? voff + sp[j] : 0;
+}
+
+__global__ __launch_bounds__(256) void k_ls_count(Params p) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int dim = 1; dim <= p.top_dim; ++dim) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.count[dim]; r += stride) {
+      int32_t g[4];
+      simplex_rows(p, dim, r, g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j <= dim) atomicAdd((unsigned long long*)&p.ls_cur[g[j]], 1ull);
+    }
+  }
+}
+
+// Sum over a block of 256 threads (every thread gets it); red holds 256 values.
+__device__ __forceinline__ int64_t block_sum256(int64_t v, int64_t* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const int64_t r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// per chunk of kLsChunk vertices: the sum of the counts, and the largest count
+__global__ __launch_bounds__(256) void k_ls_scan_parts(Params p) {
+  __shared__ int64_t red[256];
+  const int64_t V = p.count[0];
+  const int64_t c0 = (int64_t)blockIdx.x * kLsChunk, c1 = mn64(V, c0 + kLsChunk);
+  int64_t sum = 0, mx = 0;
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    const int64_t c = p.ls_cur[i];
+    sum += c;
+    mx = mx64(mx, c);
+  }
+  sum = block_sum256(sum, red);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = mx64(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    p.ls_part[blockIdx.x] = sum;
+    atomicMax((unsigned long long*)&p.ls_hdr[1], (unsigned long long)red[0]);
+  }
+}
+
+// exclusive scan of the nparts chunk sums, in place (one block)
+__global__ __launch_bounds__(1024) void k_ls_scan_top(Params p, int64_t nparts) {
+  __shared__ int64_t tot[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t per = (nparts + nt - 1) / nt;
+  const int64_t a = mn64(nparts, tid * per), z = mn64(nparts, a + per);
+  int64_t s = 0;
+  for (int64_t i = a; i < z; ++i) s += p.ls_part[i];
+  tot[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < nt; o <<= 1) {
+    const int64_t add = tid >= o ? tot[tid - o] : 0;
+    __syncthreads();
+    tot[tid] += add;
+    __syncthreads();
+  }
+  int64_t run = tot[tid] - s;
+  for (int64_t i = a; i < z; ++i) {
+    const int64_t c = p.ls_part[i];
+    p.ls_part[i] = run;
+    run += c;
+  }
+}
+
+// offsets (off[v+1] = counts up to v) and fill cursors (cur[v] = off[v]) of one
+// chunk: every thread scans kLsChunk / 256 consecutive counts
+__global__ __launch_bounds__(256) void k_ls_scan_apply(Params p) {
+  __shared__ int64_t tot[256];
+  constexpr int PER = kLsChunk / 256;
+  const int64_t V = p.count[0];
+  const int tid = threadIdx.x;
+  const int64_t a = (int64_t)blockIdx.x * kLsChunk + (int64_t)tid * PER;
+  int64_t c[PER];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    c[k] = a + k < V ? p.ls_cur[a + k] : 0;
+    s += c[k];
+  }
+  tot[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int64_t add = tid >= o ? tot[tid - o] : 0;
+    __syncthreads();
+    tot[tid] += add;
+    __syncthreads();
+  }
+  int64_t run = p.ls_part[blockIdx.x] + tot[tid] - s;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (a + k < V) {
+      p.ls_cur[a + k] = run;
+      run += c[k];
+      p.ls_off[a + k + 1] = run;
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) p.ls_off[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_ls_fill(Params p) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int dim = 1; dim <= p.top_dim; ++dim) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.count[dim]; r += stride) {
+      int32_t g[4];
+      simplex_rows(p, dim, r, g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j <= dim) {
+          const int64_t pos = (int64_t)atomicAdd((unsigned long long*)&p.ls_cur[g[j]], 1ull);
+          // the other vertices in their order within the simplex
+          int32_t o[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int src = k < j ? k : k + 1;  // skip slot j
+            o[k] = src <= dim ? g[src] : -1;
+          }
+          int4 e;
+          e.x = dim;
+          e.y = o[0];
+          e.z = o[1];
+          e.w = o[2];
+          ((int4*)p.ls_ent)[pos] = e;
+          p.ls_row[pos] = r;
+        }
+      }
+    }
+  }
+}
+
+// Cofaces are staged per wavefront.  A wavefront takes groups of kLsGroup
+// consecutive vertices; their cofaces are consecutive in the index, so as
+// many of the group's vertices as have at most kLsRows cofaces together are
+// staged at once: lane r loads coface row r (its entry, then the other
+// vertices' coordinates and weights, all rows in flight at once), lane t < nv
+// loads vertex t's coordinates and own weight, and every lane then reads the
+// rows as broadcasts.  A vertex with more than kLsRows cofaces is staged in
+// chunks on its own.  Coface row layout (floats):
+//   [3k .. 3k+N-1]  coordinates of the k-th other vertex (k < dim)
+//   [9 + k]         its global row (-1 past dim)
+//   [12] dim, [13] signed weight (-1)^dim w, [14..15] simplex row (int64),
+//   [16] owner: lowest-numbered vertex of largest vertex weight (vertex-max)
+// Vertex rows: [4t .. 4t+N-1] coordinates, [4t+3] own weight.
+constexpr int kLsStride = 17;
+constexpr int kLsRows = 64;   // staged coface rows per wavefront
+constexpr int kLsGroup = 8;   // vertices per wavefront group
+
+template <int N, int WM, bool BWD>
+__device__ __forceinline__ void ls_stage(const Params& p, int64_t e, int32_t gv, float* dst) {
+  const int4 en = ((const int4*)p.ls_ent)[e];
+  const int dim = en.x;
+  const int32_t o[3] = {en.y, en.z, en.w};
+  const float* vw = (const float*)p.weights[0];
+  float wm = 0.0f;
+  int32_t own = gv;
+  if constexpr (WM == WM_VMAX) wm = vw[gv];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < dim) {
+      const float* c = p.coords + (int64_t)o[k] * N;
+#pragma unroll
+      for (int cc = 0; cc < N; ++cc) dst[3 * k + cc] = c[cc];
+      if constexpr (WM == WM_VMAX) {
+        const float x = vw[o[k]];
+        if (x > wm || (x == wm && o[k] < own)) { wm = x; own = o[k]; }
+      }
+    }
+    dst[9 + k] = bitcast<float>(k < dim ? o[k] : -1);
+  }
+  float w = 1.0f;
+  int64_t row = 0;
+  if constexpr (WM == WM_EXPLICIT || BWD) row = p.ls_row[e];
+  if constexpr (WM == WM_EXPLICIT) w = ((const float*)p.weights[dim])[row];
+  else if constexpr (WM == WM_VMAX) w = wm;
+  dst[12] = bitcast<float>(dim);
+  dst[13] = (dim & 1) ? -w : w;
+  if constexpr (BWD) {
+    dst[14] = bitcast<float>((uint32_t)row);
+    dst[15] = bitcast<float>((uint32_t)((uint64_t)row >> 32));
+    dst[16] = bitcast<float>(own);
+  }
+}
+
+// LDS writes of a wavefront made visible to its other lanes (and reads
+// finished before the rows are overwritten).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Does vertex gv (height hv for the lane) attain the maximum height of the
+// staged coface E?  Ties go to the lowest global row.  The row's dimension is
+// the same for every lane (a broadcast read), so the loop over the other
+// vertices branches on a scalar; the common case is decided by the largest
+// other height, and only a wavefront with a lane on a tie takes the exact
+// per-vertex test.
+template <int N>
+__device__ __forceinline__ bool ls_top(const float* E, int32_t gv, float hv, float sx, float sy, float sz) {
+  const int dim = uniform(bitcast<int>(E[12]));
+  float ho[3];
+  float hmax = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k < dim) {
+      ho[k] = height<N>(E + 3 * k, sx, sy, sz);
+      hmax = fmaxf(hmax, ho[k]);
+    }
+  }
+  bool top = hv > hmax;
+  if (__builtin_amdgcn_ballot_w64(hv == hmax) != 0) {
+    top = hv >= hmax;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k < dim) top = top && (ho[k] < hv || bitcast<int32_t>(E[9 + k]) > gv);
+    }
+  }
+  return top;
+}
+
+template <int WM>
+__device__ __forceinline__ float ls_self_weight(const Params& p, int32_t gv) {
+  if constexpr (WM == WM_ONES) return 1.0f;
+  else return ((const float*)p.weights[0])[gv];  // explicit vertex weight, or the vertex weight itself
+}
+
+// Walks the vertices [lo, hi) (local numbering, global row voff + v) of the
+// wavefront's groups: begin(gv, xv, wself), then rows(S, r0, r1) for the
+// vertex's coface rows (possibly in several chunks), then end().
+template <int N, int WM, bool BWD, typename Begin, typename Rows, typename End>
+__device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi, int64_t voff, float* S, float* Vr,
+                                        Begin begin, Rows rows, End end) {
+  const int lane = threadIdx.x & (W - 1);
+  const int wave = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  for (int64_t vg = lo + (int64_t)wave * kLsGroup; vg < hi; vg += (int64_t)nw * kLsGroup) {
+    const int64_t vend = mn64(vg + kLsGroup, hi);
+    int64_t i = vg;
+    while (i < vend) {
+      const int64_t rb = p.ls_off[voff + i];
+      int64_t j = i + 1;
+      while (j < vend && p.ls_off[voff + j + 1] - rb <= kLsRows) ++j;
+      const int nv = (int)(j - i);
+      const int64_t nrows = p.ls_off[voff + j] - rb;
+      // vertex rows
+      if (lane < nv) {
+        const int32_t gv = (int32_t)(voff + i + lane);
+        const float* c = p.coords + (int64_t)gv * N;
+#pragma unroll
+        for (int cc = 0; cc < N; ++cc) Vr[4 * lane + cc] = c[cc];
+        Vr[4 * lane + 3] = ls_self_weight<WM>(p, gv);
+      }
+      if (nrows <= kLsRows) {
+        if (lane < nrows) {
+          // the vertex this row belongs to: rows of vertex t start at off[i + t] - rb
+          int t = 0;
+#pragma unroll
+          for (int k = 1; k < kLsGroup; ++k)
+            if (k < nv && p.ls_off[voff + i + k] - rb <= lane) t = k;
+          ls_stage<N, WM, BWD>(p, rb + lane, (int32_t)(voff + i + t), S + lane * kLsStride);
+        }
+        wave_lds_sync();
+        for (int t = 0; t < nv; ++t) {
+          const int32_t gv = (int32_t)(voff + i + t);
+          begin(gv, Vr + 4 * t, Vr[4 * t + 3]);
+          rows(S, (int)(p.ls_off[gv] - rb), (int)(p.ls_off[gv + 1] - rb));
+          end();
+        }
+        wave_lds_sync();
+      } else {  // one vertex with more than kLsRows cofaces, in chunks
+        const int32_t gv = (int32_t)(voff + i);
+        wave_lds_sync();
+        begin(gv, Vr, Vr[3]);
+        for (int64_t c0 = 0; c0 < nrows; c0 += kLsRows) {
+          const int m = (int)mn64(kLsRows, nrows - c0);
+          if (lane < m) ls_stage<N, WM, BWD>(p, rb + c0 + lane, gv, S + lane * kLsStride);
+          wave_lds_sync();
+          rows(S, 0, m);
+          wave_lds_sync();
+        }
+        end();
+      }
+      i = j;
+    }
+  }
+}
+
+// Forward over vertices [lo, hi) of one complex: each lane combines the
+// vertex's own weight with its cofaces' signed weights where the vertex tops
+// them (float64 sum, then the fixed-point grid), and adds one sigmoid window.
+template <int N, int WM, bool FAST>
+__device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, float sx,
+                                             float sy, float sz, uint64_t* hist, float* stage, const Thr& th,
+                                             int fexp) {
+  const int lane = threadIdx.x & (W - 1);
+  const int wave = uniform(threadIdx.x >> 6);
+  float* S = stage + (size_t)wave * (kLsRows * kLsStride + 4 * kLsGroup);
+  float* Vr = S + kLsRows * kLsStride;
+  int32_t gv = 0;
+  float hv = 0.0f;
+  double Wc = 0.0;
+  ls_walk<N, WM, false>(
+      p, lo, hi, voff, S, Vr,
+      [&](int32_t g, const float* xv, float wself) {
+        gv = g;
+        hv = height<N>(xv, sx, sy, sz);
+        Wc = wself;
+      },
+      [&](const float* Sr, int r0, int r1) {
+        for (int r = r0; r < r1; ++r) {
+          const float* E = Sr + r * kLsStride;
+          Wc += ls_top<N>(E, gv, hv, sx, sy, sz) ? (double)E[13] : 0.0;
+        }
+      },
+      [&]() {
+        const uint64_t C = (uint64_t)(int64_t)rint(ldexp(Wc, fexp));
+        smooth_add<FAST>(hist + lane, hv, C, th, p.sm_r, p.sm_k);
+      });
+}
+
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_smooth_ls_fwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T;
+  uint64_t* hist = (uint64_t*)smem;
+  float* P = (float*)(smem + (size_t)(T + 1) * W * 8);
+  float* stage = (float*)((unsigned char*)P + align_up((size_t)(T + 1) * 4, 16));
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = 0;
+  const int fexp = fixed_exp(p);
+  __syncthreads();
+  const int k = blockIdx.x;
+  int64_t pos, end;
+  int b;
+  if (!block_range<uint64_t>(p, hist, k, fexp, pos, end, b)) return;
+  const int gpc = p.ntiles;
+  const int lane = threadIdx.x & (W - 1);
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int t = (int)((pos - base) / nb);
+    const int64_t e0 = (pos - base) - (int64_t)t * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    float sx, sy, sz;
+    load_dir(p, t * W + lane, sx, sy, sz);
+    const int64_t voff = off_or(p.vert_off, b, p.count[0]);
+    if (th.fast) ls_fwd_range<N, WM, true>(p, e0, e1, voff, sx, sy, sz, hist, stage, th, fexp);
+    else ls_fwd_range<N, WM, false>(p, e0, e1, voff, sx, sy, sz, hist, stage, th, fexp);
+    end_group<uint64_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, fexp);
+    pos += e1 - e0;
+    if (e1 == nb && t == gpc - 1) ++b;
+  }
+}
+
+// Adjoint over vertices [lo, hi) of one complex.  Per vertex and lane: the
+// window sums u = G[hi] + sum g sig and v = sum g sig (1 - sig) (they depend on
+// the vertex's height only); then the staged cofaces, eight at a time: each
+// adds its signed weight to W where the vertex tops it, and the sum over the
+// lanes of u where it does is that cell's weight gradient (eight-value
+// reduce-scatter; lanes 0..7 add it).  Finally dh = -lam W v: the vertex's
+// coordinate gradient is the lane sum of dh s_p (reduced together with the
+// vertex's own weight gradient, the lane sum of u), and the direction
+// gradient accumulates dh l(v) per lane.
+template <int N, int WM, bool FAST>
+__device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, float sx,
+                                             float sy, float sz, const float* g, const float* Gs, float* stage,
+                                             const Thr& th, float (&gd)[3]) {
+  const int lane = threadIdx.x & (W - 1);
+  const int wave = uniform(threadIdx.x >> 6);
+  const float R = p.sm_r, kap = p.sm_k, lam = p.sm_lam;
+  float* S = stage + (size_t)wave * (kLsRows * kLsStride + 4 * kLsGroup);
+  float* Vr = S + kLsRows * kLsStride;
+  int32_t gv = 0;
+  float hv = 0.0f, u = 0.0f, vs = 0.0f, Wc = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+  ls_walk<N, WM, true>(
+      p, lo, hi, voff, S, Vr,
+      [&](int32_t gvi, const float* xv, float wself) {
+        gv = gvi;
+        x0 = xv[0];
+        if (N >= 2) x1 = xv[1];
+        if (N >= 3) x2 = xv[2];
+        hv = height<N>(xv, sx, sy, sz);
+        const int qlo = thr_index<FAST>(hv - R, th);
+        const int qhi = thr_index<FAST>(next_up(hv + R), th);
+        float ua = Gs[qhi * W + lane], va = 0.0f, ub = 0.0f, vb = 0.0f;
+        auto term = [&](int q, float& uu, float& vv) {
+          float ex;
+          const float sg = sigmoid2((th.P[q + 1] - hv) * kap, ex);
+          const float gq = g[q * W + lane];
+          uu = __builtin_fmaf(gq, sg, uu);
+          vv = __builtin_fmaf(gq, ex * sg * sg, vv);
+        };
+        int q = qlo;
+        for (; q + 1 < qhi; q += 2) {
+          term(q, ua, va);
+          term(q + 1, ub, vb);
+        }
+        if (q < qhi) term(q, ua, va);
+        u = ua + ub;
+        vs = va + vb;
+        Wc = wself;
+      },
+      [&](const float* Sr, int r0, int r1) {
+        for (int j0 = r0; j0 < r1; j0 += 8) {
+          float v8[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const float* E = Sr + min(j0 + k, r1 - 1) * kLsStride;  // past r1: a valid row, weighed 0
+            const bool top = j0 + k < r1 && ls_top<N>(E, gv, hv, sx, sy, sz);
+            Wc += top ? E[13] : 0.0f;
+            v8[k] = top ? u : 0.0f;
+          }
+          if constexpr (WM != WM_ONES) {
+            const float tot = sum_scatter8(v8);
+            if (lane < 8 && j0 + lane < r1) {
+              const float* E = Sr + (j0 + lane) * kLsStride;
+              const int dim = bitcast<int>(E[12]);
+              const float gw = (dim & 1) ? -tot : tot;
+              if constexpr (WM == WM_VMAX) {
+                if (p.grad_vertex) atomicAdd(p.grad_vertex + bitcast<int32_t>(E[16]), gw);
+              } else {
+                const int64_t row =
+                    (int64_t)(((uint64_t)bitcast<uint32_t>(E[15]) << 32) | bitcast<uint32_t>(E[14]));
+                float* gwp = p.grad_w[dim];
+                if (gwp) atomicAdd(gwp + row, gw);
+              }
+            }
+          }
+        }
+      },
+      [&]() {
+        const float dh = -Wc * lam * vs;
+        float c8[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c8[k] = 0.0f;
+        c8[0] = dh * sx;
+        if (N >= 2) c8[1] = dh * sy;
+        if (N >= 3) c8[2] = dh * sz;
+        c8[3] = u;  // the vertex's own weight gradient
+        gd[0] = __builtin_fmaf(dh, x0, gd[0]);
+        if (N >= 2) gd[1] = __builtin_fmaf(dh, x1, gd[1]);
+        if (N >= 3) gd[2] = __builtin_fmaf(dh, x2, gd[2]);
+        const float tot = sum_scatter8(c8);
+        if (lane < N && p.grad_coords) atomicAdd(p.grad_coords + (int64_t)gv * N + lane, tot);
+        if constexpr (WM != WM_ONES) {
+          if (lane == 3) {
+            float* gwp = WM == WM_VMAX ? p.grad_vertex : p.grad_w[0];
+            if (gwp) atomicAdd(gwp + gv, tot);
+          }
+        }
+      });
+}
+
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_smooth_ls_bwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T, T1 = T + 1;
+  float* g = (float*)smem;
+  float* Gs = g + (size_t)T * W;
+  float* P = Gs + (size_t)T1 * W;
+  float* stage = (float*)((unsigned char*)P + align_up((size_t)T1 * 4, 16));
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  __syncthreads();
+  const int k = blockIdx.x;
+  int64_t pos = block_start(k, p.S, p.G);
+  const int64_t end = block_start(k + 1, p.S, p.G);
+  if (pos >= end) return;
+  const int gpc = p.ntiles;
+  int b = find_complex(p, pos, gpc);
+  const int tid = threadIdx.x, lane = tid & (W - 1), wave = tid >> 6;
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int t = (int)((pos - base) / nb);
+    const int64_t e0 = (pos - base) - (int64_t)t * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    const int gp = t * W + lane;
+    float sx, sy, sz;
+    load_dir(p, gp, sx, sy, sz);
+    __syncthreads();
+    for (int i = tid; i < W * T; i += blockDim.x) {
+      const int r = i / T, q = i - r * T;
+      const int dir = t * W + r;
+      g[(size_t)q * W + r] = dir < p.d ? p.grad_out[((int64_t)b * p.d + dir) * T + q] : 0.0f;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      Gs[(size_t)T * W + lane] = 0.0f;
+      double acc = 0.0;
+      for (int q = T - 1; q >= 0; --q) {
+        acc += (double)g[(size_t)q * W + lane];
+        Gs[(size_t)q * W + lane] = (float)acc;
+      }
+    }
+    __syncthreads();
+    float gd[3] = {0.0f, 0.0f, 0.0f};
+    const int64_t voff = off_or(p.vert_off, b, p.count[0]);
+    if (th.fast) ls_bwd_range<N, WM, true>(p, e0, e1, voff, sx, sy, sz, g, Gs, stage, th, gd);
+    else ls_bwd_range<N, WM, false>(p, e0, e1, voff, sx, sy, sz, g, Gs, stage, th, gd);
+    if (p.grad_dirs && gp < p.d) {
+#pragma unroll
+      for (int kk = 0; kk < N; ++kk) atomicAdd(p.grad_dirs + (int64_t)gp * N + kk, gd[kk]);
+    }
+    pos += e1 - e0;
+    if (e1 == nb && t == gpc - 1) ++b;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
 
@@ -2306,6 +2884,102 @@ hipError_t launch_smooth_backward(const Params& p, int block, size_t lds, hipStr
     case 1: return launch_sm_bwd_n<1>(p, block, lds, s);
     case 2: return launch_sm_bwd_n<2>(p, block, lds, s);
     default: return launch_sm_bwd_n<3>(p, block, lds, s);
+  }
+}
+
+LsLayout ls_layout(int64_t V, const int64_t count[4], int top_dim) {
+  LsLayout L;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  L.nent = 0;
+  for (int d = 1; d <= top_dim; ++d) L.nent += (int64_t)(d + 1) * count[d];
+  L.nparts = V > 0 ? (V + kLsChunk - 1) / kLsChunk : 1;
+  L.hdr = 0;
+  L.off = L.hdr + al(4 * 8);
+  L.cur = L.off + al((size_t)(V + 1) * 8);
+  L.part = L.cur + al((size_t)V * 8);
+  L.ent = L.part + al((size_t)L.nparts * 8);
+  L.row = L.ent + al((size_t)L.nent * 16);
+  L.total = L.row + al((size_t)L.nent * 8);
+  return L;
+}
+
+void ls_bind(Params& p, void* base, const LsLayout& L) {
+  unsigned char* b = static_cast<unsigned char*>(base);
+  p.ls_hdr = (int64_t*)(b + L.hdr);
+  p.ls_off = (int64_t*)(b + L.off);
+  p.ls_cur = (int64_t*)(b + L.cur);
+  p.ls_part = (int64_t*)(b + L.part);
+  p.ls_ent = (int32_t*)(b + L.ent);
+  p.ls_row = (int64_t*)(b + L.row);
+}
+
+hipError_t launch_lower_star_build(const Params& p, const LsLayout& L, hipStream_t s) {
+  const int64_t V = p.count[0];
+  // header and counts start at zero (fill kernels: capture-safe)
+  if (hipError_t e = launch_fill_zero((float*)p.ls_hdr, 8, s); e != hipSuccess) return e;
+  if (hipError_t e = launch_fill_zero((float*)p.ls_cur, 2 * V, s); e != hipSuccess) return e;
+  if (V == 0) return launch_fill_zero((float*)p.ls_off, 2, s);
+  int64_t kmax = 0;
+  for (int d = 1; d <= p.top_dim; ++d) kmax = kmax > p.count[d] ? kmax : p.count[d];
+  const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (kmax + 255) / 256));
+  hipLaunchKernelGGL(k_ls_count, dim3(gb), dim3(256), 0, s, p);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_scan_parts, dim3((unsigned)L.nparts), dim3(256), 0, s, p);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_scan_top, dim3(1), dim3(1024), 0, s, p, L.nparts);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_scan_apply, dim3((unsigned)L.nparts), dim3(256), 0, s, p);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_fill, dim3(gb), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+size_t smooth_ls_forward_lds_bytes(int T, int block) {
+  return (size_t)(T + 1) * W * 8 + ((size_t)(T + 1) * 4 + 15) / 16 * 16 +
+         (size_t)(block / W) * (kLsRows * kLsStride + 4 * kLsGroup) * 4;
+}
+
+size_t smooth_ls_backward_lds_bytes(int T, int block) {
+  return (size_t)(2 * T + 1) * W * 4 + ((size_t)(T + 1) * 4 + 15) / 16 * 16 +
+         (size_t)(block / W) * (kLsRows * kLsStride + 4 * kLsGroup) * 4;
+}
+
+template <int N, int WM>
+static hipError_t launch_ls_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_smooth_ls_fwd<N, WM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_smooth_ls_fwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int N, int WM>
+static hipError_t launch_ls_bwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_smooth_ls_bwd<N, WM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_smooth_ls_bwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_ls_n(const Params& p, int block, size_t lds, hipStream_t s, bool bwd) {
+  if (p.wmode == WM_ONES) return bwd ? launch_ls_bwd_t<N, WM_ONES>(p, block, lds, s)
+                                     : launch_ls_fwd_t<N, WM_ONES>(p, block, lds, s);
+  if (p.wmode == WM_EXPLICIT) return bwd ? launch_ls_bwd_t<N, WM_EXPLICIT>(p, block, lds, s)
+                                         : launch_ls_fwd_t<N, WM_EXPLICIT>(p, block, lds, s);
+  return bwd ? launch_ls_bwd_t<N, WM_VMAX>(p, block, lds, s) : launch_ls_fwd_t<N, WM_VMAX>(p, block, lds, s);
+}
+
+hipError_t launch_smooth_ls_forward(const Params& p, int block, size_t lds, hipStream_t s) {
+  switch (p.n) {
+    case 1: return launch_ls_n<1>(p, block, lds, s, false);
+    case 2: return launch_ls_n<2>(p, block, lds, s, false);
+    default: return launch_ls_n<3>(p, block, lds, s, false);
+  }
+}
+
+hipError_t launch_smooth_ls_backward(const Params& p, int block, size_t lds, hipStream_t s) {
+  switch (p.n) {
+    case 1: return launch_ls_n<1>(p, block, lds, s, true);
+    case 2: return launch_ls_n<2>(p, block, lds, s, true);
+    default: return launch_ls_n<3>(p, block, lds, s, true);
   }
 }
 

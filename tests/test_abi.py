@@ -283,3 +283,28 @@ def test_smooth_metadata(lib):
     for i in range(3):
         exf.weights[i] = FAKE
     assert lib.wect_smooth_workspace_bytes(ctypes.byref(exf), ctypes.byref(g), 1.0) > nb
+
+
+def test_lower_star_metadata(lib):
+    """The lower-star index: its size depends on the counts; a missing or too
+    small index is refused before any launch."""
+    c, g = _simplicial(), _grid()
+    nb = lib.wect_lower_star_bytes(ctypes.byref(c))
+    assert nb > 0
+    big = _simplicial()
+    big.count[0], big.count[1], big.count[2] = 30, 60, 31
+    assert lib.wect_lower_star_bytes(ctypes.byref(big)) > nb
+    assert lib.wect_lower_star_build(ctypes.byref(c), None, nb, None) == L.WECT_ERR_ARG
+    assert lib.wect_lower_star_build(ctypes.byref(c), FAKE, nb - 1, None) == L.WECT_ERR_ARG
+    assert lib.wect_lower_star_build(ctypes.byref(c), FAKE + 4, nb, None) == L.WECT_ERR_ARG  # misaligned
+    cub = L.WectComplex()
+    cub.kind, cub.n, cub.B = L.WECT_CUBICAL, 2, 1
+    assert lib.wect_lower_star_bytes(ctypes.byref(cub)) == 0
+    ws = lib.wect_smooth_ls_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 2.0)
+    assert ws > 0
+    assert lib.wect_smooth_ls_forward(ctypes.byref(c), ctypes.byref(g), 2.0, None, 0, FAKE, FAKE, ws, None) == \
+        L.WECT_ERR_ARG
+    assert lib.wect_smooth_ls_forward(ctypes.byref(c), ctypes.byref(g), 2.0, FAKE, nb - 1, FAKE, FAKE, ws, None) == \
+        L.WECT_ERR_ARG
+    assert lib.wect_smooth_ls_backward(ctypes.byref(c), ctypes.byref(g), -1.0, FAKE, nb, FAKE, None, None, None,
+                                       None, None) == L.WECT_ERR_ARG

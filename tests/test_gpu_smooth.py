@@ -86,13 +86,26 @@ def _maxw(K):
     return float(max(np.abs(np.asarray(w, np.float64)).max() for w in K.weights if len(w)))
 
 
+def _max_degree(K):
+    """Largest number of simplices (dimension >= 1) containing one vertex."""
+    deg = np.zeros(K.coords.shape[0], np.int64)
+    for s in K.simplices[1:]:
+        deg += np.bincount(np.asarray(s).ravel(), minlength=K.coords.shape[0])
+    return int(deg.max()) if deg.size else 0
+
+
 def fwd_tol(K):
-    return 16 * U * oracle.total_abs_weight(K) + 2 * _cells(K) * _maxw(K) * 2.0 ** -30
+    """16 u sum|w| plus the fixed-point grid: 2^-e <= 2 M' 2^-30 per term, with
+    M' = M for the per-cell kernels (C terms) and M (1 + degree) for the
+    vertex-centric ones (V terms per output entry)."""
+    grid = max(_cells(K), K.coords.shape[0] * (1 + _max_degree(K)))
+    return 16 * U * oracle.total_abs_weight(K) + 2 * grid * _maxw(K) * 2.0 ** -30
 
 
-def gpu_smooth(W, Ks, dirs, thr, lam):
+def gpu_smooth(W, Ks, dirs, thr, lam, ls=False):
     cx = W.SimplicialBatch.from_host(Ks)
-    out = W.smooth_forward(cx, W.Grid(dirs, thr), lam)
+    index = W.lower_star_index(cx) if ls else None
+    out = W.smooth_forward(cx, W.Grid(dirs, thr), lam, index=index)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -117,16 +130,17 @@ FWD_CASES = [
 
 @pytest.mark.parametrize("case", FWD_CASES, ids=[c[0] for c in FWD_CASES])
 @pytest.mark.parametrize("decomposition", [0, 1, 2])
-def test_smooth_forward_parity(W, case, decomposition):
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_forward_parity(W, case, decomposition, ls):
     name, make, d, T, R, lam = case
-    _say(f"smooth forward {name} decomposition={decomposition}")
+    _say(f"smooth forward {name} decomposition={decomposition} lower_star={ls}")
     Ks = make()
     n = Ks[0].n
     dirs = dirs_for(n, d)
     thr = synth.uniform_thresholds(T, R)
     W.set_launch(decomposition=decomposition)
     try:
-        got = gpu_smooth(W, Ks, dirs, thr, lam)
+        got = gpu_smooth(W, Ks, dirs, thr, lam, ls)
     finally:
         W.set_launch()
     assert got.shape == (len(Ks), d, T)
@@ -136,19 +150,21 @@ def test_smooth_forward_parity(W, case, decomposition):
         assert err <= fwd_tol(K), f"{name} complex {b}: error {err} > {fwd_tol(K)}"
 
 
-def test_smooth_large_lam_tends_to_the_wect(W):
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_large_lam_tends_to_the_wect(W, ls):
     """At lam = 1e6 with every threshold at least 1e-3 from every height, each
     relaxed term is the step up to exp(-1000): the output equals the WECT."""
     K = tri2d(11, 10, "explicit", 10)
     dirs = synth.s1_directions(6)
     h = oracle.heights(K.coords, dirs).astype(np.float64).ravel()
     thr = np.array([t for t in np.linspace(-1.6, 1.6, 57) if np.min(np.abs(h - t)) >= 1e-3], np.float32)
-    got = gpu_smooth(W, [K], dirs, thr, 1e6)[0]
+    got = gpu_smooth(W, [K], dirs, thr, 1e6, ls)[0]
     ref = oracle.wect(K, dirs, thr).astype(np.float64)
     assert np.abs(got - ref).max() <= fwd_tol(K)
 
 
-def test_smooth_duplicate_thresholds_and_empty_complex(W):
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_duplicate_thresholds_and_empty_complex(W, ls):
     """Non-decreasing thresholds with repeats (binary-search index), and a
     batch with an empty complex (all-zero rows)."""
     K = tri2d(8, 8, "vertex_max", 11)
@@ -156,7 +172,7 @@ def test_smooth_duplicate_thresholds_and_empty_complex(W):
                          "vertex_max", [np.zeros(0, np.float32)])
     dirs = synth.s1_directions(7)
     thr = np.sort(np.concatenate([synth.uniform_thresholds(12, 1.5), synth.uniform_thresholds(6, 1.5)]))
-    got = gpu_smooth(W, [K, E], dirs, thr, 3.0)
+    got = gpu_smooth(W, [K, E], dirs, thr, 3.0, ls)
     ref = osm.smooth_wect(K, dirs, thr, 3.0)
     assert np.abs(got[0] - ref).max() <= fwd_tol(K)
     assert np.all(got[1] == 0.0)
@@ -165,13 +181,6 @@ def test_smooth_duplicate_thresholds_and_empty_complex(W):
 # ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
-
-def _max_degree(K):
-    deg = np.ones(K.coords.shape[0], np.int64)
-    for s in K.simplices[1:]:
-        deg += np.bincount(np.asarray(s).ravel(), minlength=K.coords.shape[0])
-    return int(deg.max())
-
 
 BWD_CASES = [
     ("tri2d explicit d70 T40 lam5", lambda: [tri2d(12, 10, "explicit", 20)], 70, 40, 1.6, 5.0),
@@ -185,9 +194,10 @@ BWD_CASES = [
 
 
 @pytest.mark.parametrize("case", BWD_CASES, ids=[c[0] for c in BWD_CASES])
-def test_smooth_backward_parity(W, case):
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_backward_parity(W, case, ls):
     name, make, d, T, R, lam = case
-    _say(f"smooth backward {name}")
+    _say(f"smooth backward {name} lower_star={ls}")
     Ks = make()
     n = Ks[0].n
     dirs = dirs_for(n, d)
@@ -195,7 +205,8 @@ def test_smooth_backward_parity(W, case):
     B = len(Ks)
     g = synth.rng(52, len(name), 0).normal(size=(B, d, T)).astype(np.float32)
     cx = W.SimplicialBatch.from_host(Ks)
-    res = W.smooth_backward(cx, W.Grid(dirs, thr), lam, torch.from_numpy(g).cuda())
+    index = W.lower_star_index(cx) if ls else None
+    res = W.smooth_backward(cx, W.Grid(dirs, thr), lam, torch.from_numpy(g).cuda(), index=index)
     torch.cuda.synchronize()
     gx = res["coords"].cpu().numpy()
     gd = res["dirs"].cpu().numpy()
@@ -209,7 +220,7 @@ def test_smooth_backward_parity(W, case):
         mag = osm.smooth_wect_vjp(K, dirs, thr, lam, g[b], absolute=True)
         ref_dirs += ref["dirs"]
         abs_dirs += mag["dirs"]
-        chain = T + 48 + _max_degree(K) * ntiles
+        chain = T + 48 + (1 + _max_degree(K)) * ntiles
         e = np.abs(gx[vo[b]:vo[b + 1]] - ref["coords"])
         assert np.all(e <= (chain + 16) * U * mag["coords"] + 1e-30), f"{name} coords, complex {b}: {e.max()}"
         if K.wmode == "vertex_max":
@@ -265,7 +276,7 @@ def test_smooth_autograd_layer(W):
     torch.cuda.synchronize()
     ref = osm.smooth_wect_vjp(K, dirs, thr, 9.0, g)
     mag = osm.smooth_wect_vjp(K, dirs, thr, 9.0, g, absolute=True)
-    chain = 30 + 48 + _max_degree(K)
+    chain = 30 + 48 + 1 + _max_degree(K)
     for got, key, n in ((coords.grad, "coords", chain), (w.grad, "weights", chain),
                         (layer.dirs.grad, "dirs", _cells(K) + 30 + 1024)):
         e = np.abs(got.cpu().numpy() - ref[key])
@@ -279,19 +290,21 @@ def smooth_lam(thr):
     return float(np.float32(2.0 * (thr.size - 1) / (thr[-1] - thr[0])))
 
 
-def test_smooth_differentiation_batch_sampled(W):
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_differentiation_batch_sampled(W, ls):
     """Full size, in the launch configuration the benchmark times (defaults):
     the differentiation batch (64 jittered Freudenthal grids of 10k-200k
     vertices, vertex-max weights, 128 directions, 128 thresholds).  Sampled
     (complex, direction) rows of the forward against the oracle; the adjoint
     with grad_out non-zero on the sampled rows only, against the oracle
     restricted to those directions (the other rows contribute exact zeros)."""
-    _say("smooth differentiation batch, full size")
+    _say(f"smooth differentiation batch, full size, lower_star={ls}")
     w = synth.cfg5()
     lam = smooth_lam(w.thr)
     cx = W.SimplicialBatch.from_host(w.complexes)
     grid = W.Grid(w.dirs, w.thr)
-    out = W.smooth_forward(cx, grid, lam).cpu().numpy()
+    index = W.lower_star_index(cx) if ls else None
+    out = W.smooth_forward(cx, grid, lam, index=index).cpu().numpy()
     Vs = [K.coords.shape[0] for K in w.complexes]
     small, mid = int(np.argmin(Vs)), int(np.argsort(Vs)[len(Vs) // 2])
     samples = [(small, 5), (small, 77), (mid, 40)]
@@ -305,7 +318,7 @@ def test_smooth_differentiation_batch_sampled(W):
     rg = synth.rng(54, 0, 0)
     for b, p in samples:
         g[b, p] = rg.normal(size=T)
-    res = W.smooth_backward(cx, grid, lam, torch.from_numpy(g).cuda())
+    res = W.smooth_backward(cx, grid, lam, torch.from_numpy(g).cuda(), index=index)
     torch.cuda.synchronize()
     gx, gd, gv = res["coords"].cpu().numpy(), res["dirs"].cpu().numpy(), res["weights"].cpu().numpy()
     vo = np.concatenate([[0], np.cumsum(Vs)])
@@ -316,7 +329,7 @@ def test_smooth_differentiation_batch_sampled(W):
         ps = [p for bb, p in samples if bb == b]
         ref = osm.smooth_wect_vjp(K, w.dirs[ps], w.thr, lam, g[b, ps])
         mag = osm.smooth_wect_vjp(K, w.dirs[ps], w.thr, lam, g[b, ps], absolute=True)
-        chain = T + 48 + _max_degree(K) * 2
+        chain = T + 48 + (1 + _max_degree(K)) * 2
         e = np.abs(gx[vo[b]:vo[b + 1]] - ref["coords"])
         assert np.all(e <= (chain + 16) * U * mag["coords"] + 1e-30), f"coords of complex {b}: {e.max()}"
         e = np.abs(gv[vo[b]:vo[b + 1]] - ref["weights"])
