@@ -189,11 +189,26 @@ wect_status wect_batched(const wect_complex* c, const wect_grid* g, void* out,
  * ws:    wect_wecf_workspace_bytes(c, m, T) bytes.  Work is split like
  *        wect_forward with the m columns in place of the d directions, 64 per
  *        wavefront (m below 64 leaves lanes idle).  Errors, asynchrony and
- *        capture safety as for wect_forward; no backward is provided.
+ *        capture safety as for wect_forward; the adjoint is wect_wecf_backward.
  */
 size_t wect_wecf_workspace_bytes(const wect_complex* c, int32_t m, int32_t T);
 wect_status wect_wecf_forward(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T,
                               void* out, void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Adjoint of wect_wecf_forward with respect to the weights (float32 weights,
+ * EXPLICIT or VERTEX_MAX), as wect_backward with the filter values in place of
+ * the heights:
+ *   dL/dw(s) = (-1)^dim(s) sum_p sum_{q : max_{v in s} fvals[v][p] <= thr[q]} grad_out[b][p][q].
+ * Gradients with respect to the filter values are zero almost everywhere and
+ * are not produced.  grad_out [B, m, T] float32; grad_w / grad_vertex as for
+ * wect_backward.  ws: at least wect_wecf_workspace_bytes(c, m, T) bytes (the
+ * threshold index of every filter value is formed there first).  Asynchronous
+ * and capture-safe; outputs overwritten.
+ */
+wect_status wect_wecf_backward(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T,
+                               const float* grad_out, float* const grad_w[4], float* grad_vertex, void* ws,
+                               size_t ws_bytes, void* hip_stream);
 
 /*
  * Weighted Freudenthal complexes of images, built on the device (images become

@@ -420,9 +420,10 @@ def owner_vertex(K) -> List[np.ndarray]:
     return owners
 
 
-def _cell_grads(cells: Cells, dirs, thr, grad_out, absolute=False):
+def _cell_grads(cells: Cells, dirs, thr, grad_out, absolute=False, fvals=None):
     """d L / d w(c) for L = sum_{p,q} g[p][q] out[p][q]:
-    (-1)^dim(c) * sum_p sum_{q : f_p^max(c) <= thr[q]} g[p][q]  (float64)."""
+    (-1)^dim(c) * sum_p sum_{q : f_p^max(c) <= thr[q]} g[p][q]  (float64).
+    The vertex filter f_p is the height along dirs[p], or column p of fvals."""
     g = np.asarray(grad_out, dtype=np.float64)
     if absolute:
         g = np.abs(g)
@@ -433,7 +434,10 @@ def _cell_grads(cells: Cells, dirs, thr, grad_out, absolute=False):
     tail[:, :T] = np.cumsum(g[:, ::-1], axis=1)[:, ::-1]
     grads = [np.zeros(v.shape[0], dtype=np.float64) for v in cells.verts]
     for p in range(d):
-        h = heights(cells.coords, np.asarray(dirs, np.float32)[p:p + 1])[0]
+        if fvals is None:
+            h = heights(cells.coords, np.asarray(dirs, np.float32)[p:p + 1])[0]
+        else:
+            h = np.asarray(fvals, np.float32)[:, p]
         for dim, v in enumerate(cells.verts):
             if v.shape[0] == 0:
                 continue
@@ -445,15 +449,18 @@ def _cell_grads(cells: Cells, dirs, thr, grad_out, absolute=False):
     return grads
 
 
-def wect_backward(K, dirs, thr, grad_out, absolute=False):
+def wect_backward(K, dirs, thr, grad_out, absolute=False, fvals=None):
     """Gradient of L = <grad_out, WECT> with respect to the weights.
 
     explicit weights -> list per dimension of float64 arrays d L / d w(sigma);
     vertex-max weights -> float64 [V], each simplex's gradient routed to its
     owner vertex (lowest id attaining the max).  ``absolute`` replaces every
-    term by its absolute value (used for error bounds)."""
+    term by its absolute value (used for error bounds).  With ``fvals`` [V, m]
+    (dirs unused) it is the gradient of the WECF of those vertex filters
+    (Section "Computation of WECFs"), the output being linear in the weights
+    for any filter."""
     cells = simplicial_cells(K)
-    gc = _cell_grads(cells, dirs, thr, grad_out, absolute)
+    gc = _cell_grads(cells, dirs, thr, grad_out, absolute, fvals)
     if K.wmode == "vertex_max":
         V = K.coords.shape[0]
         gv = np.zeros(V, dtype=np.float64)

@@ -92,6 +92,9 @@ def lib() -> ctypes.CDLL:
     L.wect_wecf_forward.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
                                     c_size_t, c_void_p]
     L.wect_wecf_forward.restype = c_int
+    L.wect_wecf_backward.argtypes = [P(WectComplex), c_void_p, c_int32, c_void_p, c_int32, c_void_p, P(c_void_p),
+                                     c_void_p, c_void_p, c_size_t, c_void_p]
+    L.wect_wecf_backward.restype = c_int
     L.wect_freudenthal_counts.argtypes = [c_int32, c_void_p, P(c_int64)]
     L.wect_freudenthal_counts.restype = c_int
     L.wect_freudenthal_build.argtypes = [P(WectComplex)] + [c_void_p] * 8

@@ -18,7 +18,7 @@ __all__ = [
     "Grid", "SimplicialBatch", "CubicalBatch", "wect_workspace_bytes", "wect_forward", "wect_backward",
     "wect_batched", "wect_validate", "set_launch", "get_launch", "profile_enable", "profile_read",
     "WECTFunction", "wect", "WECT", "smooth_workspace_bytes", "smooth_forward", "smooth_backward",
-    "SmoothWECTFunction", "smooth_wect", "SmoothWECT", "lower_star_index",
+    "SmoothWECTFunction", "smooth_wect", "SmoothWECT", "lower_star_index", "wecf_backward",
 ]
 
 _WMODES = {"ones": L.WECT_W_ONES, "explicit": L.WECT_W_EXPLICIT, "vertex_max": L.WECT_W_VERTEX_MAX}
@@ -355,6 +355,30 @@ def wecf_forward(cx, fvals, thr, out: Optional[torch.Tensor] = None,
                                    _stream(cx.device))
     L.check(st, "wect_wecf_forward")
     return out
+
+
+def wecf_backward(cx, fvals, thr, grad_out: torch.Tensor, ws: Optional[torch.Tensor] = None):
+    """Adjoint of ``wecf_forward`` with respect to the (float32) weights: list per
+    dimension (explicit) or [V] (vertex_max); see wect_wecf_backward."""
+    fvals = torch.as_tensor(fvals, dtype=torch.float32).to(cx.device).contiguous()
+    if fvals.dim() != 2 or fvals.shape[0] != cx.counts[0]:
+        raise ValueError(f"fvals must be [{cx.counts[0]}, m], got {tuple(fvals.shape)}")
+    thr = torch.as_tensor(thr, dtype=torch.float32).to(cx.device).contiguous()
+    m, T = int(fvals.shape[1]), int(thr.numel())
+    grad_out = grad_out.to(dtype=torch.float32).contiguous()
+    _check_tensor(grad_out, "grad_out", cx.device, torch.float32, (cx.B, m, T))
+    gw, gv = _grad_outputs(cx)
+    need = wecf_workspace_bytes(cx, m, T)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=cx.device)
+    else:
+        _check_tensor(ws, "ws", cx.device)
+    c = cx.struct()
+    st = L.lib().wect_wecf_backward(ctypes.byref(c), _ptr(fvals), ctypes.c_int32(m), _ptr(thr), ctypes.c_int32(T),
+                                    _ptr(grad_out), _gw_array(gw), _ptr(gv), _ptr(ws),
+                                    ctypes.c_size_t(int(ws.numel()) * ws.element_size()), _stream(cx.device))
+    L.check(st, "wect_wecf_backward")
+    return gv if gv is not None else gw
 
 
 def freudenthal_counts(shapes) -> Tuple[int, int, int]:

@@ -432,7 +432,8 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
 // WECF of a general vertex filter on a simplicial complex: planned as a
 // forward over m columns whose heights are read from fvals [V, m] (n = 0 in
 // the kernels), so decomposition, staging and reduction are shared.
-wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T, Plan* pl) {
+wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T, Plan* pl,
+                      bool bwd = false) {
   if (!c || c->kind != WECT_SIMPLICIAL || m < 0 || T < 0) return WECT_ERR_ARG;
   if (m > 0 && c->count[0] > 0 && !fvals) return WECT_ERR_ARG;
   if (c->count[0] > 0 && m > 0 && c->count[0] > INT64_MAX / m) return WECT_ERR_ARG;
@@ -440,7 +441,7 @@ wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, cons
   cc.n = 1;                                        // coordinates are not read
   cc.coords = fvals ? fvals : reinterpret_cast<const float*>(c);  // any non-null: not dereferenced
   const wect_grid gg = {fvals ? fvals : cc.coords, m, T, thr};
-  if (wect_status st = make_plan(&cc, &gg, true, false, pl); st != WECT_OK) return st;
+  if (wect_status st = make_plan(&cc, &gg, !bwd, bwd, pl); st != WECT_OK) return st;
   pl->p.n = 0;
   pl->p.coords = nullptr;
   pl->p.dirs = nullptr;
@@ -449,7 +450,7 @@ wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, cons
   pl->p.vb_bytes = T < 255 ? 1 : 2;
   if (pl->ws_fwd > 0 || (m > 0 && T > 0)) {
     pl->vb_bytes = align256((size_t)c->count[0] * (size_t)m * (size_t)pl->p.vb_bytes);
-    pl->ws_fwd += pl->vb_bytes;
+    if (!bwd) pl->ws_fwd += pl->vb_bytes;
   }
   return WECT_OK;
 }
@@ -750,6 +751,26 @@ wect_status wect_wecf_forward(const wect_complex* c, const float* fvals, int32_t
   Plan pl;
   if (wect_status st = wecf_plan(c, fvals, m, thr, T, &pl); st != WECT_OK) return st;
   return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
+}
+
+wect_status wect_wecf_backward(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T,
+                               const float* grad_out, float* const grad_w[4], float* grad_vertex, void* ws,
+                               size_t ws_bytes, void* hip_stream) {
+  Plan pl;
+  if (wect_status st = wecf_plan(c, fvals, m, thr, T, &pl, true); st != WECT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool work = (int64_t)c->B * m * T > 0 && pl.S_bwd > 0;
+  if (work) {
+    if (!ws || ws_bytes < pl.vb_bytes) return WECT_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) & 15) return WECT_ERR_ARG;
+    if (c->wmode == WECT_W_VERTEX_MAX && !grad_vertex && c->count[0] > 0) return WECT_ERR_ARG;
+    if (!grad_out) return WECT_ERR_ARG;
+    pl.p.vbuckets = ws;
+    // threshold index of every filter value first (Algorithm 1's order), then the adjoint
+    if (hipError_t e = wect::launch_vertex_buckets(pl.p, c->count[0] * (int64_t)m, s); e != hipSuccess)
+      return device_error(e, "vertex index kernel");
+  }
+  return run_backward(pl, grad_out, grad_w, grad_vertex, s);
 }
 
 wect_status wect_freudenthal_counts(int32_t B, const int32_t* shape_host, int64_t counts[3]) {

@@ -1360,7 +1360,7 @@ constexpr int kMaxDG = 4;
 
 template <int N, int DIM, int WM, bool FAST>
 __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
-                               const float* sx, const float* sy, const float* sz, int ntl,
+                               const float* sx, const float* sy, const float* sz, int ntl, int tile0,
                                const float* Gt, float* stage, const Thr& th) {
   using L = SimpLayout<N, DIM, uint64_t>;
   const int tid = threadIdx.x, lane = tid & (W - 1);
@@ -1393,13 +1393,25 @@ __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t l
 #pragma unroll
         for (int jj = 0; jj < kMaxDG; ++jj) {
           if (jj < ntl) {
-            const float h = max_height<N, DIM>(E, sx[jj], sy[jj], sz[jj]);
             int bi;
-            if (FAST && th.arith) {
-              // arithmetic index; the one-read fix only where a lane sits on a threshold
-              if (__builtin_amdgcn_ballot_w64(!thr_arith(h, th, bi) ? 1 : 0) != 0) bi = thr_index<FAST>(h, th);
+            if constexpr (N == 0) {
+              // general vertex filter: the largest of the vertices' threshold indices
+              const int col = min((tile0 + jj) * W + lane, p.d - 1);
+              bi = 0;
+#pragma unroll
+              for (int j = 0; j <= DIM; ++j) {
+                const int64_t r = (int64_t)bitcast<int32_t>(E[j]) * p.d + col;
+                bi = max(bi, p.vb_bytes == 1 ? (int)((const uint8_t*)p.vbuckets)[r]
+                                             : (int)((const uint16_t*)p.vbuckets)[r]);
+              }
             } else {
-              bi = thr_index<FAST>(h, th);
+              const float h = max_height<N, DIM>(E, sx[jj], sy[jj], sz[jj]);
+              if (FAST && th.arith) {
+                // arithmetic index; the one-read fix only where a lane sits on a threshold
+                if (__builtin_amdgcn_ballot_w64(!thr_arith(h, th, bi) ? 1 : 0) != 0) bi = thr_index<FAST>(h, th);
+              } else {
+                bi = thr_index<FAST>(h, th);
+              }
             }
             a += Gt[((size_t)jj * T1 + bi) * W + lane];
           }
@@ -1430,12 +1442,12 @@ __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t l
 template <int N, int WM, bool FAST>
 __device__ __forceinline__ void simp_bwd_dim(int dim, const Params& p, int b, int64_t lo, int64_t hi, int64_t voff,
                                              int64_t soff, const float* sx, const float* sy, const float* sz, int ntl,
-                                             const float* Gt, float* stage, const Thr& th) {
+                                             int tile0, const float* Gt, float* stage, const Thr& th) {
   switch (dim) {
-    case 0: simp_bwd_range<N, 0, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
-    case 1: simp_bwd_range<N, 1, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
-    case 2: simp_bwd_range<N, 2, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
-    default: simp_bwd_range<N, 3, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, Gt, stage, th); break;
+    case 0: simp_bwd_range<N, 0, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
+    case 1: simp_bwd_range<N, 1, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
+    case 2: simp_bwd_range<N, 2, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
+    default: simp_bwd_range<N, 3, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
   }
 }
 
@@ -1472,7 +1484,10 @@ __global__ __launch_bounds__(1024) void k_simp_bwd(Params p) {
     const int ntl = min(dg, p.ntiles - tile0);
     float sx[kMaxDG], sy[kMaxDG], sz[kMaxDG];
 #pragma unroll
-    for (int j = 0; j < kMaxDG; ++j) load_dir(p, (tile0 + j) * W + lane, sx[j], sy[j], sz[j]);
+    for (int j = 0; j < kMaxDG; ++j) {
+      sx[j] = sy[j] = sz[j] = 0.0f;
+      if constexpr (N > 0) load_dir(p, (tile0 + j) * W + lane, sx[j], sy[j], sz[j]);
+    }
     // reverse scan of grad_out for the group's tiles: one wavefront per tile
     __syncthreads();
     for (int j = wave; j < dg; j += nw) {
@@ -1500,8 +1515,10 @@ __global__ __launch_bounds__(1024) void k_simp_bwd(Params p) {
       const int64_t lo = mx64(e0, dlo), hi = mn64(e1, dhi);
       if (lo < hi) {
         const int64_t soff = dim == 0 ? voff : off_or(p.simp_off[dim], b, p.count[dim]);
-        if (th.fast) simp_bwd_dim<N, WM, true>(dim, p, b, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, ntl, Gt, stage, th);
-        else simp_bwd_dim<N, WM, false>(dim, p, b, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, ntl, Gt, stage, th);
+        if (th.fast)
+          simp_bwd_dim<N, WM, true>(dim, p, b, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th);
+        else
+          simp_bwd_dim<N, WM, false>(dim, p, b, lo - dlo, hi - dlo, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th);
       }
       dlo = dhi;
     }
@@ -2859,6 +2876,7 @@ static hipError_t launch_bwd_t(const Params& p, int block, size_t lds, hipStream
 hipError_t launch_backward_main(const Params& p, int block, size_t lds, hipStream_t s) {
   const bool vm = p.wmode == WM_VMAX;
   switch (p.n) {
+    case 0: return vm ? launch_bwd_t<0, WM_VMAX>(p, block, lds, s) : launch_bwd_t<0, WM_EXPLICIT>(p, block, lds, s);
     case 1: return vm ? launch_bwd_t<1, WM_VMAX>(p, block, lds, s) : launch_bwd_t<1, WM_EXPLICIT>(p, block, lds, s);
     case 2: return vm ? launch_bwd_t<2, WM_VMAX>(p, block, lds, s) : launch_bwd_t<2, WM_EXPLICIT>(p, block, lds, s);
     default: return vm ? launch_bwd_t<3, WM_VMAX>(p, block, lds, s) : launch_bwd_t<3, WM_EXPLICIT>(p, block, lds, s);

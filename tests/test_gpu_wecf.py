@@ -117,3 +117,35 @@ def test_float_weights_larger_batch(W):
         Ki = synth.Simplicial(K.coords, K.simplices, "ones", [])
         check(gpu_wecf(W, [Ki], F[v0:v0 + nv], thr)[0], oracle.wecf(Ki, F[v0:v0 + nv], thr), Ki, f"ones {b}")
         v0 += nv
+
+
+@pytest.mark.parametrize("wmode,m,T,seed", [("explicit", 70, 33, 0), ("vertex_max", 64, 300, 1),
+                                            ("vertex_max", 5, 20, 2), ("explicit", 130, 16, 3)])
+def test_wecf_backward_parity(W, wmode, m, T, seed):
+    """Adjoint to the weights for general filters (uint8 indices below 255
+    thresholds, uint16 above; one and several column tiles), against the
+    oracle's adjoint within 1e-5 of the adjoint with absolute values."""
+    _say(f"wecf backward {wmode} m={m} T={T}")
+    g0 = np.random.default_rng(100 + seed)
+    coords, edges, tris = synth.freudenthal_grid(17, 13, 0.02, synth.rng(60, seed, 0))
+    counts = [coords.shape[0], edges.shape[0], tris.shape[0]]
+    if wmode == "vertex_max":
+        w = [g0.normal(1.0, 0.3, size=counts[0]).astype(np.float32)]
+    else:
+        w = [g0.normal(0.0, 1.0, size=k).astype(np.float32) for k in counts]
+    K = synth.Simplicial(coords, [None, edges, tris], wmode, w)
+    F = g0.normal(size=(counts[0], m)).astype(np.float32)
+    thr = np.sort(g0.normal(size=T)).astype(np.float32)
+    g = g0.normal(size=(1, m, T)).astype(np.float32)
+    cx = W.SimplicialBatch.from_host([K])
+    got = W.wecf_backward(cx, F, thr, torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.wect_backward(K, None, thr, g[0], fvals=F)
+    mag = oracle.wect_backward(K, None, thr, g[0], absolute=True, fvals=F)
+    if wmode == "vertex_max":
+        e = np.abs(got.cpu().numpy() - ref)
+        assert np.all(e <= 1e-5 * mag + 1e-6), e.max()
+    else:
+        for dim in range(3):
+            e = np.abs(got[dim].cpu().numpy() - ref[dim])
+            assert np.all(e <= 1e-5 * mag[dim] + 1e-6), (dim, e.max())

@@ -451,3 +451,36 @@ def test_wecf_closed_forms():
         F = g.uniform(-1, 1, size=(K.coords.shape[0], 6)).astype(np.float32)
         out = oracle.wecf(K, F, np.array([-1.5, 1.5], dtype=np.float32))
         assert np.all(out[:, 0] == 0) and np.all(out[:, 1] == chi)
+
+
+def test_wecf_backward_of_heights_is_the_wect_backward():
+    """With the heights as filter values the WECF adjoint is the WECT adjoint
+    (pinned by the hand examples and brute force above)."""
+    for wmode in ("explicit", "vertex_max"):
+        K = synth.random_tiny_complex(31, n=2, nv=10, top_dim=2, wmode=wmode, wdtype=np.float32)
+        dirs = synth.s1_directions(5)
+        thr = np.linspace(-1.5, 1.5, 13).astype(np.float32)
+        g = np.random.default_rng(3).normal(size=(5, 13))
+        F = oracle.heights(K.coords, dirs).T.copy()
+        a = oracle.wect_backward(K, None, thr, g, fvals=F)
+        b = oracle.wect_backward(K, dirs, thr, g)
+        if wmode == "vertex_max":
+            np.testing.assert_array_equal(a, b)
+        else:
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
+
+
+def test_wecf_backward_adjoint_identity():
+    """<g, J w> = <J^T g, w> for a general filter: the WECF is linear in the
+    weights, so the forward of the oracle and its adjoint must agree."""
+    K = synth.random_tiny_complex(32, n=2, nv=11, top_dim=2, wmode="explicit", wdtype=np.float32)
+    g0 = np.random.default_rng(5)
+    F = g0.normal(size=(11, 7)).astype(np.float32)
+    thr = np.linspace(-2, 2, 9).astype(np.float32)
+    g = g0.normal(size=(7, 9))
+    out = oracle.wecf(K, F, thr)
+    grads = oracle.wect_backward(K, None, thr, g, fvals=F)
+    lhs = float((g * out).sum())
+    rhs = sum(float(np.dot(gr, np.asarray(w, np.float64))) for gr, w in zip(grads, K.weights))
+    assert abs(lhs - rhs) <= 1e-9 * (1 + abs(lhs))
