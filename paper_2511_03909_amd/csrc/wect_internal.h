@@ -69,6 +69,8 @@ struct Params {
   int64_t* ls_part;              // build: scan partial sums
   int32_t* ls_ent;               // [entries][4]: dim, then the other vertices' global rows (-1 pad)
   int64_t* ls_row;               // [entries]: the coface's row within its dimension
+  uint32_t* ls_mask;             // [entries]: the coface's other vertices as bits over the vertex's edges
+  int32_t* ls_nbc;               // [V]: the vertex's edge count when every coface maps to bits, else -1
 };
 
 // Sigmoid terms with |lam (thr - h)| > kSmoothW are taken as 0 (below) or 1
@@ -99,7 +101,7 @@ hipError_t launch_vertex_buckets(const Params& p, int64_t nvals, hipStream_t s);
 // Lower-star index: layout inside one caller buffer, and its build (count,
 // scan, fill: five kernels, no allocation).
 struct LsLayout {
-  size_t hdr, off, cur, part, ent, row, total;
+  size_t hdr, off, cur, part, ent, row, mask, nbc, total;
   int64_t nent, nparts;
 };
 LsLayout ls_layout(int64_t V, const int64_t count[4], int top_dim);

@@ -1915,33 +1915,72 @@ __global__ __launch_bounds__(256) void k_ls_scan_apply(Params p) {
   if (blockIdx.x == 0 && tid == 0) p.ls_off[0] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_ls_fill(Params p) {
+// One launch per dimension, in increasing order, so that every vertex's
+// entries list its edges first.  Each entry also gets its neighbour bits: an
+// edge is bit k when it is the vertex's k-th edge; after the edges (and
+// k_ls_edge_counts), a higher coface maps each other vertex to the bit of
+// the vertex's edge to it.  Every coface of a face-closed complex maps this
+// way; a vertex with more than 32 edges, or with a coface whose vertex pair
+// has no edge, gets nbc = -1 and is handled by the per-row height test.
+__global__ __launch_bounds__(256) void k_ls_fill(Params p, int dim) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int dim = 1; dim <= p.top_dim; ++dim) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.count[dim]; r += stride) {
-      int32_t g[4];
-      simplex_rows(p, dim, r, g);
+  const int4* ent = (const int4*)p.ls_ent;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.count[dim]; r += stride) {
+    int32_t g[4];
+    simplex_rows(p, dim, r, g);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j <= dim) {
-          const int64_t pos = (int64_t)atomicAdd((unsigned long long*)&p.ls_cur[g[j]], 1ull);
-          // the other vertices in their order within the simplex
-          int32_t o[3];
+    for (int j = 0; j < 4; ++j) {
+      if (j <= dim) {
+        const int32_t v = g[j];
+        const int64_t pos = (int64_t)atomicAdd((unsigned long long*)&p.ls_cur[v], 1ull);
+        // the other vertices in their order within the simplex
+        int32_t o[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int src = k < j ? k : k + 1;  // skip slot j
+          o[k] = src <= dim ? g[src] : -1;
+        }
+        uint32_t m = 0;
+        if (dim == 1) {
+          const int64_t k = pos - p.ls_off[v];
+          m = k < 32 ? 1u << (uint32_t)k : 0u;
+        } else {
+          const int nbc = p.ls_nbc[v];  // may turn -1 concurrently: then the bits are not used
+          const int64_t e0 = p.ls_off[v];
+          bool ok = nbc >= 0;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            const int src = k < j ? k : k + 1;  // skip slot j
-            o[k] = src <= dim ? g[src] : -1;
+            if (k < dim && ok) {
+              int at = -1;
+              for (int q = 0; q < nbc; ++q)
+                if (ent[e0 + q].y == o[k]) at = q;
+              if (at < 0) ok = false;
+              else m |= 1u << (uint32_t)at;
+            }
           }
-          int4 e;
-          e.x = dim;
-          e.y = o[0];
-          e.z = o[1];
-          e.w = o[2];
-          ((int4*)p.ls_ent)[pos] = e;
-          p.ls_row[pos] = r;
+          if (nbc >= 0 && !ok) p.ls_nbc[v] = -1;
         }
+        int4 e;
+        e.x = dim;
+        e.y = o[0];
+        e.z = o[1];
+        e.w = o[2];
+        ((int4*)p.ls_ent)[pos] = e;
+        p.ls_row[pos] = r;
+        p.ls_mask[pos] = m;
       }
     }
+  }
+}
+
+// After the edges are filled: nbc = the vertex's edge count (its first
+// entries), or -1 above 32.
+__global__ __launch_bounds__(256) void k_ls_edge_counts(Params p) {
+  const int64_t V = p.count[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < V; v += stride) {
+    const int64_t ne1 = p.ls_cur[v] - p.ls_off[v];
+    p.ls_nbc[v] = ne1 <= 32 ? (int32_t)ne1 : -1;
   }
 }
 
@@ -1956,9 +1995,16 @@ __global__ __launch_bounds__(256) void k_ls_fill(Params p) {
 //   [3k .. 3k+N-1]  coordinates of the k-th other vertex (k < dim)
 //   [9 + k]         its global row (-1 past dim)
 //   [12] dim, [13] signed weight (-1)^dim w, [14..15] simplex row (int64),
-//   [16] owner: lowest-numbered vertex of largest vertex weight (vertex-max)
+//   [16] owner: lowest-numbered vertex of largest vertex weight (vertex-max),
+//   [17] neighbour bits (k_ls_masks)
 // Vertex rows: [4t .. 4t+N-1] coordinates, [4t+3] own weight.
-constexpr int kLsStride = 17;
+//
+// When every coface of the vertex maps to bits over its edges (nbc >= 0; the
+// edges are its first nbc rows), each lane first sets bit k for every edge
+// neighbour that lies above the vertex (greater height, or equal height and
+// a lower row), and the vertex tops a coface exactly when the coface's bits
+// miss that set: one AND per row instead of the other vertices' heights.
+constexpr int kLsStride = 18;
 constexpr int kLsRows = 64;   // staged coface rows per wavefront
 constexpr int kLsGroup = 8;   // vertices per wavefront group
 
@@ -1991,6 +2037,7 @@ __device__ __forceinline__ void ls_stage(const Params& p, int64_t e, int32_t gv,
   else if constexpr (WM == WM_VMAX) w = wm;
   dst[12] = bitcast<float>(dim);
   dst[13] = (dim & 1) ? -w : w;
+  dst[17] = bitcast<float>(p.ls_mask[e]);
   if constexpr (BWD) {
     dst[14] = bitcast<float>((uint32_t)row);
     dst[15] = bitcast<float>((uint32_t)((uint64_t)row >> 32));
@@ -2033,6 +2080,21 @@ __device__ __forceinline__ bool ls_top(const float* E, int32_t gv, float hv, flo
     }
   }
   return top;
+}
+
+// Bits of the vertex's edge neighbours (rows E0 .. E0 + nbc - 1) that lie
+// above it for the lane's direction.
+template <int N>
+__device__ __forceinline__ uint32_t ls_above(const float* E0, int nbc, int32_t gv, float hv, float sx, float sy,
+                                             float sz) {
+  uint32_t above = 0;
+  for (int k = 0; k < nbc; ++k) {
+    const float* E = E0 + k * kLsStride;
+    const float ho = height<N>(E, sx, sy, sz);
+    const int32_t id = bitcast<int32_t>(E[9]);
+    above |= (ho > hv || (ho == hv && id < gv)) ? (1u << k) : 0u;
+  }
+  return above;
 }
 
 template <int WM>
@@ -2115,17 +2177,33 @@ __device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_
   int32_t gv = 0;
   float hv = 0.0f;
   double Wc = 0.0;
+  int nbc = -1;
+  bool have = false;
+  uint32_t above = 0;
   ls_walk<N, WM, false>(
       p, lo, hi, voff, S, Vr,
       [&](int32_t g, const float* xv, float wself) {
         gv = g;
         hv = height<N>(xv, sx, sy, sz);
         Wc = wself;
+        nbc = uniform(p.ls_nbc[g]);
+        have = false;
       },
       [&](const float* Sr, int r0, int r1) {
-        for (int r = r0; r < r1; ++r) {
-          const float* E = Sr + r * kLsStride;
-          Wc += ls_top<N>(E, gv, hv, sx, sy, sz) ? (double)E[13] : 0.0;
+        if (nbc >= 0) {
+          if (!have) {  // the edges lead the vertex's first rows
+            above = ls_above<N>(Sr + r0 * kLsStride, nbc, gv, hv, sx, sy, sz);
+            have = true;
+          }
+          for (int r = r0; r < r1; ++r) {
+            const float* E = Sr + r * kLsStride;
+            Wc += (bitcast<uint32_t>(E[17]) & above) == 0 ? (double)E[13] : 0.0;
+          }
+        } else {
+          for (int r = r0; r < r1; ++r) {
+            const float* E = Sr + r * kLsStride;
+            Wc += ls_top<N>(E, gv, hv, sx, sy, sz) ? (double)E[13] : 0.0;
+          }
         }
       },
       [&]() {
@@ -2191,10 +2269,15 @@ __device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_
   float* Vr = S + kLsRows * kLsStride;
   int32_t gv = 0;
   float hv = 0.0f, u = 0.0f, vs = 0.0f, Wc = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+  int nbc = -1;
+  bool have = false;
+  uint32_t above = 0;
   ls_walk<N, WM, true>(
       p, lo, hi, voff, S, Vr,
       [&](int32_t gvi, const float* xv, float wself) {
         gv = gvi;
+        nbc = uniform(p.ls_nbc[gvi]);
+        have = false;
         x0 = xv[0];
         if (N >= 2) x1 = xv[1];
         if (N >= 3) x2 = xv[2];
@@ -2220,14 +2303,28 @@ __device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_
         Wc = wself;
       },
       [&](const float* Sr, int r0, int r1) {
+        if (nbc >= 0 && !have) {  // the edges lead the vertex's first rows
+          above = ls_above<N>(Sr + r0 * kLsStride, nbc, gv, hv, sx, sy, sz);
+          have = true;
+        }
         for (int j0 = r0; j0 < r1; j0 += 8) {
           float v8[8];
+          if (nbc >= 0) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const float* E = Sr + min(j0 + k, r1 - 1) * kLsStride;  // past r1: a valid row, weighed 0
-            const bool top = j0 + k < r1 && ls_top<N>(E, gv, hv, sx, sy, sz);
-            Wc += top ? E[13] : 0.0f;
-            v8[k] = top ? u : 0.0f;
+            for (int k = 0; k < 8; ++k) {
+              const float* E = Sr + min(j0 + k, r1 - 1) * kLsStride;  // past r1: a valid row, weighed 0
+              const bool top = j0 + k < r1 && (bitcast<uint32_t>(E[17]) & above) == 0;
+              Wc += top ? E[13] : 0.0f;
+              v8[k] = top ? u : 0.0f;
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const float* E = Sr + min(j0 + k, r1 - 1) * kLsStride;
+              const bool top = j0 + k < r1 && ls_top<N>(E, gv, hv, sx, sy, sz);
+              Wc += top ? E[13] : 0.0f;
+              v8[k] = top ? u : 0.0f;
+            }
           }
           if constexpr (WM != WM_ONES) {
             const float tot = sum_scatter8(v8);
@@ -2917,7 +3014,9 @@ LsLayout ls_layout(int64_t V, const int64_t count[4], int top_dim) {
   L.part = L.cur + al((size_t)V * 8);
   L.ent = L.part + al((size_t)L.nparts * 8);
   L.row = L.ent + al((size_t)L.nent * 16);
-  L.total = L.row + al((size_t)L.nent * 8);
+  L.mask = L.row + al((size_t)L.nent * 8);
+  L.nbc = L.mask + al((size_t)L.nent * 4);
+  L.total = L.nbc + al((size_t)V * 4);
   return L;
 }
 
@@ -2929,6 +3028,8 @@ void ls_bind(Params& p, void* base, const LsLayout& L) {
   p.ls_part = (int64_t*)(b + L.part);
   p.ls_ent = (int32_t*)(b + L.ent);
   p.ls_row = (int64_t*)(b + L.row);
+  p.ls_mask = (uint32_t*)(b + L.mask);
+  p.ls_nbc = (int32_t*)(b + L.nbc);
 }
 
 hipError_t launch_lower_star_build(const Params& p, const LsLayout& L, hipStream_t s) {
@@ -2948,8 +3049,20 @@ hipError_t launch_lower_star_build(const Params& p, const LsLayout& L, hipStream
   if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ls_scan_apply, dim3((unsigned)L.nparts), dim3(256), 0, s, p);
   if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ls_fill, dim3(gb), dim3(256), 0, s, p);
-  return hipGetLastError();
+  const unsigned gv = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (V + 255) / 256));
+  for (int d = 1; d <= p.top_dim; ++d) {
+    hipLaunchKernelGGL(k_ls_fill, dim3(gb), dim3(256), 0, s, p, d);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    if (d == 1) {
+      hipLaunchKernelGGL(k_ls_edge_counts, dim3(gv), dim3(256), 0, s, p);
+      if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    }
+  }
+  if (p.top_dim < 1) {  // no edges: every vertex has nbc = 0
+    hipLaunchKernelGGL(k_ls_edge_counts, dim3(gv), dim3(256), 0, s, p);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 size_t smooth_ls_forward_lds_bytes(int T, int block) {

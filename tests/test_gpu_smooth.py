@@ -344,3 +344,58 @@ def test_smooth_differentiation_batch_sampled(W, ls):
     others[[b for b, _ in samples]] = False
     for b in np.nonzero(others)[0][:8]:
         assert np.all(gx[vo[b]:vo[b + 1]] == 0.0)
+
+
+def _fan(spokes, seed):
+    """A disc fanned around one centre vertex with `spokes` > 32 edges (the
+    centre cannot use neighbour bits)."""
+    g = np.random.default_rng(seed)
+    ang = np.sort(g.uniform(0, 2 * np.pi, size=spokes))
+    ring = np.stack([np.cos(ang), np.sin(ang)], axis=1) * g.uniform(0.8, 1.2, size=(spokes, 1))
+    coords = np.concatenate([g.normal(0, 0.05, size=(1, 2)), ring]).astype(np.float32)
+    k = np.arange(1, spokes + 1)
+    nxt = np.where(k == spokes, 1, k + 1)
+    edges = np.concatenate([np.stack([np.zeros_like(k), k], 1), np.stack([k, nxt], 1)]).astype(np.int32)
+    tris = np.stack([np.zeros_like(k), k, nxt], 1).astype(np.int32)
+    counts = [coords.shape[0], edges.shape[0], tris.shape[0]]
+    return synth.Simplicial(coords, [None, edges, tris], "explicit",
+                            [g.lognormal(0, 0.5, size=c).astype(np.float32) for c in counts])
+
+
+def _not_face_closed(seed):
+    """A triangulated grid with a third of its edges removed: triangles whose
+    vertex pairs have no edge (those vertices cannot use neighbour bits)."""
+    K = tri2d(12, 10, "vertex_max", seed)
+    g = np.random.default_rng(seed)
+    keep = g.random(K.simplices[1].shape[0]) > 0.33
+    return synth.Simplicial(K.coords, [None, K.simplices[1][keep], K.simplices[2]], K.wmode, K.weights)
+
+
+@pytest.mark.parametrize("make", [lambda: _fan(40, 1), lambda: _not_face_closed(2)], ids=["fan40", "not_closed"])
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_general_complexes(W, make, ls):
+    """The per-row height test of the vertex-centric kernels (vertices with more
+    than 32 edges, cofaces without edges), forward and adjoint."""
+    K = make()
+    _say(f"smooth general complex lower_star={ls}")
+    dirs, thr, lam = synth.s1_directions(70), synth.uniform_thresholds(40, 1.6), 6.0
+    got = gpu_smooth(W, [K], dirs, thr, lam, ls)[0]
+    ref = osm.smooth_wect(K, dirs, thr, lam)
+    assert np.abs(got - ref).max() <= fwd_tol(K)
+    g = synth.rng(56, 0, 0).normal(size=(1, 70, 40)).astype(np.float32)
+    cx = W.SimplicialBatch.from_host([K])
+    index = W.lower_star_index(cx) if ls else None
+    res = W.smooth_backward(cx, W.Grid(dirs, thr), lam, torch.from_numpy(g).cuda(), index=index)
+    torch.cuda.synchronize()
+    r = osm.smooth_wect_vjp(K, dirs, thr, lam, g[0])
+    mag = osm.smooth_wect_vjp(K, dirs, thr, lam, g[0], absolute=True)
+    chain = 40 + 48 + (1 + _max_degree(K)) * 2
+    e = np.abs(res["coords"].cpu().numpy() - r["coords"])
+    assert np.all(e <= (chain + 16) * U * mag["coords"] + 1e-30), e.max()
+    if K.wmode == "vertex_max":
+        e = np.abs(res["weights"].cpu().numpy() - r["weights"])
+        assert np.all(e <= (chain + 16) * U * mag["weights"] + 1e-30), e.max()
+    else:
+        for dim in range(3):
+            e = np.abs(res["weights"][dim].cpu().numpy() - r["weights"][dim])
+            assert np.all(e <= (40 + 48 + 64 * 2 + 16) * U * mag["weights"][dim] + 1e-30), (dim, e.max())
