@@ -2113,13 +2113,19 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
   const int wave = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
   for (int64_t vg = lo + (int64_t)wave * kLsGroup; vg < hi; vg += (int64_t)nw * kLsGroup) {
     const int64_t vend = mn64(vg + kLsGroup, hi);
+    // the group's kLsGroup + 1 offsets in one load: lane k holds off[vg + k]
+    const int64_t offl = p.ls_off[voff + mn64(vg + min(lane, kLsGroup), vend)];
+    auto off_at = [&](int64_t v) {  // off[v] for vg <= v <= vend (scalar)
+      return (int64_t)__builtin_amdgcn_readlane((int)(uint32_t)offl, (int)(v - vg)) |
+             ((int64_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)offl >> 32), (int)(v - vg)) << 32);
+    };
     int64_t i = vg;
     while (i < vend) {
-      const int64_t rb = p.ls_off[voff + i];
+      const int64_t rb = off_at(i);
       int64_t j = i + 1;
-      while (j < vend && p.ls_off[voff + j + 1] - rb <= kLsRows) ++j;
+      while (j < vend && off_at(j + 1) - rb <= kLsRows) ++j;
       const int nv = (int)(j - i);
-      const int64_t nrows = p.ls_off[voff + j] - rb;
+      const int64_t nrows = off_at(j) - rb;
       // vertex rows
       if (lane < nv) {
         const int32_t gv = (int32_t)(voff + i + lane);
@@ -2129,19 +2135,23 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
         Vr[4 * lane + 3] = ls_self_weight<WM>(p, gv);
       }
       if (nrows <= kLsRows) {
+        // the vertex each row belongs to: rows of vertex t start at off[i + t] - rb
+        const int64_t rel = offl - rb;  // lane k: start of vertex vg + k
+        const int sh = (int)(i - vg);
         if (lane < nrows) {
-          // the vertex this row belongs to: rows of vertex t start at off[i + t] - rb
           int t = 0;
 #pragma unroll
-          for (int k = 1; k < kLsGroup; ++k)
-            if (k < nv && p.ls_off[voff + i + k] - rb <= lane) t = k;
+          for (int k = 1; k < kLsGroup; ++k) {
+            const int64_t st = __shfl(rel, min(sh + k, kLsGroup));
+            if (k < nv && st <= lane) t = k;
+          }
           ls_stage<N, WM, BWD>(p, rb + lane, (int32_t)(voff + i + t), S + lane * kLsStride);
         }
         wave_lds_sync();
         for (int t = 0; t < nv; ++t) {
           const int32_t gv = (int32_t)(voff + i + t);
           begin(gv, Vr + 4 * t, Vr[4 * t + 3]);
-          rows(S, (int)(p.ls_off[gv] - rb), (int)(p.ls_off[gv + 1] - rb));
+          rows(S, (int)(off_at(i + t) - rb), (int)(off_at(i + t + 1) - rb));
           end();
         }
         wave_lds_sync();
