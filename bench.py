@@ -216,6 +216,8 @@ def main(argv=None):
         "hbm_alg_bytes_per_launch": alg_bytes,
         "hbm_frac": (alg_bytes / (k_ms * 1e-3) / 1e9) / HBM_PEAK_GBPS,
         "hbm_achieved_GBps": alg_bytes / (k_ms * 1e-3) / 1e9,
+        # one LDS atomic add per included vertex and direction (lane-level)
+        "lds_atomics_per_s": nverts * d / (k_ms * 1e-3),
     }
     result = {
         "metric": METRIC,

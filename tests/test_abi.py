@@ -308,3 +308,17 @@ def test_lower_star_metadata(lib):
         L.WECT_ERR_ARG
     assert lib.wect_smooth_ls_backward(ctypes.byref(c), ctypes.byref(g), -1.0, FAKE, nb, FAKE, None, None, None,
                                        None, None) == L.WECT_ERR_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with a message, before touching a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]

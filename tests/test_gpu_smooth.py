@@ -399,3 +399,21 @@ def test_smooth_general_complexes(W, make, ls):
         for dim in range(3):
             e = np.abs(res["weights"][dim].cpu().numpy() - r["weights"][dim])
             assert np.all(e <= (40 + 48 + 64 * 2 + 16) * U * mag["weights"][dim] + 1e-30), (dim, e.max())
+
+
+@pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
+def test_smooth_many_thresholds(W, ls):
+    """T = 256: the 64-bit histogram leaves less LDS for staging (smaller
+    blocks for the vertex-centric kernels); T = 600 does not fit and is
+    refused before any launch."""
+    K = tri2d(16, 14, "explicit", 40)
+    dirs, lam = synth.s1_directions(20), 40.0
+    thr = synth.uniform_thresholds(256, 1.6)
+    got = gpu_smooth(W, [K], dirs, thr, lam, ls)[0]
+    ref = osm.smooth_wect(K, dirs, thr, lam)
+    assert np.abs(got - ref).max() <= fwd_tol(K)
+    cx = W.SimplicialBatch.from_host([K])
+    index = W.lower_star_index(cx) if ls else None
+    with pytest.raises(Exception) as ei:
+        W.smooth_forward(cx, W.Grid(dirs, synth.uniform_thresholds(600, 1.6)), lam, index=index)
+    assert "unsupported" in str(ei.value)
