@@ -364,6 +364,23 @@ def main(argv=None):
                                              f"8 directions, {tc:.1f} s"}
         extras["differentiation_batch64"]["relaxation_lam_spacing2"] = relax
         del cx5, o5, gv5, ws5, gout, os5, index5
+        # the relaxation on the 3D Kuhn mesh (tetrahedra; 74 cofaces per inner vertex), vertex-centric
+        w3r = synth.cfg3()
+        cx3r = W.SimplicialBatch.from_host(w3r.complexes, device=dev)
+        g3r = W.Grid(w3r.dirs, w3r.thr, device=dev)
+        t3r = w3r.thr.astype(np.float64)
+        lam3 = float(np.float32(2.0 * (t3r.size - 1) / (t3r[-1] - t3r[0])))
+        idx3 = W.lower_star_index(cx3r)
+        o3r = torch.empty((1, g3r.d, g3r.T), dtype=torch.float32, device=dev)
+        ws3r = torch.empty(max(1, W.smooth_workspace_bytes(cx3r, g3r, lam3, idx3)), dtype=torch.uint8, device=dev)
+        go3 = torch.randn((1, g3r.d, g3r.T), device=dev)
+        t3f = timed(lambda: W.smooth_forward(cx3r, g3r, lam3, out=o3r, ws=ws3r, index=idx3), 3, 1)
+        t3b = timed(lambda: W.smooth_backward(cx3r, g3r, lam3, go3, index=idx3), 3, 1)
+        it3r = g3r.d * sum(cx3r.counts)
+        extras["relaxation_3d_kuhn64"] = {"workload": w3r.name, "lam": lam3, "fwd_ms": t3f * 1e3,
+                                          "bwd_ms": t3b * 1e3, "items": it3r, "fwd_items_per_s": it3r / t3f,
+                                          "path": "lower_star"}
+        del cx3r, idx3, o3r, ws3r, go3
         # 3D simplicial, float32 weights
         w3 = synth.cfg3()
         cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)

@@ -63,7 +63,7 @@ struct Params {
   float* grad_dirs;              // smooth adjoint: [d, n], accumulated (pre-zeroed); may be null
   // lower-star index (relaxation, vertex-centric kernels): the stream runs over vertices
   int32_t ls;                    // 1: stream elements are vertices, cofaces read from the index
-  int64_t* ls_hdr;               // [4]: [0] entries, [1] largest vertex degree (device-written)
+  int64_t* ls_hdr;               // [4]: [1] largest vertex degree (device-written), others reserved
   int64_t* ls_off;               // [V+1] CSR offsets of each vertex's cofaces
   int64_t* ls_cur;               // [V] build: counts, then fill cursors
   int64_t* ls_part;              // build: scan partial sums
