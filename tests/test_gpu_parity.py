@@ -389,6 +389,46 @@ def test_stream_and_group_decompositions(W, block, mi, dec):
         W.set_launch()
 
 
+@pytest.mark.parametrize("dec", [1, 2])
+def test_cubical_threshold_ranges(W, dec):
+    """The cubical forward drops the clamp of its threshold index when every
+    height of a complex provably maps inside the threshold range, and keeps a
+    per-lane copy of the thresholds when LDS allows: threshold arrays that
+    cover every height, that cut heights off at either end, that lie on the
+    lattice heights of the diagonal directions, and that are too long for the
+    copy, on pixel-lattice and random axes."""
+    # 40 x 40 pixel lattice on [-1, 1]^2 with 40 thresholds on [-sqrt2, sqrt2]: along the diagonals
+    # every other pixel height is a threshold up to rounding
+    ims = [synth.Cubical(synth.random_tiny_cubical(11, (40, 40), include_above=60).intensity,
+                         [synth.cubical_axis(40), synth.cubical_axis(40)], 60, True),
+           synth.random_tiny_cubical(12, (37, 29), include_above=60),
+           synth.Cubical(np.full((6, 9), 200, np.uint8), [synth.cubical_axis(9), synth.cubical_axis(6)], 60, True)]
+    vols = [synth.Cubical(synth.random_tiny_cubical(13, (9, 8, 7), include_above=50).intensity,
+                          [synth.cubical_axis(9), synth.cubical_axis(8), synth.cubical_axis(7)], 50, True),
+            synth.random_tiny_cubical(14, (6, 10, 5), include_above=50)]
+    thresholds = {
+        "covering": synth.uniform_thresholds(128, 3.0),
+        "lattice": synth.uniform_thresholds(40, math.sqrt(2)),
+        "narrow": synth.uniform_thresholds(128, 0.4),
+        "above": np.linspace(0.3, 1.2, 100).astype(np.float32),
+        "below": np.linspace(-1.6, -0.9, 77).astype(np.float32),
+        "long": synth.uniform_thresholds(300, 1.5),
+        "T2": np.array([-0.2, 0.3], np.float32),
+    }
+    d2 = np.concatenate([synth.s1_directions(64), np.eye(2, dtype=np.float32)])
+    d3 = np.concatenate([synth.fibonacci_directions(60), np.eye(3, dtype=np.float32)])
+    try:
+        W.set_launch(1024, 0, 0, dec)
+        for name, thr in thresholds.items():
+            for batch, dirs in ((ims, d2), (vols, d3)):
+                _say(f"cubical thresholds {name} T={thr.shape[0]} n={len(batch[0].axes)} decomposition={dec}")
+                got = gpu_wect(W, batch, dirs, thr)
+                for b, C in enumerate(batch):
+                    assert_match(got[b], oracle.wect(C, dirs, thr), C, f"{name} complex {b}")
+    finally:
+        W.set_launch()
+
+
 def test_float_results_independent_of_launch_shape(W):
     """Float32 weights accumulate as 64-bit fixed point, so the result does not
     depend on the order of the additions: every launch shape gives the same bits."""
