@@ -2104,8 +2104,9 @@ __device__ __forceinline__ float ls_self_weight(const Params& p, int32_t gv) {
 }
 
 // Walks the vertices [lo, hi) (local numbering, global row voff + v) of the
-// wavefront's groups: begin(gv, xv, wself), then rows(S, r0, r1) for the
-// vertex's coface rows (possibly in several chunks), then end().
+// wavefront's groups: begin(gv, xv, wself, nbc), then rows(S, r0, r1) for the
+// vertex's coface rows (possibly in several chunks), then end().  nbc is the
+// vertex's edge count from the index (-1: no neighbour bits).
 template <int N, int WM, bool BWD, typename Begin, typename Rows, typename End>
 __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi, int64_t voff, float* S, float* Vr,
                                         Begin begin, Rows rows, End end) {
@@ -2115,6 +2116,9 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
     const int64_t vend = mn64(vg + kLsGroup, hi);
     // the group's kLsGroup + 1 offsets in one load: lane k holds off[vg + k]
     const int64_t offl = p.ls_off[voff + mn64(vg + min(lane, kLsGroup), vend)];
+    // and their edge counts: lane k holds nbc[vg + k] (k < vend - vg)
+    const int nbcl = p.ls_nbc[voff + mn64(vg + min(lane, kLsGroup - 1), vend - 1)];
+    auto nbc_at = [&](int64_t v) { return __builtin_amdgcn_readlane(nbcl, (int)(v - vg)); };
     auto off_at = [&](int64_t v) {  // off[v] for vg <= v <= vend (scalar)
       return (int64_t)__builtin_amdgcn_readlane((int)(uint32_t)offl, (int)(v - vg)) |
              ((int64_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)offl >> 32), (int)(v - vg)) << 32);
@@ -2150,7 +2154,7 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
         wave_lds_sync();
         for (int t = 0; t < nv; ++t) {
           const int32_t gv = (int32_t)(voff + i + t);
-          begin(gv, Vr + 4 * t, Vr[4 * t + 3]);
+          begin(gv, Vr + 4 * t, Vr[4 * t + 3], nbc_at(i + t));
           rows(S, (int)(off_at(i + t) - rb), (int)(off_at(i + t + 1) - rb));
           end();
         }
@@ -2158,7 +2162,7 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
       } else {  // one vertex with more than kLsRows cofaces, in chunks
         const int32_t gv = (int32_t)(voff + i);
         wave_lds_sync();
-        begin(gv, Vr, Vr[3]);
+        begin(gv, Vr, Vr[3], nbc_at(i));
         for (int64_t c0 = 0; c0 < nrows; c0 += kLsRows) {
           const int m = (int)mn64(kLsRows, nrows - c0);
           if (lane < m) ls_stage<N, WM, BWD>(p, rb + c0 + lane, gv, S + lane * kLsStride);
@@ -2192,11 +2196,11 @@ __device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_
   uint32_t above = 0;
   ls_walk<N, WM, false>(
       p, lo, hi, voff, S, Vr,
-      [&](int32_t g, const float* xv, float wself) {
+      [&](int32_t g, const float* xv, float wself, int nb) {
         gv = g;
         hv = height<N>(xv, sx, sy, sz);
         Wc = wself;
-        nbc = uniform(p.ls_nbc[g]);
+        nbc = nb;
         have = false;
       },
       [&](const float* Sr, int r0, int r1) {
@@ -2284,9 +2288,9 @@ __device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_
   uint32_t above = 0;
   ls_walk<N, WM, true>(
       p, lo, hi, voff, S, Vr,
-      [&](int32_t gvi, const float* xv, float wself) {
+      [&](int32_t gvi, const float* xv, float wself, int nb) {
         gv = gvi;
-        nbc = uniform(p.ls_nbc[gvi]);
+        nbc = nb;
         have = false;
         x0 = xv[0];
         if (N >= 2) x1 = xv[1];
