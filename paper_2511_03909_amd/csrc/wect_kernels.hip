@@ -2006,7 +2006,7 @@ __global__ __launch_bounds__(256) void k_ls_edge_counts(Params p) {
 // miss that set: one AND per row instead of the other vertices' heights.
 constexpr int kLsStride = 18;
 constexpr int kLsRows = 64;   // staged coface rows per wavefront
-constexpr int kLsGroup = 8;   // vertices per wavefront group
+constexpr int kLsGroup = 10;  // vertices per wavefront group
 
 template <int N, int WM, bool BWD>
 __device__ __forceinline__ void ls_stage(const Params& p, int64_t e, int32_t gv, float* dst) {
