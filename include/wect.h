@@ -337,8 +337,9 @@ wect_status wect_smooth_backward(const wect_complex* c, const wect_grid* g, floa
  *   least wect_lower_star_bytes(c) bytes, 16-byte aligned, owned by the
  *   caller).  Reads the simplex lists and offsets only, so one build serves
  *   every call with the same topology (coordinates and weights may change).
- *   Asynchronous and capture-safe: six kernels, no allocation.  Vertex ids must
- *   be valid (wect_validate).
+ *   Asynchronous and capture-safe, no allocation: fill kernels clear the
+ *   counters, then a count, a three-kernel scan, one fill per simplex
+ *   dimension and the edge counts.  Vertex ids must be valid (wect_validate).
  */
 size_t wect_lower_star_bytes(const wect_complex* c);
 wect_status wect_lower_star_build(const wect_complex* c, void* index, size_t index_bytes, void* hip_stream);
