@@ -1996,7 +1996,7 @@ __global__ __launch_bounds__(256) void k_ls_edge_counts(Params p) {
 //   [9 + k]         its global row (-1 past dim)
 //   [12] dim, [13] signed weight (-1)^dim w, [14..15] simplex row (int64),
 //   [16] owner: lowest-numbered vertex of largest vertex weight (vertex-max),
-//   [17] neighbour bits (k_ls_masks)
+//   [17] neighbour bits (written by k_ls_fill)
 // Vertex rows: [4t .. 4t+N-1] coordinates, [4t+3] own weight.
 //
 // When every coface of the vertex maps to bits over its edges (nbc >= 0; the
