@@ -635,3 +635,41 @@ def test_group_decomposition_many_thresholds(W, T):
         W.set_launch()
     for b, C in enumerate(ims):
         assert_match(got[b], oracle.wect(C, dirs, thr), C, f"image {b}")
+
+
+@pytest.mark.parametrize("wdt", [np.int32, np.float32])
+def test_simplex_order_gives_identical_bits(W, wdt):
+    """Permuting the simplex rows of each dimension and the vertices within each
+    row changes the stream order but no cell's index or weight: the forward
+    (integer sums, or 64-bit fixed point for float weights) is bit-identical,
+    and so is the explicit-weight adjoint once its rows are put back (one
+    direction tile: each simplex's gradient is one lane sum, no atomics)."""
+    K = synth.cfg3(n=8).complexes[0]  # 3D Kuhn grid, 9,843 simplices, float32 weights
+    g = np.random.default_rng(21)
+    if wdt == np.int32:
+        K = synth.Simplicial(K.coords, K.simplices, "explicit",
+                             [g.integers(-50, 51, size=c).astype(np.int32) for c in K.counts()])
+    simp, ws, perms = [None], [K.weights[0]], [None]
+    for dim in range(1, 4):
+        perm = g.permutation(K.simplices[dim].shape[0])
+        rows = np.array([g.permutation(r) for r in K.simplices[dim][perm]], np.int32).reshape(-1, dim + 1)
+        simp.append(np.ascontiguousarray(rows))
+        ws.append(K.weights[dim][perm])
+        perms.append(perm)
+    K2 = synth.Simplicial(K.coords, simp, "explicit", ws)
+    dirs, thr = synth.fibonacci_directions(64), synth.uniform_thresholds(40, 1.8)
+    _say(f"simplex order forward wdt={np.dtype(wdt).name}")
+    a = gpu_wect(W, [K], dirs, thr)
+    b = gpu_wect(W, [K2], dirs, thr)
+    assert np.array_equal(a, b)
+    assert_match(a[0], oracle.wect(K, dirs, thr), K, "simplex order")
+    if wdt == np.float32:
+        _say("simplex order adjoint")
+        G = torch.from_numpy(np.random.default_rng(5).normal(size=(1, 64, 40)).astype(np.float32)).cuda()
+        ga = W.wect_backward(W.SimplicialBatch.from_host([K]), W.Grid(dirs, thr), G)
+        gb = W.wect_backward(W.SimplicialBatch.from_host([K2]), W.Grid(dirs, thr), G)
+        torch.cuda.synchronize()
+        assert np.array_equal(ga[0].cpu().numpy(), gb[0].cpu().numpy())
+        for dim in range(1, 4):
+            x, y = ga[dim].cpu().numpy(), gb[dim].cpu().numpy()
+            assert np.array_equal(x[perms[dim]], y), dim
