@@ -25,7 +25,7 @@ namespace {
 using wect::Params;
 
 constexpr int kW = wect::kWave;
-constexpr size_t kLdsLimit = 160 * 1024 - 1024;  // dynamic LDS per workgroup on gfx950 (160 KiB, less static use)
+constexpr size_t kLdsLimit = wect::kLdsBudget;
 
 struct DeviceInfo {
   int cus = 0;

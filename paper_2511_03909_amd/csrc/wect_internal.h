@@ -8,6 +8,7 @@
 namespace wect {
 
 constexpr int kWave = 64;          // lanes per wavefront on gfx950; one lane = one direction
+constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // dynamic LDS per workgroup on gfx950 (160 KiB, less static use)
 constexpr int kMaxStride = 16;     // floats per staged simplicial entry (4 vertices x 3 + weight + owner)
 
 // Everything a kernel needs, passed by value.

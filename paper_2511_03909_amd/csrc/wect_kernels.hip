@@ -1986,11 +1986,12 @@ __global__ __launch_bounds__(256) void k_ls_edge_counts(Params p) {
 
 // Cofaces are staged per wavefront.  A wavefront takes groups of kLsGroup
 // consecutive vertices; their cofaces are consecutive in the index, so as
-// many of the group's vertices as have at most kLsRows cofaces together are
+// many of the group's vertices as have at most R cofaces (R = kLsRows, or half
+// of it when the LDS is short) together are
 // staged at once: lane r loads coface row r (its entry, then the other
 // vertices' coordinates and weights, all rows in flight at once), lane t < nv
 // loads vertex t's coordinates and own weight, and every lane then reads the
-// rows as broadcasts.  A vertex with more than kLsRows cofaces is staged in
+// rows as broadcasts.  A vertex with more than R cofaces is staged in
 // chunks on its own.  Coface row layout (floats):
 //   [3k .. 3k+N-1]  coordinates of the k-th other vertex (k < dim)
 //   [9 + k]         its global row (-1 past dim)
@@ -2005,7 +2006,7 @@ __global__ __launch_bounds__(256) void k_ls_edge_counts(Params p) {
 // a lower row), and the vertex tops a coface exactly when the coface's bits
 // miss that set: one AND per row instead of the other vertices' heights.
 constexpr int kLsStride = 18;
-constexpr int kLsRows = 64;   // staged coface rows per wavefront
+constexpr int kLsRows = 64;   // staged coface rows per wavefront (32 when 64 leave too little LDS)
 constexpr int kLsGroup = 10;  // vertices per wavefront group
 
 template <int N, int WM, bool BWD>
@@ -2108,8 +2109,8 @@ __device__ __forceinline__ float ls_self_weight(const Params& p, int32_t gv) {
 // vertex's coface rows (possibly in several chunks), then end().  nbc is the
 // vertex's edge count from the index (-1: no neighbour bits).
 template <int N, int WM, bool BWD, typename Begin, typename Rows, typename End>
-__device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi, int64_t voff, float* S, float* Vr,
-                                        Begin begin, Rows rows, End end) {
+__device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi, int64_t voff, int R, float* S,
+                                        float* Vr, Begin begin, Rows rows, End end) {
   const int lane = threadIdx.x & (W - 1);
   const int wave = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
   for (int64_t vg = lo + (int64_t)wave * kLsGroup; vg < hi; vg += (int64_t)nw * kLsGroup) {
@@ -2127,7 +2128,7 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
     while (i < vend) {
       const int64_t rb = off_at(i);
       int64_t j = i + 1;
-      while (j < vend && off_at(j + 1) - rb <= kLsRows) ++j;
+      while (j < vend && off_at(j + 1) - rb <= R) ++j;
       const int nv = (int)(j - i);
       const int64_t nrows = off_at(j) - rb;
       // vertex rows
@@ -2138,7 +2139,7 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
         for (int cc = 0; cc < N; ++cc) Vr[4 * lane + cc] = c[cc];
         Vr[4 * lane + 3] = ls_self_weight<WM>(p, gv);
       }
-      if (nrows <= kLsRows) {
+      if (nrows <= R) {
         // the vertex each row belongs to: rows of vertex t start at off[i + t] - rb
         const int64_t rel = offl - rb;  // lane k: start of vertex vg + k
         const int sh = (int)(i - vg);
@@ -2159,12 +2160,12 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
           end();
         }
         wave_lds_sync();
-      } else {  // one vertex with more than kLsRows cofaces, in chunks
+      } else {  // one vertex with more than R cofaces, in chunks
         const int32_t gv = (int32_t)(voff + i);
         wave_lds_sync();
         begin(gv, Vr, Vr[3], nbc_at(i));
-        for (int64_t c0 = 0; c0 < nrows; c0 += kLsRows) {
-          const int m = (int)mn64(kLsRows, nrows - c0);
+        for (int64_t c0 = 0; c0 < nrows; c0 += R) {
+          const int m = (int)mn64(R, nrows - c0);
           if (lane < m) ls_stage<N, WM, BWD>(p, rb + c0 + lane, gv, S + lane * kLsStride);
           wave_lds_sync();
           rows(S, 0, m);
@@ -2181,13 +2182,13 @@ __device__ __forceinline__ void ls_walk(const Params& p, int64_t lo, int64_t hi,
 // vertex's own weight with its cofaces' signed weights where the vertex tops
 // them (float64 sum, then the fixed-point grid), and adds one sigmoid window.
 template <int N, int WM, bool FAST>
-__device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, float sx,
+__device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int R, float sx,
                                              float sy, float sz, uint64_t* hist, float* stage, const Thr& th,
                                              int fexp) {
   const int lane = threadIdx.x & (W - 1);
   const int wave = uniform(threadIdx.x >> 6);
-  float* S = stage + (size_t)wave * (kLsRows * kLsStride + 4 * kLsGroup);
-  float* Vr = S + kLsRows * kLsStride;
+  float* S = stage + (size_t)wave * (R * kLsStride + 4 * kLsGroup);
+  float* Vr = S + R * kLsStride;
   int32_t gv = 0;
   float hv = 0.0f;
   double Wc = 0.0;
@@ -2195,7 +2196,7 @@ __device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_
   bool have = false;
   uint32_t above = 0;
   ls_walk<N, WM, false>(
-      p, lo, hi, voff, S, Vr,
+      p, lo, hi, voff, R, S, Vr,
       [&](int32_t g, const float* xv, float wself, int nb) {
         gv = g;
         hv = height<N>(xv, sx, sy, sz);
@@ -2227,7 +2228,7 @@ __device__ __forceinline__ void ls_fwd_range(const Params& p, int64_t lo, int64_
 }
 
 template <int N, int WM>
-__global__ __launch_bounds__(1024) void k_smooth_ls_fwd(Params p) {
+__global__ __launch_bounds__(1024) void k_smooth_ls_fwd(Params p, int rows) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = p.T;
   uint64_t* hist = (uint64_t*)smem;
@@ -2255,8 +2256,8 @@ __global__ __launch_bounds__(1024) void k_smooth_ls_fwd(Params p) {
     float sx, sy, sz;
     load_dir(p, t * W + lane, sx, sy, sz);
     const int64_t voff = off_or(p.vert_off, b, p.count[0]);
-    if (th.fast) ls_fwd_range<N, WM, true>(p, e0, e1, voff, sx, sy, sz, hist, stage, th, fexp);
-    else ls_fwd_range<N, WM, false>(p, e0, e1, voff, sx, sy, sz, hist, stage, th, fexp);
+    if (th.fast) ls_fwd_range<N, WM, true>(p, e0, e1, voff, rows, sx, sy, sz, hist, stage, th, fexp);
+    else ls_fwd_range<N, WM, false>(p, e0, e1, voff, rows, sx, sy, sz, hist, stage, th, fexp);
     end_group<uint64_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, fexp);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;
@@ -2273,21 +2274,21 @@ __global__ __launch_bounds__(1024) void k_smooth_ls_fwd(Params p) {
 // vertex's own weight gradient, the lane sum of u), and the direction
 // gradient accumulates dh l(v) per lane.
 template <int N, int WM, bool FAST>
-__device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, float sx,
-                                             float sy, float sz, const float* g, const float* Gs, float* stage,
-                                             const Thr& th, float (&gd)[3]) {
+__device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_t hi, int64_t voff, int rows,
+                                             float sx, float sy, float sz, const float* g, const float* Gs,
+                                             float* stage, const Thr& th, float (&gd)[3]) {
   const int lane = threadIdx.x & (W - 1);
   const int wave = uniform(threadIdx.x >> 6);
   const float R = p.sm_r, kap = p.sm_k, lam = p.sm_lam;
-  float* S = stage + (size_t)wave * (kLsRows * kLsStride + 4 * kLsGroup);
-  float* Vr = S + kLsRows * kLsStride;
+  float* S = stage + (size_t)wave * (rows * kLsStride + 4 * kLsGroup);
+  float* Vr = S + rows * kLsStride;
   int32_t gv = 0;
   float hv = 0.0f, u = 0.0f, vs = 0.0f, Wc = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
   int nbc = -1;
   bool have = false;
   uint32_t above = 0;
   ls_walk<N, WM, true>(
-      p, lo, hi, voff, S, Vr,
+      p, lo, hi, voff, rows, S, Vr,
       [&](int32_t gvi, const float* xv, float wself, int nb) {
         gv = gvi;
         nbc = nb;
@@ -2382,7 +2383,7 @@ __device__ __forceinline__ void ls_bwd_range(const Params& p, int64_t lo, int64_
 }
 
 template <int N, int WM>
-__global__ __launch_bounds__(1024) void k_smooth_ls_bwd(Params p) {
+__global__ __launch_bounds__(1024) void k_smooth_ls_bwd(Params p, int rows) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = p.T, T1 = T + 1;
   float* g = (float*)smem;
@@ -2428,8 +2429,8 @@ __global__ __launch_bounds__(1024) void k_smooth_ls_bwd(Params p) {
     __syncthreads();
     float gd[3] = {0.0f, 0.0f, 0.0f};
     const int64_t voff = off_or(p.vert_off, b, p.count[0]);
-    if (th.fast) ls_bwd_range<N, WM, true>(p, e0, e1, voff, sx, sy, sz, g, Gs, stage, th, gd);
-    else ls_bwd_range<N, WM, false>(p, e0, e1, voff, sx, sy, sz, g, Gs, stage, th, gd);
+    if (th.fast) ls_bwd_range<N, WM, true>(p, e0, e1, voff, rows, sx, sy, sz, g, Gs, stage, th, gd);
+    else ls_bwd_range<N, WM, false>(p, e0, e1, voff, rows, sx, sy, sz, g, Gs, stage, th, gd);
     if (p.grad_dirs && gp < p.d) {
 #pragma unroll
       for (int kk = 0; kk < N; ++kk) atomicAdd(p.grad_dirs + (int64_t)gp * N + kk, gd[kk]);
@@ -3079,27 +3080,33 @@ hipError_t launch_lower_star_build(const Params& p, const LsLayout& L, hipStream
   return hipSuccess;
 }
 
-size_t smooth_ls_forward_lds_bytes(int T, int block) {
-  return (size_t)(T + 1) * W * 8 + ((size_t)(T + 1) * 4 + 15) / 16 * 16 +
-         (size_t)(block / W) * (kLsRows * kLsStride + 4 * kLsGroup) * 4;
+// LDS of the vertex-centric kernels: the histogram (forward: uint64 [T+1][W];
+// adjoint: float g and G columns), the thresholds, and per wavefront `rows`
+// coface rows plus the vertex rows.  64 rows per wavefront, or 32 when 64
+// would not fit (long threshold arrays): half the rows, twice the wavefronts.
+static size_t ls_lds(int T, int block, int rows, bool bwd) {
+  const size_t hist = bwd ? (size_t)(2 * T + 1) * W * 4 : (size_t)(T + 1) * W * 8;
+  return hist + ((size_t)(T + 1) * 4 + 15) / 16 * 16 + (size_t)(block / W) * (rows * kLsStride + 4 * kLsGroup) * 4;
+}
+static int ls_rows(int T, int block, bool bwd) {
+  return ls_lds(T, block, kLsRows, bwd) <= kLdsBudget ? kLsRows : kLsRows / 2;
 }
 
-size_t smooth_ls_backward_lds_bytes(int T, int block) {
-  return (size_t)(2 * T + 1) * W * 4 + ((size_t)(T + 1) * 4 + 15) / 16 * 16 +
-         (size_t)(block / W) * (kLsRows * kLsStride + 4 * kLsGroup) * 4;
-}
+size_t smooth_ls_forward_lds_bytes(int T, int block) { return ls_lds(T, block, ls_rows(T, block, false), false); }
+
+size_t smooth_ls_backward_lds_bytes(int T, int block) { return ls_lds(T, block, ls_rows(T, block, true), true); }
 
 template <int N, int WM>
 static hipError_t launch_ls_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
   if (hipError_t e = set_lds_limit(k_smooth_ls_fwd<N, WM>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_smooth_ls_fwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  hipLaunchKernelGGL((k_smooth_ls_fwd<N, WM>), dim3(p.G), dim3(block), lds, s, p, ls_rows(p.T, block, false));
   return hipGetLastError();
 }
 
 template <int N, int WM>
 static hipError_t launch_ls_bwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
   if (hipError_t e = set_lds_limit(k_smooth_ls_bwd<N, WM>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_smooth_ls_bwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  hipLaunchKernelGGL((k_smooth_ls_bwd<N, WM>), dim3(p.G), dim3(block), lds, s, p, ls_rows(p.T, block, true));
   return hipGetLastError();
 }
 
