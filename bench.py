@@ -116,9 +116,11 @@ def timed(fn, steps, warmup):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("wect_kernels.hip", "wect_api.cpp", "wect_internal.h"):
-        with open(os.path.join(ROOT, "paper_2511_03909_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2511_03909_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -8,6 +8,7 @@ there.  Every call recompiles.
 from __future__ import annotations
 
 import argparse
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -20,7 +21,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libwect.so")
 ARCH = "gfx950"
 
-SOURCES = ["wect_kernels.hip", "wect_api.cpp"]
+# kernel translation units are compiled in parallel, then linked with the host runtime
+SOURCES = ["k_simp_fwd.hip", "k_cub_fwd.hip", "k_reduce.hip", "k_simp_bwd.hip", "k_smooth_bwd.hip",
+           "k_lower_star.hip", "k_image.hip", "wect_api.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -42,17 +45,24 @@ def hipcc() -> str:
 
 def build(asm_dir: str | None = None, verbose: bool = False) -> str:
     cc = hipcc()
-    objs = []
     tmp = os.path.join(PKG, "_build")
     os.makedirs(tmp, exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(tmp, src + ".o")
-        cmd = [cc, f"--offload-arch={ARCH}", *COMMON, "-I", INCLUDE, "-I", CSRC, "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmds.append([cc, f"--offload-arch={ARCH}", *COMMON, "-I", INCLUDE, "-I", CSRC, "-c",
+                     os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(run, c) for c in cmds]:
+            f.result()
     out_tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
     if verbose:
@@ -62,9 +72,12 @@ def build(asm_dir: str | None = None, verbose: bool = False) -> str:
     if asm_dir:
         os.makedirs(asm_dir, exist_ok=True)
         # device assembly of the kernels, for inspection
-        cmd = [cc, f"--offload-arch={ARCH}", *COMMON, "-I", INCLUDE, "-I", CSRC, "--cuda-device-only", "-S",
-               os.path.join(CSRC, "wect_kernels.hip"), "-o", os.path.join(asm_dir, "wect_kernels.s")]
-        subprocess.run(cmd, check=True)
+        for src in SOURCES:
+            if not src.endswith(".hip"):
+                continue
+            cmd = [cc, f"--offload-arch={ARCH}", *COMMON, "-I", INCLUDE, "-I", CSRC, "--cuda-device-only", "-S",
+                   os.path.join(CSRC, src), "-o", os.path.join(asm_dir, src[:-4] + ".s")]
+            subprocess.run(cmd, check=True)
     return LIB
 
 

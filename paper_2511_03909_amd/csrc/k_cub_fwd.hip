@@ -1,0 +1,274 @@
+// Cubical forward: implicit cells of images and volumes.
+
+#include "wect_device.h"
+
+namespace wect {
+namespace {
+
+// ---------------------------------------------------------------------------
+// forward, cubical (implicit cells of an image / volume)
+// ---------------------------------------------------------------------------
+//
+// Heights of a grid vertex are ((x_i*sx) + (y_j*sy)) + (z_k*sz).  Rounding is
+// monotone, so for sx >= 0 the height never decreases with i (and never
+// increases for sx < 0), and the same for the other axes: the maximum height
+// of a cell is attained at its "top" corner, the corner furthest along the
+// sign pattern of the direction.  Each vertex therefore adds, per direction,
+// one combined weight: the signed weights of the 2^n cells (itself, its
+// edges, squares, cubes) that it tops for that sign pattern ("orthant").  The
+// 2^n combined weights of a vertex are computed once when it is staged; each
+// lane then reads the one for its direction's orthant.  With a zero component
+// the heights along that axis are equal, so either corner gives the same index.
+
+template <int N>
+struct CubLayout {
+  static constexpr int NO = 1 << N;                 // orthants
+  static constexpr int COFF = N == 2 ? 2 : 4;       // first combined weight
+  static constexpr int STRIDE = N == 2 ? 8 : 12;
+};
+
+// Raw neighbourhood of one voxel, loaded one tile ahead of its use: the
+// intensities of the 3^N voxels around it, its axis coordinates and which of
+// its neighbours lie inside the grid.  Coordinates are clamped into the grid,
+// so every load is unconditional and in bounds; cub_weights masks the
+// neighbours outside (bits of `inside`: i0 > 0, i0 < n0-1, i1 > 0, i1 < n1-1,
+// i2 > 0, i2 < n2-1).
+template <int N>
+struct CubFetch {
+  static constexpr int M = N == 2 ? 9 : 27;
+  int nb[M];
+  float cx, cy, cz;
+  uint32_t inside;
+  bool valid;
+
+  __device__ __forceinline__ void load(const uint8_t* vol, const float* ax0, const float* ax1, const float* ax2,
+                                       int n0, int n1, int n2, int i0, int i1, int i2, bool active) {
+    valid = active;
+    i0 = min(i0, n0 - 1);  // past the end of the range: any in-bounds voxel
+    i1 = min(i1, n1 - 1);
+    i2 = min(i2, n2 - 1);
+    const uint32_t col[3] = {(uint32_t)max(i0 - 1, 0), (uint32_t)i0, (uint32_t)min(i0 + 1, n0 - 1)};
+    const int row[3] = {max(i1 - 1, 0), i1, min(i1 + 1, n1 - 1)};
+    const int lay[3] = {max(i2 - 1, 0), i2, min(i2 + 1, n2 - 1)};
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int d0 = m % 3, d1 = (m / 3) % 3, d2 = N == 3 ? m / 9 : 1;
+      nb[m] = vol[(uint32_t)(lay[d2] * n1 + row[d1]) * (uint32_t)n0 + col[d0]];
+    }
+    inside = (uint32_t)(i0 > 0) | (uint32_t)(i0 < n0 - 1) << 1 | (uint32_t)(i1 > 0) << 2 |
+             (uint32_t)(i1 < n1 - 1) << 3 | (uint32_t)(i2 > 0) << 4 | (uint32_t)(i2 < n2 - 1) << 5;
+    cx = ax0[i0];
+    cy = ax1[i1];
+    cz = N == 3 ? ax2[i2] : 0.0f;
+  }
+};
+
+// Combined weights of a staged vertex for the 2^N orthants, from its raw
+// neighbourhood.  Orthant bit k set means s_k < 0: the cells topped by v then
+// extend towards +k, otherwise towards -k.  Each distinct cell containing v
+// (2N edges, the squares of each axis pair, the 2^N cubes) is evaluated once.
+template <int N, int WM>
+__device__ __forceinline__ void cub_weights(const CubFetch<N>& f, int include_above, int32_t* cw) {
+  constexpr int M = CubFetch<N>::M;
+  auto nbi = [](int d0, int d1, int d2) { return (d0 + 1) + 3 * (d1 + 1) + (N == 3 ? 9 * (d2 + 1) : 0); };
+  // neighbour present: inside the grid and a vertex (lane masks, no arithmetic)
+  bool pr[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int d0 = m % 3 - 1, d1 = (m / 3) % 3 - 1, d2 = N == 3 ? m / 9 - 1 : 0;
+    const bool in = (d0 < 0 ? (f.inside & 1) : d0 > 0 ? (f.inside & 2) : 1) &&
+                    (d1 < 0 ? (f.inside & 4) : d1 > 0 ? (f.inside & 8) : 1) &&
+                    (d2 < 0 ? (f.inside & 16) : d2 > 0 ? (f.inside & 32) : 1);
+    pr[m] = in && f.nb[m] > include_above;
+  }
+  const int x = f.nb[nbi(0, 0, 0)];  // the voxel itself (a vertex: the caller checked)
+  // a cell's weight: 1, or (vertex-max) the largest corner intensity; x is a corner of every cell here
+  auto val = [&](bool present, int mx) { return present ? (WM == WM_ONES ? 1 : mx) : 0; };
+  auto at = [&](int d0, int d1, int d2) { return f.nb[nbi(d0, d1, d2)]; };
+  auto has = [&](int d0, int d1, int d2) { return pr[nbi(d0, d1, d2)]; };
+  // edges E[axis][side] (side 0: towards -axis)
+  int E[N][2], Emx[N][2];
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s = sd ? 1 : -1;
+      const int d0 = a == 0 ? s : 0, d1 = a == 1 ? s : 0, d2 = a == 2 ? s : 0;
+      Emx[a][sd] = max(x, at(d0, d1, d2));
+      E[a][sd] = val(has(d0, d1, d2), Emx[a][sd]);
+    }
+  const int vx = WM == WM_ONES ? 1 : x;
+  if constexpr (N == 2) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const int s0 = o & 1, s1 = (o >> 1) & 1;
+      const int a0 = s0 ? 1 : -1, a1 = s1 ? 1 : -1;
+      const bool sq = has(a0, 0, 0) && has(0, a1, 0) && has(a0, a1, 0);
+      const int sqv = val(sq, max(max(Emx[0][s0], at(0, a1, 0)), at(a0, a1, 0)));
+      cw[o] = vx - E[0][s0] - E[1][s1] + sqv;
+    }
+  } else {
+    // squares F01[s0][s1], F02[s0][s2], F12[s1][s2]: presence and largest corner
+    int F01[2][2], F02[2][2], F12[2][2], M01[2][2], M12[2][2];
+    bool P01[2][2], P12[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int sa = a ? 1 : -1, sb = b ? 1 : -1;
+        P01[a][b] = has(sa, 0, 0) && has(0, sb, 0) && has(sa, sb, 0);
+        M01[a][b] = max(max(Emx[0][a], at(0, sb, 0)), at(sa, sb, 0));
+        F01[a][b] = val(P01[a][b], M01[a][b]);
+        const bool p02 = has(sa, 0, 0) && has(0, 0, sb) && has(sa, 0, sb);
+        F02[a][b] = val(p02, max(max(Emx[0][a], at(0, 0, sb)), at(sa, 0, sb)));
+        P12[a][b] = has(0, sa, 0) && has(0, 0, sb) && has(0, sa, sb);
+        M12[a][b] = max(max(Emx[1][a], at(0, 0, sb)), at(0, sa, sb));
+        F12[a][b] = val(P12[a][b], M12[a][b]);
+      }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int s0 = o & 1, s1 = (o >> 1) & 1, s2 = (o >> 2) & 1;
+      const int a0 = s0 ? 1 : -1, a1 = s1 ? 1 : -1, a2 = s2 ? 1 : -1;
+      // the cube's corners: those of F01 and F12 plus the 0-2 diagonal and the far corner
+      const bool pc = P01[s0][s1] && P12[s1][s2] && has(a0, 0, a2) && has(a0, a1, a2);
+      const int cube = val(pc, max(max(M01[s0][s1], M12[s1][s2]), max(at(a0, 0, a2), at(a0, a1, a2))));
+      cw[o] = vx - E[0][s0] - E[1][s1] - E[2][s2] + F01[s0][s1] + F02[s0][s2] + F12[s1][s2] - cube;
+    }
+  }
+}
+
+// Forward over the voxels [lo, hi) of complex b for one direction tile: the
+// neighbourhoods of tile t+1 are loaded while the histogram of tile t runs.
+template <int N, int WM, bool FAST>
+__device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, float sx, float sy, float sz,
+                              int orth, uint32_t* hist, float* stage, int* counter, const Thr& th) {
+  using L = CubLayout<N>;
+  const int tid = threadIdx.x, lane = tid & (W - 1);
+  const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
+  const int TS = p.stage;
+  const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = N == 3 ? p.shape[3 * b + 2] : 1;
+  const int64_t goff = off_or(p.grid_off, b, p.total_voxels);
+  const int64_t aoff = p.axis_off ? p.axis_off[b] : 0;
+  const uint8_t* vol = p.intensity + goff;
+  const float* ax0 = p.axis + aoff;
+  const float* ax1 = ax0 + n0;
+  const float* ax2 = ax1 + n1;
+  int arith = th.arith;
+  // grid position of the thread's voxel lo + tid, advanced by TS voxels per
+  // tile without division (voxel counts of one complex are below 2^31)
+  const uint32_t ts = (uint32_t)TS;
+  const uint32_t s0 = ts % (uint32_t)n0, s1 = (ts / (uint32_t)n0) % (uint32_t)n1;
+  const uint32_t s2 = ts / ((uint32_t)n0 * (uint32_t)n1);
+  uint32_t v = (uint32_t)(lo + tid);
+  int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
+  int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
+  CubFetch<N> f;
+  f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
+  for (int64_t t0 = lo; t0 < hi; t0 += TS) {
+    if (tid == 0) *counter = 0;
+    __syncthreads();
+    bool keep = false;
+    int32_t cw[L::NO];
+    if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
+      cub_weights<N, WM>(f, p.include_above, cw);
+      bool nz = false;
+#pragma unroll
+      for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
+      keep = nz;
+    }
+    // compact the contributing vertices
+    const uint64_t bal = __ballot(keep);
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(counter, __popcll(bal));
+    base = __shfl(base, 0);
+    if (keep) {
+      const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+      float* E = stage + slot * L::STRIDE;
+      E[0] = f.cx;
+      E[1] = f.cy;
+      if constexpr (N == 3) { E[2] = f.cz; E[3] = 0.0f; }
+#pragma unroll
+      for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
+    }
+    // neighbourhoods of the next tile (in flight during this tile's histogram)
+    i0 += (int)s0;
+    int carry = i0 >= n0;
+    i0 -= carry ? n0 : 0;
+    i1 += (int)s1 + carry;
+    carry = i1 >= n1;
+    i1 -= carry ? n1 : 0;
+    i2 += (int)s2 + carry;
+    v += ts;
+    f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
+    __syncthreads();
+    const int ne = uniform(*counter);
+    const float* Wl = stage + L::COFF + orth;  // the lane's combined weight within an entry
+    hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
+                                 [&](int e, float& h, uint32_t& w) {
+                                   h = height<N>(stage + e * L::STRIDE, sx, sy, sz);
+                                   w = bitcast<uint32_t>(Wl[e * L::STRIDE]);
+                                 });
+    __syncthreads();
+  }
+}
+
+template <int N, int WM>
+__global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = p.T;
+  uint32_t* hist = (uint32_t*)smem;
+  size_t off = (size_t)(T + 1) * W * 4;
+  float* P = (float*)(smem + off);
+  off += align_up((size_t)(T + 1) * 4, 16);
+  int* counter = (int*)(smem + off);
+  off += 16;
+  float* stage = (float*)(smem + off);
+  Thr th;
+  setup_thresholds(p.thr, T, P, th);
+  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = 0u;
+  __syncthreads();
+
+  const int k = blockIdx.x;
+  int64_t pos, end;
+  int b;
+  if (!block_range<uint32_t>(p, hist, k, 0, pos, end, b)) return;
+  const int gpc = p.ntiles;
+  const int lane = threadIdx.x & (W - 1);
+  while (pos < end) {
+    const int64_t cb = cum_elems(p, b);
+    const int64_t nb = cum_elems(p, b + 1) - cb;
+    if (nb == 0) { ++b; continue; }
+    const int64_t base = (int64_t)gpc * cb;
+    const int t = (int)((pos - base) / nb);
+    const int64_t e0 = (pos - base) - (int64_t)t * nb;
+    const int64_t e1 = mn64(nb, e0 + (end - pos));
+    float sx, sy, sz;
+    load_dir(p, t * W + lane, sx, sy, sz);
+    const int orth = (sx < 0.0f ? 1 : 0) | (sy < 0.0f ? 2 : 0) | (sz < 0.0f ? 4 : 0);
+    if (th.fast) cub_fwd_range<N, WM, true>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    else cub_fwd_range<N, WM, false>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    end_group<uint32_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, 0);
+    pos += e1 - e0;
+    if (e1 == nb && t == gpc - 1) ++b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+}  // namespace
+
+template <int N, int WM>
+static hipError_t launch_cub_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cub_fwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_cub(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (p.n == 2) return p.wmode == WM_ONES ? launch_cub_fwd_t<2, WM_ONES>(p, block, lds, s)
+                                          : launch_cub_fwd_t<2, WM_VMAX>(p, block, lds, s);
+  return p.wmode == WM_ONES ? launch_cub_fwd_t<3, WM_ONES>(p, block, lds, s)
+                            : launch_cub_fwd_t<3, WM_VMAX>(p, block, lds, s);
+}
+
+}  // namespace wect

@@ -1,5 +1,5 @@
 // Internal interface between the host runtime (wect_api.cpp) and the HIP
-// kernels (wect_kernels.hip).  Not part of the public ABI.
+// kernels (k_*.hip, with device helpers in wect_device.h).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -80,6 +80,9 @@ constexpr double kSmoothW = 17.0;
 
 // Launchers (enqueue only, return hipError_t of the launch).
 hipError_t launch_forward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+// the two kinds of forward main kernel, which launch_forward_main dispatches to
+hipError_t launch_forward_simp(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+hipError_t launch_forward_cub(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 hipError_t launch_forward_reduce(const Params& p, hipStream_t s);
 hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 // Adjoint of the sigmoid relaxation (p.G blocks over p.S = ntiles * cells).
