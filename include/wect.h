@@ -23,8 +23,14 @@
  *     the first stored threshold at or above that value; a value above
  *     thr[T-1] enters at no threshold;
  *   - integer weights accumulate in int32 with wrap-around (exact whenever
- *     every result fits in int32); float32 weights accumulate in float32
- *     per block and are combined in float64.
+ *     every result fits in int32); float32 weights are rounded once each to a
+ *     64-bit fixed-point grid 2^-e (e chosen from the largest |w| and the
+ *     cell count so that no sum overflows) and summed exactly, so float32
+ *     results do not depend on the launch shape or the order of the work;
+ *   - any number of thresholds: a histogram of all T thresholds is kept in
+ *     LDS when it fits, otherwise the thresholds are processed in tiles of
+ *     consecutive entries, one launch each (out[b][p][q] depends on thr[q]
+ *     alone, so the tiles are exact and independent).
  *
  * Memory: every data pointer is a DEVICE pointer owned by the caller; the
  * library keeps no pointer after a call returns.  Sizes and counts in the
@@ -59,7 +65,8 @@ typedef enum {
   WECT_ERR_THRESHOLDS = 3,   /* wect_validate: thresholds not non-decreasing, or an axis not strictly increasing */
   WECT_ERR_NONFINITE = 4,    /* wect_validate: NaN or Inf in coordinates, directions, thresholds or weights */
   WECT_ERR_WORKSPACE = 5,    /* workspace pointer missing or smaller than wect_workspace_bytes() */
-  WECT_ERR_UNSUPPORTED = 6,  /* valid request outside what the kernels implement (e.g. T too large) */
+  WECT_ERR_UNSUPPORTED = 6,  /* valid request outside what the kernels implement (e.g. explicit
+                                weights on a cubical complex) */
   WECT_ERR_DEVICE = 7        /* a HIP runtime call failed (no device, launch failure, ...) */
 } wect_status;
 
@@ -391,6 +398,11 @@ const char* wect_status_string(wect_status s);
  *   2 = one block per group: every block writes its group's output, with no
  *       partial histograms and no second kernel (balanced when the groups
  *       are of similar size and at least as many as the compute units).
+ * threshold_tile: thresholds per launch (0 = automatic: all T when their
+ *   LDS histogram fits, else the fewest balanced tiles that fit).  A smaller
+ *   tile means a smaller histogram, so more blocks per compute unit or a
+ *   larger staging area, at the price of one pass over the cells per tile.
+ *   Values above what fits are lowered to the largest tile that fits.
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */
@@ -399,6 +411,7 @@ typedef struct {
   int32_t blocks_per_cu;
   int32_t min_items_per_block;
   int32_t decomposition;
+  int32_t threshold_tile;
 } wect_launch;
 
 wect_status wect_set_launch(const wect_launch* l);

@@ -655,7 +655,7 @@ __global__ __launch_bounds__(1024) void k_smooth_ls_bwd(Params p, int rows) {
     for (int i = tid; i < W * T; i += blockDim.x) {
       const int r = i / T, q = i - r * T;
       const int dir = t * W + r;
-      g[(size_t)q * W + r] = dir < p.d ? p.grad_out[((int64_t)b * p.d + dir) * T + q] : 0.0f;
+      g[(size_t)q * W + r] = dir < p.d ? p.grad_out[((int64_t)b * p.d + dir) * p.ldo + q] : 0.0f;
     }
     __syncthreads();
     if (wave == 0) {

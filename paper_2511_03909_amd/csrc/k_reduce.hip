@@ -160,10 +160,10 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
   }
   __syncthreads();
   const int dv = min(W, p.d - t * W);
-  OT* out = (OT*)p.out + ((int64_t)b * p.d + (int64_t)t * W) * T;
+  OT* out = (OT*)p.out + ((int64_t)b * p.d + (int64_t)t * W) * p.ldo;
   for (int i = threadIdx.x; i < dv * T; i += blockDim.x) {
     const int pp = i / T, q = i - pp * T;
-    out[i] = L[pp * LS + q];
+    out[(int64_t)pp * p.ldo + q] = L[pp * LS + q];
   }
 }
 

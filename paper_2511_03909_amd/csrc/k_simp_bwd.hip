@@ -153,7 +153,7 @@ __global__ __launch_bounds__(1024) void k_simp_bwd(Params p) {
       float* G = Gt + (size_t)j * T1 * W;
       G[(size_t)T * W + lane] = 0.0f;
       if (j < ntl && gp < p.d) {
-        const float* g = p.grad_out + ((int64_t)b * p.d + gp) * T;
+        const float* g = p.grad_out + ((int64_t)b * p.d + gp) * p.ldo;
         double acc = 0.0;
         for (int q = T - 1; q >= 0; --q) {
           acc += (double)g[q];

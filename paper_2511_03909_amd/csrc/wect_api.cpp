@@ -56,6 +56,7 @@ std::atomic<int> g_block{0};  // 0: chosen per request by auto_block()
 std::atomic<int> g_bpc{0};  // 0: as many as LDS and wave slots allow
 std::atomic<int> g_min_items{256};
 std::atomic<int> g_decomp{0};  // wect_launch.decomposition
+std::atomic<int> g_ttile{0};   // wect_launch.threshold_tile (0: automatic)
 
 // measurement
 std::atomic<int> g_profile{0};
@@ -71,6 +72,16 @@ bool valid_block(int b) { return b == 256 || b == 512 || b == 1024; }
 // Everything the host derives for one request.
 struct Plan {
   Params p;
+  // Thresholds are processed in tiles of consecutive entries, one launch per
+  // tile: out[b][p][q] depends on thr[q] alone (the cells whose value is at
+  // most thr[q]), so a launch given thr[q0 .. q0+t) computes exactly the
+  // columns q0 .. q0+t of the output; the adjoint is a sum over the
+  // thresholds, so its tiles add up.  One tile whenever the LDS histogram of
+  // all T thresholds fits.
+  int T_full = 0;
+  const float* thr = nullptr;
+  int tt_fwd = 0, tt_bwd = 0;  // threshold tile of the forward / adjoint launches
+  int stage_fwd = 0, stage_bwd = 0;
   int block = 1024;
   size_t lds_fwd = 0, lds_bwd = 0;
   size_t partial_bytes = 0, dsum_bytes = 0, absmax_bytes = 0;
@@ -134,13 +145,54 @@ int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only, bool sm
 }
 
 // Largest block whose vertex-centric relaxation kernel fits in LDS (the
-// coface rows grow with the block).
+// coface rows grow with the block); 0 when none does.
 int ls_block(int T, bool bwd) {
   for (int b : {1024, 512, 256}) {
     const size_t lds = bwd ? wect::smooth_ls_backward_lds_bytes(T, b) : wect::smooth_ls_forward_lds_bytes(T, b);
     if (lds <= kLdsLimit) return b;
   }
-  return 256;
+  return 0;
+}
+
+// Largest t in [1, T] for which fits(t) holds (fits is monotone: true up to
+// some length, false beyond); 0 when not even t = 1 fits.
+template <typename F>
+int largest_fit(int T, F fits) {
+  if (T <= 0) return 0;
+  if (fits(T)) return T;
+  if (!fits(1)) return 0;
+  int lo = 1, hi = T;
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (fits(mid)) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Threshold tile for T thresholds when at most tmax fit in one launch: the
+// fewest tiles, of balanced length (a multiple of 4 when that still fits, so
+// that output rows keep their vector stores).
+int balanced_tile(int T, int tmax) {
+  if (tmax <= 0 || T <= 0) return 0;
+  if (T <= tmax) return T;
+  const int nt = (int)ceil_div(T, tmax);
+  const int t = (int)ceil_div(T, nt);
+  const int t4 = (t + 3) & ~3;
+  return t4 <= tmax ? t4 : t;
+}
+
+// Threshold tile of a launch family: with a user tile, at most that and at
+// most what fits at all (fits_min); automatically, all T thresholds when they
+// fit at all, else the largest tile that fits with a comfortable staging area
+// (fits_good), balanced.
+template <typename FMin, typename FGood>
+int choose_tile(int T, FMin fits_min, FGood fits_good) {
+  const int user = g_ttile.load();
+  int tmax;
+  if (user > 0) tmax = std::min(user, largest_fit(T, fits_min));
+  else tmax = fits_min(T) ? T : largest_fit(T, fits_good);
+  return balanced_tile(T, tmax);
 }
 
 // Check host metadata and build the plan.  need_bwd: backward requested.
@@ -238,6 +290,27 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   DeviceInfo di;
   const bool have_dev = device_info(&di);
   const int cus = have_dev ? di.cus : 256;
+  pl->T_full = g->T;
+  pl->thr = g->thr;
+  p.ldo = g->T;
+  // forward threshold tile: all thresholds whenever their histogram fits LDS
+  // with at least one wavefront's staging, else the fewest tiles that leave a
+  // staging area of 256 entries (relaxation over the lower-star index: the
+  // smallest block's coface rows)
+  int tt_fwd = g->T;
+  if (need_fwd && g->d > 0 && g->T > 0) {
+    const int acc_bytes = acc_bytes_of(c, smooth);
+    const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
+    auto fits_stage = [&](int t, size_t nst) {
+      return ls ? wect::smooth_ls_forward_lds_bytes(t, 256) <= kLdsLimit
+                : wect::forward_lds_fixed(t, c->kind, acc_bytes) + nst * entry <= kLdsLimit;
+    };
+    tt_fwd = choose_tile(g->T, [&](int t) { return fits_stage(t, 64); }, [&](int t) { return fits_stage(t, 256); });
+    if (tt_fwd == 0) return WECT_ERR_UNSUPPORTED;
+  }
+  wect_grid gt = *g;  // the grid of one forward launch: its threshold tile
+  gt.T = tt_fwd;
+  pl->tt_fwd = tt_fwd;
   // Automatic one block per group (complex, direction tile): when there is at
   // least one group per compute unit and every group holds on average 8 tiles
   // of a 1024-thread block.  Measured on MI355X (256 images of 128^2, 64
@@ -249,11 +322,20 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   const bool auto_group = need_fwd && decomp == 0 && g->T > 0 && S_fwd > 0 && groups_fwd >= cus &&
                           S_fwd >= groups_fwd * 8 * 1024;
   int block = g_block.load();
-  if (!block) block = auto_group ? 1024 : ls ? ls_block(g->T, false) : auto_block(c, g, need_bwd && !need_fwd, smooth);
+  if (ls) {
+    // the coface rows of the vertex-centric kernels grow with the block:
+    // at most the largest block that fits, also for a block set by the caller
+    const int fit = ls_block(tt_fwd, false);
+    block = block ? std::min(block, fit) : fit;
+    if (block == 0) block = 256;
+  } else if (!block) {
+    block = auto_group ? 1024 : auto_block(c, &gt, need_bwd && !need_fwd, smooth);
+  }
   pl->block = block;
   pl->elems = elems;
   p.ntiles = ntiles;
   p.stage = block;
+  p.T = tt_fwd;
   const int64_t min_items = std::max(1, g_min_items.load());
   // blocks resident per compute unit: 32 wavefronts and 160 KiB of LDS per CU
   auto blocks_per_cu = [&](size_t lds) -> int64_t {
@@ -271,12 +353,13 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     size_t lds = 0;
     if (ls) {  // per-wavefront coface rows instead of a block staging tile
       stage = block;
-      lds = wect::smooth_ls_forward_lds_bytes(g->T, block);
+      lds = wect::smooth_ls_forward_lds_bytes(tt_fwd, block);
       if (lds > kLdsLimit) stage = 0;
     } else {
-      fwd_stage_lds(c, g, block, &stage, &lds, smooth);
+      fwd_stage_lds(c, &gt, block, &stage, &lds, smooth);
     }
     if (stage == 0) return WECT_ERR_UNSUPPORTED;
+    pl->stage_fwd = stage;
     p.stage = stage;
     pl->lds_fwd = lds;
     const int64_t S = S_fwd;
@@ -291,7 +374,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->S_fwd = S;
     p.group_mode = pl->group_mode ? 1 : 0;
     const int64_t slots = pl->group_mode ? 0 : G + groups;
-    const size_t slot_bytes = (size_t)g->T * kW * acc_bytes;
+    const size_t slot_bytes = (size_t)tt_fwd * kW * acc_bytes;
     // Slots a group may have (blocks meeting its stream range).  A batch's
     // per-complex sizes are on the device: the kernels decide per group, and
     // the separate slot summation is launched when the average group has many
@@ -307,17 +390,25 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     p.cells_total = (double)std::max<int64_t>(cells, 1);
   }
   if (need_bwd && g->d > 0 && g->T > 0) {
+    // adjoint threshold tile: the reverse-scanned grad_out of one direction
+    // tile and a 256-entry staging area must fit
+    const int tt = choose_tile(
+        g->T, [&](int t) { return wect::backward_lds_bytes(t, 256, 1) <= kLdsLimit; },
+        [&](int t) { return wect::backward_lds_bytes(t, 256, 1) <= kLdsLimit; });
+    if (tt == 0) return WECT_ERR_UNSUPPORTED;
+    pl->tt_bwd = tt;
     int dg = std::min(ntiles, 4);
     int stage = block;
-    while (dg > 0 && wect::backward_lds_bytes(g->T, stage, dg) > kLdsLimit) --dg;
+    while (dg > 0 && wect::backward_lds_bytes(tt, stage, dg) > kLdsLimit) --dg;
     if (dg == 0) {
       dg = 1;
-      while (stage > 256 && wect::backward_lds_bytes(g->T, stage, dg) > kLdsLimit) stage /= 2;
-      if (wect::backward_lds_bytes(g->T, stage, dg) > kLdsLimit) return WECT_ERR_UNSUPPORTED;
+      while (stage > 256 && wect::backward_lds_bytes(tt, stage, dg) > kLdsLimit) stage /= 2;
+      if (wect::backward_lds_bytes(tt, stage, dg) > kLdsLimit) return WECT_ERR_UNSUPPORTED;
     }
     pl->dg = dg;
     pl->ngd = (int)ceil_div(ntiles, dg);
-    pl->lds_bwd = wect::backward_lds_bytes(g->T, stage, dg);
+    pl->stage_bwd = stage;
+    pl->lds_bwd = wect::backward_lds_bytes(tt, stage, dg);
     const int64_t S = (int64_t)pl->ngd * elems;
     const int64_t max_blocks = (int64_t)cus * blocks_per_cu(pl->lds_bwd);
     int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
@@ -325,8 +416,8 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->G_bwd = (int)G;
     pl->S_bwd = S;
     pl->ws_bwd = 0;
-    if (stage < p.stage) p.stage = stage;  // only lowered when the backward needs it
   }
+  p.T = g->T;  // the launches set their tile's thresholds
   return WECT_OK;
 }
 
@@ -338,21 +429,30 @@ wect_status device_error(hipError_t e, const char* where) {
   return WECT_ERR_DEVICE;
 }
 
+// Creates and records a timing event; on failure nothing is left allocated.
 hipError_t record(hipEvent_t* e, hipStream_t s) {
   hipError_t r = hipEventCreate(e);
-  if (r != hipSuccess) return r;
-  return hipEventRecord(*e, s);
+  if (r != hipSuccess) {
+    *e = nullptr;
+    return r;
+  }
+  r = hipEventRecord(*e, s);
+  if (r != hipSuccess) {
+    (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
+  return r;
 }
 
 wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, hipStream_t s) {
   Plan pl = pl0;
   Params& p = pl.p;
-  const int64_t nout = (int64_t)p.B * p.d * p.T;
+  const int Tfull = pl.T_full;
+  const int64_t nout = (int64_t)p.B * p.d * Tfull;
   if (nout == 0) return WECT_OK;
   if (!out) return WECT_ERR_ARG;
   if (pl.ws_fwd > 0 && (!ws || ws_bytes < pl.ws_fwd)) return WECT_ERR_WORKSPACE;
   if (ws && (reinterpret_cast<uintptr_t>(ws) & 15)) return WECT_ERR_ARG;
-  p.out = out;
   unsigned char* w8 = static_cast<unsigned char*>(ws);
   p.partial = w8;
   p.dsum = pl.dsum_bytes ? w8 + pl.partial_bytes : nullptr;
@@ -361,27 +461,40 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   p.vbuckets = pl.vb_bytes ? w8 + pl.partial_bytes + pl.dsum_bytes + pl.absmax_bytes : nullptr;
   p.G = pl.G_fwd;
   p.S = pl.S_fwd;
+  p.stage = pl.stage_fwd;
+  p.ldo = Tfull;
   const bool prof = g_profile.load() != 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p.nabsmax > 0) {
     if (hipError_t e = wect::launch_absmax(p, s); e != hipSuccess) return device_error(e, "abs-max kernel");
   }
-  if (p.n == 0 && p.S > 0) {
-    if (hipError_t e = wect::launch_vertex_buckets(p, p.count[0] * (int64_t)p.d, s); e != hipSuccess)
-      return device_error(e, "vertex index kernel");
-  }
-  if (p.S > 0) {
-    if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
-    const hipError_t le = p.ls ? wect::launch_smooth_ls_forward(p, pl.block, pl.lds_fwd, s)
-                               : wect::launch_forward_main(p, pl.block, pl.lds_fwd, s);
-    if (le != hipSuccess) return device_error(le, "forward kernel");
-    if (prof) {
-      if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
-      std::lock_guard<std::mutex> lk(g_prof_mu);
-      g_prof.push_back({e0, e1, 0});
+  for (int q0 = 0; q0 < Tfull; q0 += pl.tt_fwd) {
+    p.T = std::min(pl.tt_fwd, Tfull - q0);
+    p.thr = pl.thr + q0;
+    p.out = static_cast<unsigned char*>(out) + (size_t)q0 * 4;  // int32 or float32 entries
+    if (p.n == 0 && p.S > 0) {
+      if (hipError_t e = wect::launch_vertex_buckets(p, p.count[0] * (int64_t)p.d, s); e != hipSuccess)
+        return device_error(e, "vertex index kernel");
     }
+    if (p.S > 0) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
+      const hipError_t le = p.ls ? wect::launch_smooth_ls_forward(p, pl.block, pl.lds_fwd, s)
+                                 : wect::launch_forward_main(p, pl.block, pl.lds_fwd, s);
+      if (le != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return device_error(le, "forward kernel");
+      }
+      if (prof) {
+        if (record(&e1, s) != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          return WECT_ERR_DEVICE;
+        }
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof.push_back({e0, e1, 0});
+      }
+    }
+    if (hipError_t e = wect::launch_forward_reduce(p, s); e != hipSuccess) return device_error(e, "reduce kernel");
   }
-  if (hipError_t e = wect::launch_forward_reduce(p, s); e != hipSuccess) return device_error(e, "reduce kernel");
   return WECT_OK;
 }
 
@@ -389,8 +502,8 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
                          hipStream_t s) {
   Plan pl = pl0;
   Params& p = pl.p;
-  if (!grad_out && (int64_t)p.B * p.d * p.T > 0) return WECT_ERR_ARG;
-  p.grad_out = grad_out;
+  const int Tfull = pl.T_full;
+  if (!grad_out && (int64_t)p.B * p.d * Tfull > 0) return WECT_ERR_ARG;
   if (p.wmode == WECT_W_VERTEX_MAX) {
     if (!grad_vertex && p.count[0] > 0) return WECT_ERR_ARG;
     p.grad_vertex = grad_vertex;
@@ -401,26 +514,45 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
   p.ngroups_dir = pl.ngd;
   p.G = pl.G_bwd;
   p.S = pl.S_bwd;
+  p.stage = pl.stage_bwd;
+  p.ldo = Tfull;
+  const bool work = p.d > 0 && Tfull > 0 && p.S > 0;
+  const int ntt = work ? (int)ceil_div(Tfull, pl.tt_bwd) : 0;
   // Outputs that are accumulated with atomics start from zero; with a single
-  // direction group every explicit-weight gradient is written exactly once.
-  const bool atomic_explicit = pl.ngd > 1;
+  // direction group and a single threshold tile every explicit-weight
+  // gradient is written exactly once.
+  const bool atomic_explicit = pl.ngd > 1 || ntt > 1;
   p.bwd_atomic = atomic_explicit ? 1 : 0;
   if (p.wmode == WECT_W_VERTEX_MAX) {
     if (wect::launch_fill_zero(grad_vertex, p.count[0], s) != hipSuccess) return WECT_ERR_DEVICE;
-  } else if (atomic_explicit || p.d == 0 || p.T == 0 || p.S == 0) {
+  } else if (atomic_explicit || !work) {
     for (int i = 0; i <= p.top_dim; ++i)
       if (p.grad_w[i] && wect::launch_fill_zero(p.grad_w[i], p.count[i], s) != hipSuccess) return WECT_ERR_DEVICE;
   }
-  if (p.d == 0 || p.T == 0 || p.S == 0) return WECT_OK;
+  if (!work) return WECT_OK;
   const bool prof = g_profile.load() != 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
-  if (hipError_t e = wect::launch_backward_main(p, pl.block, pl.lds_bwd, s); e != hipSuccess)
-    return device_error(e, "adjoint kernel");
-  if (prof) {
-    if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof.push_back({e0, e1, 1});
+  for (int q0 = 0; q0 < Tfull; q0 += pl.tt_bwd) {
+    p.T = std::min(pl.tt_bwd, Tfull - q0);
+    p.thr = pl.thr + q0;
+    p.grad_out = grad_out + q0;
+    if (p.n == 0) {  // general vertex filter: threshold index of every filter value first
+      if (hipError_t e = wect::launch_vertex_buckets(p, p.count[0] * (int64_t)p.d, s); e != hipSuccess)
+        return device_error(e, "vertex index kernel");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
+    if (hipError_t e = wect::launch_backward_main(p, pl.block, pl.lds_bwd, s); e != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return device_error(e, "adjoint kernel");
+    }
+    if (prof) {
+      if (record(&e1, s) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return WECT_ERR_DEVICE;
+      }
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof.push_back({e0, e1, 1});
+    }
   }
   return WECT_OK;
 }
@@ -431,22 +563,30 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
 
 // WECF of a general vertex filter on a simplicial complex: planned as a
 // forward over m columns whose heights are read from fvals [V, m] (n = 0 in
-// the kernels), so decomposition, staging and reduction are shared.
+// the kernels), so decomposition, staging and reduction are shared.  With
+// sizing set, only the sizes are planned and fvals / thr may be null.
 wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, const float* thr, int32_t T, Plan* pl,
-                      bool bwd = false) {
+                      bool bwd = false, bool sizing = false) {
   if (!c || c->kind != WECT_SIMPLICIAL || m < 0 || T < 0) return WECT_ERR_ARG;
-  if (m > 0 && c->count[0] > 0 && !fvals) return WECT_ERR_ARG;
+  if (!sizing && m > 0 && c->count[0] > 0 && !fvals) return WECT_ERR_ARG;
   if (c->count[0] > 0 && m > 0 && c->count[0] > INT64_MAX / m) return WECT_ERR_ARG;
+  // make_plan checks pointers it would read; here the coordinates are not
+  // read and the directions are the filter columns, so stand-ins for the
+  // pointers make_plan requires are passed and then cleared
+  static const float kStandIn = 0.0f;
   wect_complex cc = *c;
-  cc.n = 1;                                        // coordinates are not read
-  cc.coords = fvals ? fvals : reinterpret_cast<const float*>(c);  // any non-null: not dereferenced
-  const wect_grid gg = {fvals ? fvals : cc.coords, m, T, thr};
+  cc.n = 1;
+  cc.coords = &kStandIn;
+  const wect_grid gg = {&kStandIn, m, T, (thr || !sizing) ? thr : &kStandIn};
   if (wect_status st = make_plan(&cc, &gg, !bwd, bwd, pl); st != WECT_OK) return st;
   pl->p.n = 0;
   pl->p.coords = nullptr;
   pl->p.dirs = nullptr;
   pl->p.fvals = fvals;
-  // threshold index of every filter value, one byte while T < 255
+  pl->thr = thr;
+  pl->p.thr = thr;
+  // threshold index of every filter value (within a launch's threshold tile,
+  // at most T), one byte while T < 255
   pl->p.vb_bytes = T < 255 ? 1 : 2;
   if (pl->ws_fwd > 0 || (m > 0 && T > 0)) {
     pl->vb_bytes = align256((size_t)c->count[0] * (size_t)m * (size_t)pl->p.vb_bytes);
@@ -474,15 +614,31 @@ wect_status smooth_plan(const wect_complex* c, const wect_grid* g, float lam, bo
   const double r = lam > 0.0f ? wect::kSmoothW / (double)lam : (double)FLT_MAX;
   p.sm_r = (float)std::min(r, (double)FLT_MAX);
   if (need_bwd && g->d > 0 && g->T > 0) {
+    // threshold tile of the adjoint: all thresholds when they fit (per-cell
+    // kernel: staging down to 64 cells; vertex-centric: 256-thread blocks),
+    // else the fewest tiles that leave 256 staged cells
+    auto fits = [&](int t, int st) {
+      return ls ? wect::smooth_ls_backward_lds_bytes(t, 256) <= kLdsLimit
+                : wect::smooth_backward_lds_bytes(t, st) <= kLdsLimit;
+    };
+    const int tt = choose_tile(g->T, [&](int t) { return fits(t, 64); }, [&](int t) { return fits(t, 256); });
+    if (tt == 0) return WECT_ERR_UNSUPPORTED;
+    pl->tt_bwd = tt;
     int block = g_block.load();
-    if (!block) block = ls ? ls_block(g->T, true) : 1024;
+    if (ls) {  // at most the largest block whose coface rows fit, also for a caller's block
+      const int fit = ls_block(tt, true);
+      block = block ? std::min(block, fit) : fit;
+    } else if (!block) {
+      block = 1024;
+    }
+    if (block == 0) return WECT_ERR_UNSUPPORTED;
     int stage = block;
     size_t lds = 0;
     if (ls) {
-      lds = wect::smooth_ls_backward_lds_bytes(g->T, block);
+      lds = wect::smooth_ls_backward_lds_bytes(tt, block);
     } else {
-      while (stage > 64 && wect::smooth_backward_lds_bytes(g->T, stage) > kLdsLimit) stage /= 2;
-      lds = wect::smooth_backward_lds_bytes(g->T, stage);
+      while (stage > 64 && wect::smooth_backward_lds_bytes(tt, stage) > kLdsLimit) stage /= 2;
+      lds = wect::smooth_backward_lds_bytes(tt, stage);
     }
     if (lds > kLdsLimit) return WECT_ERR_UNSUPPORTED;
     DeviceInfo di;
@@ -507,8 +663,8 @@ wect_status run_smooth_backward(const Plan& pl0, const float* grad_out, float* g
                                 float* const grad_w[4], float* grad_vertex, hipStream_t s) {
   Plan pl = pl0;
   Params& p = pl.p;
-  if (!grad_out && (int64_t)p.B * p.d * p.T > 0) return WECT_ERR_ARG;
-  p.grad_out = grad_out;
+  const int Tfull = pl.T_full;
+  if (!grad_out && (int64_t)p.B * p.d * Tfull > 0) return WECT_ERR_ARG;
   p.grad_coords = grad_coords;
   p.grad_dirs = grad_dirs;
   if (p.wmode == WECT_W_VERTEX_MAX) p.grad_vertex = grad_vertex;
@@ -517,9 +673,12 @@ wect_status run_smooth_backward(const Plan& pl0, const float* grad_out, float* g
   p.G = pl.G_bwd;
   p.S = pl.S_bwd;
   p.stage = pl.sm_stage;
-  const bool work = p.d > 0 && p.T > 0 && p.S > 0;
-  // explicit-weight gradients are written once when there is one direction tile
-  p.bwd_atomic = p.ntiles > 1 ? 1 : 0;
+  p.ldo = Tfull;
+  const bool work = p.d > 0 && Tfull > 0 && p.S > 0;
+  const int ntt = work ? (int)ceil_div(Tfull, pl.tt_bwd) : 0;
+  // explicit-weight gradients are written once when there is one direction
+  // tile and one threshold tile
+  p.bwd_atomic = (p.ntiles > 1 || ntt > 1) ? 1 : 0;
   auto zero = [&](float* x, int64_t n) { return x ? wect::launch_fill_zero(x, n, s) : hipSuccess; };
   if (zero(grad_coords, p.count[0] * (int64_t)p.n) != hipSuccess) return WECT_ERR_DEVICE;
   if (zero(grad_dirs, (int64_t)p.d * p.n) != hipSuccess) return WECT_ERR_DEVICE;
@@ -531,15 +690,26 @@ wect_status run_smooth_backward(const Plan& pl0, const float* grad_out, float* g
   }
   if (!work) return WECT_OK;
   const bool prof = g_profile.load() != 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
-  const hipError_t le = p.ls ? wect::launch_smooth_ls_backward(p, pl.sm_block, pl.lds_bwd, s)
-                            : wect::launch_smooth_backward(p, pl.sm_block, pl.lds_bwd, s);
-  if (le != hipSuccess) return device_error(le, "relaxation adjoint kernel");
-  if (prof) {
-    if (record(&e1, s) != hipSuccess) return WECT_ERR_DEVICE;
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof.push_back({e0, e1, 1});
+  for (int q0 = 0; q0 < Tfull; q0 += pl.tt_bwd) {
+    p.T = std::min(pl.tt_bwd, Tfull - q0);
+    p.thr = pl.thr + q0;
+    p.grad_out = grad_out + q0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
+    const hipError_t le = p.ls ? wect::launch_smooth_ls_backward(p, pl.sm_block, pl.lds_bwd, s)
+                              : wect::launch_smooth_backward(p, pl.sm_block, pl.lds_bwd, s);
+    if (le != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return device_error(le, "relaxation adjoint kernel");
+    }
+    if (prof) {
+      if (record(&e1, s) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return WECT_ERR_DEVICE;
+      }
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof.push_back({e0, e1, 1});
+    }
   }
   return WECT_OK;
 }
@@ -692,7 +862,9 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (l->block != 0 && !valid_block(l->block)) return WECT_ERR_ARG;
   if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64 || l->min_items_per_block < 0) return WECT_ERR_ARG;
   if (l->decomposition < 0 || l->decomposition > 2) return WECT_ERR_ARG;
+  if (l->threshold_tile < 0) return WECT_ERR_ARG;
   g_decomp.store(l->decomposition);
+  g_ttile.store(l->threshold_tile);
   g_block.store(l->block);
   g_bpc.store(l->blocks_per_cu);
   g_min_items.store(l->min_items_per_block ? l->min_items_per_block : 256);
@@ -705,6 +877,7 @@ wect_status wect_get_launch(wect_launch* l) {
   l->blocks_per_cu = g_bpc.load();
   l->min_items_per_block = g_min_items.load();
   l->decomposition = g_decomp.load();
+  l->threshold_tile = g_ttile.load();
   return WECT_OK;
 }
 
@@ -741,8 +914,7 @@ wect_status wect_profile_read(double* fwd_ms, int64_t* fwd_launches, double* bwd
 
 size_t wect_wecf_workspace_bytes(const wect_complex* c, int32_t m, int32_t T) {
   Plan pl;
-  if (wecf_plan(c, reinterpret_cast<const float*>(c), m, reinterpret_cast<const float*>(c), T, &pl) != WECT_OK)
-    return 0;
+  if (wecf_plan(c, nullptr, m, nullptr, T, &pl, false, true) != WECT_OK) return 0;
   return pl.ws_fwd;
 }
 
@@ -765,10 +937,9 @@ wect_status wect_wecf_backward(const wect_complex* c, const float* fvals, int32_
     if (reinterpret_cast<uintptr_t>(ws) & 15) return WECT_ERR_ARG;
     if (c->wmode == WECT_W_VERTEX_MAX && !grad_vertex && c->count[0] > 0) return WECT_ERR_ARG;
     if (!grad_out) return WECT_ERR_ARG;
+    // run_backward forms the threshold index of every filter value for each
+    // threshold tile first (Algorithm 1's order), then runs the adjoint
     pl.p.vbuckets = ws;
-    // threshold index of every filter value first (Algorithm 1's order), then the adjoint
-    if (hipError_t e = wect::launch_vertex_buckets(pl.p, c->count[0] * (int64_t)m, s); e != hipSuccess)
-      return device_error(e, "vertex index kernel");
   }
   return run_backward(pl, grad_out, grad_w, grad_vertex, s);
 }

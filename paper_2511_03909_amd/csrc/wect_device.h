@@ -615,7 +615,9 @@ struct OutOf<uint64_t> {
 };
 
 // A block that covered a whole group (complex b, direction tile t) writes its
-// output itself: out[b][t*64 + lane][q] = sum_{j <= q} hist[j][lane] (the
+// output itself: out[b][t*64 + lane][q] = sum_{j <= q} hist[j][lane] (row
+// stride p.ldo, so that a launch over one tile of the thresholds writes its
+// columns of the full output) (the
 // cumulative sum of Algorithm 1), then clears hist.  The scan runs in place:
 // wavefront r takes rows [r c, (r+1) c) and turns them into a running sum, so
 // the last row of each chunk holds the chunk total that later chunks add.
@@ -641,8 +643,8 @@ __device__ void finish_group(const Params& p, ACC* hist, int b, int t, int fexp)
   }
   const int dir = t * W + lane;
   if (dir < p.d && q0 < q1) {
-    OT* o = (OT*)p.out + ((int64_t)b * p.d + dir) * T;
-    if ((T & 3) == 0 && (reinterpret_cast<uintptr_t>(p.out) & 15) == 0) {
+    OT* o = (OT*)p.out + ((int64_t)b * p.d + dir) * p.ldo;
+    if ((T & 3) == 0 && (p.ldo & 3) == 0 && (reinterpret_cast<uintptr_t>(p.out) & 15) == 0) {
       // rows start 16-byte aligned and q0 is a multiple of 4
       for (int q = q0; q < q1; q += 4) {
         OT v[4];

@@ -33,8 +33,9 @@ struct Params {
   int32_t include_above;
   // sampling grid
   const float* dirs;
-  int32_t d, T;
-  const float* thr;
+  int32_t d, T;          // T: thresholds of this launch (one tile of the request's thresholds)
+  const float* thr;      // the launch's thresholds (first entry of its tile)
+  int32_t ldo;           // row stride of out and grad_out: the request's full threshold count
   // decomposition
   int32_t ntiles;        // direction tiles of 64 (forward) / per group (backward)
   int32_t G;             // blocks of the main kernel

@@ -2,14 +2,17 @@
 
 For one request (a complex batch and a sampling grid) it times the forward for a
 set of launch shapes (threads per block, blocks per compute unit, minimum stream
-items per block, work decomposition) and keeps the fastest.  Results are cached in a JSON file
-keyed by a signature of the request (kind, ambient dimension, batch size,
-total cells rounded to a power of two, directions, thresholds, dtype), so a
-workload of the same shape reuses the choice.
+items per block, work decomposition) and keeps the fastest; then, with that
+shape, it times how the thresholds are split between LDS-resident tiles: all
+thresholds in one pass (when their histogram fits), or tiles of a half or a
+third of them, one pass each (a smaller histogram leaves room for more blocks
+per compute unit and a larger staging area, at the price of re-reading the
+cells).  Results are cached in a JSON file keyed by a signature of the request
+(kind, ambient dimension, batch size, total cells rounded to a power of two,
+directions, thresholds, dtype), so a workload of the same shape reuses the
+choice.
 
-The direction tile is fixed at one wavefront (64 directions, one per lane) and
-the histograms always live in LDS, so the shape knobs (and the choice between
-the stream decomposition and one block per group) are the only ones.
+The direction tile is one wavefront (64 directions, one per lane).
 
     from paper_2511_03909_amd import tune
     shape = tune.tune(cx, grid)        # times, caches, applies
@@ -69,9 +72,17 @@ def _save(path: str, data: Dict[str, dict]) -> None:
 def apply(shape: Optional[dict]) -> None:
     if shape:
         api.set_launch(shape["block"], shape["blocks_per_cu"], shape["min_items_per_block"],
-                       shape.get("decomposition", 0))
+                       shape.get("decomposition", 0), shape.get("threshold_tile", 0))
     else:
         api.set_launch()
+
+
+def tile_candidates(T: int) -> Tuple[int, ...]:
+    """Threshold tiles tried after the shape: automatic (0), and about a half
+    and a third of T for longer threshold arrays."""
+    if T < 96:
+        return (0,)
+    return (0, -(-T // 2), -(-T // 3))
 
 
 def lookup(cx, grid, cache: str = DEFAULT_CACHE) -> Optional[dict]:
@@ -93,22 +104,31 @@ def _time_forward(cx, grid, reps: int) -> float:
 
 def tune(cx, grid, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES, reps: Optional[int] = None,
          cache: Optional[str] = DEFAULT_CACHE, apply_best: bool = True) -> dict:
-    """Time every candidate shape, cache and (by default) apply the fastest."""
+    """Time every candidate shape, then the threshold tiles with the fastest
+    shape; cache and (by default) apply the best."""
     before = api.get_launch()
     results = []
+
+    def run(block, bpc, mi, dec, tt):
+        api.set_launch(block, bpc, mi, dec, tt)
+        t1 = _time_forward(cx, grid, 1)
+        r = reps or max(2, min(50, int(0.05 / max(t1, 1e-6))))
+        results.append((_time_forward(cx, grid, r), block, bpc, mi, dec, tt))
+
     try:
         for block, bpc, mi, dec in candidates:
-            api.set_launch(block, bpc, mi, dec)
-            t1 = _time_forward(cx, grid, 1)
-            r = reps or max(2, min(50, int(0.05 / max(t1, 1e-6))))
-            results.append((_time_forward(cx, grid, r), block, bpc, mi, dec))
+            run(block, bpc, mi, dec, 0)
+        _, block, bpc, mi, dec, _ = min(results)
+        for tt in tile_candidates(grid.T)[1:]:
+            run(block, bpc, mi, dec, tt)
     finally:
         api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"],
-                       before["decomposition"])
-    t, block, bpc, mi, dec = min(results)
-    best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "decomposition": dec, "ms": t * 1e3,
-            "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "decomposition": e, "ms": s * 1e3}
-                      for s, b, c, m, e in results]}
+                       before["decomposition"], before["threshold_tile"])
+    t, block, bpc, mi, dec, tt = min(results)
+    best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "decomposition": dec,
+            "threshold_tile": tt, "ms": t * 1e3,
+            "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "decomposition": e,
+                       "threshold_tile": x, "ms": s * 1e3} for s, b, c, m, e, x in results]}
     if cache:
         data = _load(cache)
         data[signature(cx, grid)] = best

@@ -157,10 +157,12 @@ def test_launch_shape_roundtrip(lib):
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(300, 1, 0, 0))) == L.WECT_ERR_ARG
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 3))) == L.WECT_ERR_ARG
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, -1))) == L.WECT_ERR_ARG
-    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2))) == L.WECT_OK
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, -5))) == L.WECT_ERR_ARG
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77))) == L.WECT_OK
     now = L.WectLaunch()
     lib.wect_get_launch(ctypes.byref(now))
-    assert (now.block, now.blocks_per_cu, now.min_items_per_block, now.decomposition) == (512, 2, 1024, 2)
+    assert (now.block, now.blocks_per_cu, now.min_items_per_block, now.decomposition,
+            now.threshold_tile) == (512, 2, 1024, 2, 77)
     assert lib.wect_set_launch(ctypes.byref(before)) == L.WECT_OK
 
 
@@ -186,7 +188,36 @@ def test_workspace_grows_with_batch(lib):
     c, g = _simplicial(), _grid(d=100, T=64)
     a = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
     assert a % (64 * 64 * 4) == 0  # whole [T][64] slots
-    assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(L.WectGrid(FAKE, 100, 100000, FAKE)), 0) == 0
+    slots = a // (64 * 64 * 4)
+    # 100,000 thresholds do not fit one LDS histogram: they run in tiles of at
+    # most about 600 (int32), and the partial slots are sized for one tile
+    big = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(L.WectGrid(FAKE, 100, 100000, FAKE)), 0)
+    assert 0 < big <= slots * 700 * 64 * 4 + 256
+
+
+def test_threshold_tile_sets_the_slot_size(lib):
+    """A caller's threshold tile of 16 for T = 64 sizes the partial slots for
+    16 thresholds (a quarter); a tile above T is T; float weights (64-bit
+    fixed point) at T = 1000 run in tiles that fit LDS."""
+    before = L.WectLaunch()
+    lib.wect_get_launch(ctypes.byref(before))
+    c, g = _simplicial(), _grid(d=100, T=64)
+    try:
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 0, 1, 0))) == L.WECT_OK
+        full = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 0, 1, 16))) == L.WECT_OK
+        quarter = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
+        assert quarter * 4 == full
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 0, 1, 1000))) == L.WECT_OK
+        assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0) == full
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 0, 1, 0))) == L.WECT_OK
+        f = _simplicial(wmode=L.WECT_W_EXPLICIT, dtype=L.WECT_F32)
+        for i in range(3):
+            f.weights[i] = FAKE
+        ws = lib.wect_workspace_bytes(ctypes.byref(f), ctypes.byref(L.WectGrid(FAKE, 100, 1000, FAKE)), 1)
+        assert ws > 0
+    finally:
+        lib.wect_set_launch(ctypes.byref(before))
 
 
 def test_binding_rejects_mismatched_buffers():

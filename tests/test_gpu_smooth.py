@@ -402,21 +402,39 @@ def test_smooth_general_complexes(W, make, ls):
 
 
 @pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
-def test_smooth_many_thresholds(W, ls):
+@pytest.mark.parametrize("T", [256, 600])
+def test_smooth_many_thresholds(W, ls, T):
     """T = 256: the 64-bit histogram leaves less LDS for staging (smaller
-    blocks for the vertex-centric kernels); T = 600 does not fit and is
-    refused before any launch."""
-    K = tri2d(16, 14, "explicit", 40)
-    dirs, lam = synth.s1_directions(20), 40.0
-    thr = synth.uniform_thresholds(256, 1.6)
-    got = gpu_smooth(W, [K], dirs, thr, lam, ls)[0]
-    ref = osm.smooth_wect(K, dirs, thr, lam)
-    assert np.abs(got - ref).max() <= fwd_tol(K)
-    cx = W.SimplicialBatch.from_host([K])
-    index = W.lower_star_index(cx) if ls else None
-    with pytest.raises(Exception) as ei:
-        W.smooth_forward(cx, W.Grid(dirs, synth.uniform_thresholds(600, 1.6)), lam, index=index)
-    assert "unsupported" in str(ei.value)
+    blocks and 32 staged coface rows per wavefront for the vertex-centric
+    kernels); T = 600 runs in threshold tiles (each output column depends on
+    its own threshold, and each tile's windows are cut at its ends).  Forward
+    and adjoint, on a 2D mesh and a 3D Kuhn mesh whose inner vertices have
+    more than 32 cofaces (staged in chunks)."""
+    for K, dirs in ((tri2d(16, 14, "explicit", 40), synth.s1_directions(20)),
+                    (tet3d(5, "explicit", 42), synth.fibonacci_directions(20))):
+        lam = 40.0
+        thr = synth.uniform_thresholds(T, 1.6 if K.n == 2 else 2.0)
+        _say(f"smooth T={T} n={K.n} lower_star={ls}: forward")
+        got = gpu_smooth(W, [K], dirs, thr, lam, ls)[0]
+        ref = osm.smooth_wect(K, dirs, thr, lam)
+        assert np.abs(got - ref).max() <= fwd_tol(K)
+        _say(f"smooth T={T} n={K.n} lower_star={ls}: adjoint")
+        d = dirs.shape[0]
+        g = synth.rng(54, T, K.n).normal(size=(1, d, T)).astype(np.float32)
+        cx = W.SimplicialBatch.from_host([K])
+        index = W.lower_star_index(cx) if ls else None
+        res = W.smooth_backward(cx, W.Grid(dirs, thr), lam, torch.from_numpy(g).cuda(), index=index)
+        torch.cuda.synchronize()
+        r = osm.smooth_wect_vjp(K, dirs, thr, lam, g[0])
+        mag = osm.smooth_wect_vjp(K, dirs, thr, lam, g[0], absolute=True)
+        chain = T + 48 + (1 + _max_degree(K)) * 4
+        e = np.abs(res["coords"].cpu().numpy() - r["coords"])
+        assert np.all(e <= (chain + 16) * U * mag["coords"] + 1e-30), e.max()
+        for dim in range(K.top_dim + 1):
+            e = np.abs(res["weights"][dim].cpu().numpy() - r["weights"][dim])
+            assert np.all(e <= (T + 48 + 64 * 4 + 16) * U * mag["weights"][dim] + 1e-30), (dim, e.max())
+        e = np.abs(res["dirs"].cpu().numpy() - r["dirs"])
+        assert np.all(e <= (_cells(K) + T + 1024 + 16) * U * mag["dirs"] + 1e-30), e.max()
 
 
 @pytest.mark.parametrize("ls", [False, True], ids=["cells", "lower_star"])
@@ -443,3 +461,34 @@ def test_smooth_forward_invariant_to_simplex_order(W, ls, wmode):
     b = gpu_smooth(W, [K2], dirs, thr, lam, ls)[0]
     assert np.array_equal(a, b)
     assert np.abs(a - osm.smooth_wect(K, dirs, thr, lam)).max() <= fwd_tol(K)
+
+
+def test_smooth_lower_star_large_block_request(W):
+    """A 1024-thread block with one block per group (what the automatic
+    choice takes for many large groups) does not fit the vertex-centric
+    kernels' coface rows at T = 256: the plan lowers the block to one that
+    fits instead of refusing, for the forward and the adjoint."""
+    Ks = [tri2d(12, 10, "vertex_max", 60), tri2d(9, 13, "vertex_max", 61)]
+    dirs, thr, lam = synth.s1_directions(70), synth.uniform_thresholds(256, 1.6), 30.0
+    cx = W.SimplicialBatch.from_host(Ks)
+    index = W.lower_star_index(cx)
+    g = synth.rng(55, 0, 0).normal(size=(2, 70, 256)).astype(np.float32)
+    try:
+        W.set_launch(1024, 0, 0, 2)
+        _say("lower-star relaxation, requested block 1024, group decomposition, T=256")
+        out = W.smooth_forward(cx, W.Grid(dirs, thr), lam, index=index)
+        res = W.smooth_backward(cx, W.Grid(dirs, thr), lam, torch.from_numpy(g).cuda(), index=index)
+        torch.cuda.synchronize()
+    finally:
+        W.set_launch()
+    out = out.cpu().numpy()
+    vo = np.concatenate([[0], np.cumsum([K.coords.shape[0] for K in Ks])])
+    for b, K in enumerate(Ks):
+        assert np.abs(out[b] - osm.smooth_wect(K, dirs, thr, lam)).max() <= fwd_tol(K)
+        r = osm.smooth_wect_vjp(K, dirs, thr, lam, g[b])
+        mag = osm.smooth_wect_vjp(K, dirs, thr, lam, g[b], absolute=True)
+        chain = 256 + 48 + (1 + _max_degree(K)) * 2
+        e = np.abs(res["weights"].cpu().numpy()[vo[b]:vo[b + 1]] - r["weights"])
+        assert np.all(e <= (chain + 16) * U * mag["weights"] + 1e-30), e.max()
+        e = np.abs(res["coords"].cpu().numpy()[vo[b]:vo[b + 1]] - r["coords"])
+        assert np.all(e <= (chain + 16) * U * mag["coords"] + 1e-30), e.max()

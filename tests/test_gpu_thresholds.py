@@ -1,0 +1,198 @@
+"""Long threshold arrays: tiles of thresholds, one launch each.
+
+out[b][p][q] is the signed weight of the cells whose value is at most thr[q],
+so it depends on thr[q] alone (Definition "Weighted Euler Characteristic
+Function" sampled at each threshold); Algorithm 1 takes any number of
+thresholds.  When the LDS histogram of all T thresholds does not fit, the
+library runs tiles of consecutive thresholds, each a complete forward over the
+cells that writes its own columns; the adjoint sums over the thresholds, so
+its tiles add up.  Integer results must be bit-exact, float32 ones within
+1e-5 sum|w| of the oracle, and a caller's tile size must not change any
+integer or fixed-point result."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def W():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_03909_amd import api
+    api.set_launch()
+    return api
+
+
+def gpu_wect(W, complexes, dirs, thr):
+    complexes = list(complexes)
+    if hasattr(complexes[0], "intensity"):
+        cx = W.CubicalBatch.from_host(complexes)
+    else:
+        cx = W.SimplicialBatch.from_host(complexes)
+    out = W.wect_forward(cx, W.Grid(dirs, thr))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def assert_match(got, ref, X, what):
+    if np.issubdtype(ref.dtype, np.integer):
+        assert np.all(np.abs(ref) < 2 ** 31)
+        bad = np.argwhere(got.astype(np.int64) != ref)
+        assert bad.size == 0, f"{what}: {len(bad)} mismatches, first {bad[:5].tolist()}"
+    else:
+        tol = 1e-5 * max(oracle.total_abs_weight(X), 1e-30)
+        err = np.abs(got.astype(np.float64) - ref).max()
+        assert err <= tol, f"{what}: max error {err} > {tol}"
+
+
+def _simplicial_cases():
+    coords, edges, tris = synth.freudenthal_grid(17, 13, 0.02, synth.rng(70, 0, 0))
+    return [
+        ("3d explicit int32", synth.random_tiny_complex(11, n=3, nv=12, top_dim=3, wmode="explicit",
+                                                        wdtype=np.int32), synth.fibonacci_directions(70)),
+        ("3d explicit float32", synth.random_tiny_complex(12, n=3, nv=12, top_dim=3, wmode="explicit",
+                                                          wdtype=np.float32), synth.fibonacci_directions(70)),
+        ("2d vertex-max", synth.random_tiny_complex(13, n=2, nv=12, top_dim=2, wmode="vertex_max"),
+         synth.s1_directions(66)),
+        ("2d unweighted grid", synth.Simplicial(coords, [None, edges, tris], "ones", []), synth.s1_directions(64)),
+    ]
+
+
+@pytest.mark.parametrize("T", [1000, 4096])
+def test_forward_many_thresholds(W, T):
+    thr = synth.uniform_thresholds(T, 2.0)
+    for name, K, dirs in _simplicial_cases():
+        _say(f"forward T={T} {name}")
+        assert_match(gpu_wect(W, [K], dirs, thr)[0], oracle.wect(K, dirs, thr), K, f"T={T} {name}")
+    ims = [synth.random_tiny_cubical(3, (33, 40), include_above=40),
+           synth.random_tiny_cubical(4, (9, 7, 5), include_above=40)]
+    for C, dirs in ((ims[0], synth.s1_directions(70)), (ims[1], synth.fibonacci_directions(70))):
+        _say(f"forward T={T} cubical {C.intensity.shape}")
+        assert_match(gpu_wect(W, [C], dirs, thr)[0], oracle.wect(C, dirs, thr), C, f"T={T} cubical")
+
+
+def test_forward_many_thresholds_batched_and_uneven(W):
+    """A batch of uneven complexes with one empty member, d = 130 (ragged
+    direction tile), 1500 random sorted thresholds with repeats (binary-search
+    index inside each tile), in both work decompositions."""
+    g = np.random.default_rng(71)
+    thr = np.sort(np.concatenate([g.uniform(-1.7, 1.7, 1400), np.repeat(np.float32(0.25), 100)])).astype(np.float32)
+    Ks = [synth.random_tiny_complex(s, n=2, nv=7 + s, top_dim=2, wmode="explicit", wdtype=np.int32) for s in range(4)]
+    Ks.insert(1, synth.Simplicial(np.zeros((0, 2), np.float32), [None, np.zeros((0, 2), np.int32),
+                                                                 np.zeros((0, 3), np.int32)],
+                                  "explicit", [np.zeros(0, np.int32)] * 3))
+    dirs = synth.s1_directions(130)
+    try:
+        for dec in (1, 2):
+            W.set_launch(decomposition=dec)
+            _say(f"batched T=1500 decomposition={dec}")
+            got = gpu_wect(W, Ks, dirs, thr)
+            assert np.all(got[1] == 0)
+            for b, K in enumerate(Ks):
+                if b != 1:
+                    assert_match(got[b], oracle.wect(K, dirs, thr), K, f"complex {b}")
+    finally:
+        W.set_launch()
+
+
+def test_threshold_tile_does_not_change_results(W):
+    """Integer sums and 64-bit fixed-point sums are exact, so every threshold
+    tile gives the same bits, down to one threshold per launch."""
+    Ki = synth.random_tiny_complex(21, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.int32)
+    Kf = synth.random_tiny_complex(22, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.float32)
+    C = synth.random_tiny_cubical(5, (13, 11), include_above=50)
+    dirs3, dirs2 = synth.fibonacci_directions(70), synth.s1_directions(70)
+    thr = synth.uniform_thresholds(97, 1.9)
+    refs = [gpu_wect(W, [Ki], dirs3, thr), gpu_wect(W, [Kf], dirs3, thr), gpu_wect(W, [C], dirs2, thr)]
+    assert_match(refs[0][0], oracle.wect(Ki, dirs3, thr), Ki, "int reference")
+    assert_match(refs[1][0], oracle.wect(Kf, dirs3, thr), Kf, "float reference")
+    try:
+        for tt in (1, 7, 32, 50):
+            _say(f"threshold tile {tt}")
+            W.set_launch(threshold_tile=tt)
+            got = [gpu_wect(W, [Ki], dirs3, thr), gpu_wect(W, [Kf], dirs3, thr), gpu_wect(W, [C], dirs2, thr)]
+            for a, b in zip(got, refs):
+                assert np.array_equal(a, b), tt
+    finally:
+        W.set_launch()
+
+
+@pytest.mark.parametrize("T", [1000, 4096])
+def test_adjoint_many_thresholds(W, T):
+    """The adjoint over threshold tiles (each tile's reverse scan of grad_out,
+    accumulated) against the oracle, explicit and vertex-max weights."""
+    thr = synth.uniform_thresholds(T, 2.0)
+    cases = [synth.random_tiny_complex(31, n=3, nv=12, top_dim=3, wmode="explicit", wdtype=np.float32),
+             synth.random_tiny_complex(32, n=2, nv=12, top_dim=2, wmode="vertex_max")]
+    for K in cases:
+        d = 70
+        dirs = synth.fibonacci_directions(d) if K.n == 3 else synth.s1_directions(d)
+        g = synth.rng(72, T, K.n).normal(size=(1, d, T)).astype(np.float32)
+        _say(f"adjoint T={T} {K.wmode}")
+        got = W.wect_backward(W.SimplicialBatch.from_host([K]), W.Grid(dirs, thr), torch.from_numpy(g).cuda())
+        torch.cuda.synchronize()
+        ref = oracle.wect_backward(K, dirs, thr, g[0])
+        bound = oracle.wect_backward(K, dirs, thr, g[0], absolute=True)
+        if K.wmode == "vertex_max":
+            pairs = [(got.cpu().numpy(), ref, bound)]
+        else:
+            pairs = [(got[i].cpu().numpy(), ref[i], bound[i]) for i in range(K.top_dim + 1)]
+        for x, r, bnd in pairs:
+            assert np.all(np.abs(x - r) <= 1e-5 * bnd + 1e-6), np.abs(x - r).max()
+
+
+def test_batched_forward_backward_many_thresholds(W):
+    """wect_batched (forward then adjoint in one call) at T = 700 on a small
+    differentiation batch: the forward and the adjoint use their own tiles."""
+    w = synth.cfg5(n_complexes=3, vmin=200, vmax=800)
+    thr = synth.uniform_thresholds(700, 1.5)
+    cx = W.SimplicialBatch.from_host(w.complexes)
+    g = torch.from_numpy(synth.rng(73, 0, 0).normal(size=(3, w.dirs.shape[0], 700)).astype(np.float32)).cuda()
+    out, gv = W.wect_batched(cx, W.Grid(w.dirs, thr), g)
+    torch.cuda.synchronize()
+    out, gv = out.cpu().numpy(), gv.cpu().numpy()
+    voff = np.concatenate([[0], np.cumsum([K.coords.shape[0] for K in w.complexes])])
+    for b, K in enumerate(w.complexes):
+        _say(f"batched T=700 complex {b}")
+        assert_match(out[b], oracle.wect(K, w.dirs, thr), K, f"forward {b}")
+        gb = g[b].cpu().numpy()
+        ref = oracle.wect_backward(K, w.dirs, thr, gb)
+        bound = oracle.wect_backward(K, w.dirs, thr, gb, absolute=True)
+        x = gv[voff[b]:voff[b + 1]]
+        assert np.all(np.abs(x - ref) <= 1e-5 * bound + 1e-6), np.abs(x - ref).max()
+
+
+def test_wecf_many_thresholds(W):
+    """The general-filter WECF and its adjoint at T = 1200 (threshold indices
+    of the filter values formed per tile, two bytes each)."""
+    K = synth.random_tiny_complex(41, n=2, nv=12, top_dim=2, wmode="explicit", wdtype=np.float32)
+    m, T = 67, 1200
+    fv = synth.rng(74, 0, 0).normal(size=(K.coords.shape[0], m)).astype(np.float32)
+    thr = synth.uniform_thresholds(T, 2.5)
+    cx = W.SimplicialBatch.from_host([K])
+    _say("WECF forward T=1200")
+    out = W.wecf_forward(cx, torch.from_numpy(fv).cuda(), torch.from_numpy(thr).cuda())
+    torch.cuda.synchronize()
+    assert_match(out.cpu().numpy()[0], oracle.wecf(K, fv, thr), K, "wecf")
+    _say("WECF adjoint T=1200")
+    g = synth.rng(74, 0, 1).normal(size=(1, m, T)).astype(np.float32)
+    gw = W.wecf_backward(cx, torch.from_numpy(fv).cuda(), torch.from_numpy(thr).cuda(), torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    ref = oracle.wect_backward(K, None, thr, g[0], fvals=fv)
+    bound = oracle.wect_backward(K, None, thr, g[0], absolute=True, fvals=fv)
+    for i in range(3):
+        x = gw[i].cpu().numpy()
+        assert np.all(np.abs(x - ref[i]) <= 1e-5 * bound[i] + 1e-6), (i, np.abs(x - ref[i]).max())

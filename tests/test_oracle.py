@@ -25,6 +25,9 @@ def _gold(name):
 # ---------------------------------------------------------------------------
 
 def test_appendix_tensor_primitives():
+    """The library primitives the oracle is built from (cumulative sum, max
+    over an axis, gather, scatter-add) against the appendix's worked values:
+    a check of the building blocks' semantics, not of the oracle itself."""
     g = _gold("appendix_tensor_ops.json")
     T = np.array(g["T"])
     U = np.array(g["U"])
@@ -97,6 +100,30 @@ def test_hand_square(hand):
         assert np.array_equal(oracle.wect(C, dirs, thr), exp), key
         assert np.array_equal(oracle.wect_bruteforce(C, dirs, thr), exp), key
     assert oracle.euler_characteristic(synth.single_square(True)) == 10
+
+
+def test_total_abs_weight_hand_values():
+    """sum over all cells of |w(c)|, which sets every float32 tolerance, by hand:
+    the weighted triangle 1+2+3 + 0.5+0.25+4 + 10; the unweighted one 3+3+1;
+    signs do not count; vertex-max weights (1,2,3) give vertices 6, edges
+    max(1,2)+max(1,3)+max(2,3) = 8, triangle 3; the square with intensities
+    10,20,30,40 gives vertices 100, edges 20+40+30+40, square 40; with the
+    pixel of intensity 10 excluded only the 3 vertices, the top and right
+    edges (40 each) remain."""
+    assert oracle.total_abs_weight(synth.single_triangle(True)) == 20.75
+    assert oracle.total_abs_weight(synth.single_triangle(False)) == 7
+    K = synth.single_triangle(True)
+    neg = synth.Simplicial(K.coords, K.simplices, "explicit",
+                           [np.array([-1, 2, -3], np.float32), np.array([0.5, -0.25, 4], np.float32),
+                            np.array([-10], np.float32)])
+    assert oracle.total_abs_weight(neg) == 20.75
+    vm = synth.Simplicial(K.coords, K.simplices, "vertex_max", [np.array([1, 2, 3], np.float32)])
+    assert oracle.total_abs_weight(vm) == 17
+    assert oracle.total_abs_weight(synth.single_square(True)) == 270
+    assert oracle.total_abs_weight(synth.single_square(False)) == 9
+    cut = synth.single_square(True)
+    cut = synth.Cubical(cut.intensity, cut.axes, include_above=15, weighted=True)
+    assert oracle.total_abs_weight(cut) == 20 + 30 + 40 + 40 + 40
 
 
 def test_hand_gradient(hand):
