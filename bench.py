@@ -1,17 +1,32 @@
-"""Benchmark: WECT simplex*directions per second on one MI355X.
+"""Benchmark: WECT cell x direction throughput on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+                    [--no-single] [--no-calibrate] [--only WORKLOAD] [--copy-calibration]
 
-Headline workload: 256 uint8 images of 128x128 (Gaussian random fields, sigma
-4 px), pixels with intensity > 64 are vertices, cells induced, cell weight =
-max vertex intensity, 64 directions on S^1, 128 thresholds on [-sqrt2, sqrt2],
-int32 output [256, 64, 128], all images in one batched call.  One step = one
-batched forward over the whole batch, inputs resident in HBM.  Before the
-warm-up steps the step runs back to back for half a second, untimed, so that
-the GPU's clocks have left their idle state.
+Headline workload (the largest single-GPU configuration): 16 uint8 volumes
+with sides drawn uniformly from 64..192 per axis (Gaussian random fields,
+sigma 6 voxels), voxels with intensity > 100 are vertices, edges / squares /
+cubes induced, cell weight = max vertex intensity, 512 Fibonacci-sphere
+directions, 256 thresholds on [-sqrt3, sqrt3], int32 output [16, 512, 256],
+all volumes in one batched call.  One step = one batched forward over the
+whole batch, inputs resident in HBM.  Before the warm-up steps the step runs
+back to back for half a second, untimed, so that the GPU's clocks have left
+their idle state.
 
 Items = directions x (cells of every dimension, vertices included), whatever
-shortcut the kernel takes.  Prints one JSON line.
+shortcut the kernel takes.  Prints one JSON line: the headline, its roofline
+(VALU issue of the histogram kernel, algorithmic lane operations per launch
+over its HIP-event duration), the HBM fraction at algorithmic bytes against
+the MI355X peak and against a measured device copy, the LDS atomic rate
+against a measured conflict-free rate, and under "configs" the same
+quantities for every other workload (3D Kuhn mesh forward and adjoint,
+differentiation batch forward / forward + adjoint / graph, 2D image batch,
+small 2D mesh), each batched against one launch per complex; the CPU oracle
+on a bounded sample of the headline, on all host cores and on one.
+
+--only NAME runs one workload (volumes3d, images2d, kuhn3d, diffbatch,
+mesh2d) and prints its block: the profiling runs use it so that kernel
+statistics and counters belong to one workload.
 """
 from __future__ import annotations
 
@@ -19,7 +34,9 @@ import argparse
 import hashlib
 import json
 import math
+import multiprocessing as mp
 import os
+import platform
 import sys
 import time
 
@@ -31,7 +48,12 @@ UNIT = "simplex·directions/s"
 HBM_PEAK_GBPS = 8000.0
 # VALU lane-operations per second: 256 CUs x 64 lanes x 2.4 GHz (non-packed, non-fused)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+WORKLOADS = ("volumes3d", "images2d", "kuhn3d", "diffbatch", "mesh2d")
 
+
+# ---------------------------------------------------------------------------
+# bookkeeping: cells, algorithmic work and bytes
+# ---------------------------------------------------------------------------
 
 def cubical_cell_count(C) -> int:
     """Number of cells (vertices, edges, squares, cubes) of an image/volume
@@ -61,34 +83,41 @@ def included_vertices(C) -> int:
     return int((np.asarray(C.intensity) > C.include_above).sum())
 
 
-def relaxation_terms(cx, grid, lam: float, chunk: int = 1 << 20, vertices_only: bool = False) -> int:
-    """Number of sigmoid window terms of the relaxation: over every simplex (or,
-    for the vertex-centric kernels, every vertex) and direction, the thresholds
-    within 17 / lam of its maximum height (bookkeeping on the device with torch;
-    heights from a float32 matmul)."""
-    import torch
-    R = 17.0 / lam
-    thr = grid.thr
-    h = cx.coords @ grid.dirs.t()                     # [V, d]
-    total = 0
-    offs = [0] + [int(v) for v in (cx.vert_off[1:].tolist() if cx.vert_off is not None else [h.shape[0]])]
-    for dim in range(1 if vertices_only else cx.top_dim + 1):
-        if dim == 0:
-            rows = h
-        else:
-            simp = cx.simplices[dim].long()
-            if cx.simp_off is not None and cx.simp_off[dim] is not None:
-                so = cx.simp_off[dim]
-                base = torch.repeat_interleave(torch.tensor(offs[:-1], device=h.device), so[1:] - so[:-1])
-                simp = simp + base[:, None]
-            rows = None
-        n = h.shape[0] if dim == 0 else simp.shape[0]
-        for i in range(0, n, chunk):
-            hm = rows[i:i + chunk] if dim == 0 else h[simp[i:i + chunk]].amax(dim=1)
-            lo = torch.searchsorted(thr, (hm - R).contiguous(), right=False)
-            hi = torch.searchsorted(thr, (hm + R).contiguous(), right=True)
-            total += int((hi - lo).sum())
-    return total
+def search_ops(T: int) -> int:
+    return math.ceil(math.log2(T + 1))
+
+
+def cubical_ops(nverts: int, n: int, T: int, d: int) -> int:
+    """Algorithmic VALU lane-ops of the top-corner forward: per included vertex
+    and direction, (n-1) adds of the axis heights, the threshold search, one
+    select of the combined weight, one add."""
+    return nverts * d * ((n - 1) + search_ops(T) + 1 + 1)
+
+
+def simplicial_ops(counts, n: int, T: int, d: int) -> int:
+    """Algorithmic VALU lane-ops of the simplicial forward (and of the adjoint,
+    whose gather-add takes the place of the histogram add): per vertex and
+    direction (2n-1) for the height, the threshold search, one add; per
+    i-simplex and direction, i maxima and one add."""
+    per_dir = counts[0] * ((2 * n - 1) + search_ops(T) + 1)
+    per_dir += sum(counts[i] * (i + 1) for i in range(1, len(counts)))
+    return per_dir * d
+
+
+def simplicial_bytes(counts, n: int, B: int, d: int, T: int, wmode: str, backward: bool = False) -> int:
+    """Algorithmic HBM bytes: coordinates, simplex index rows and weights read
+    once, the output written once (adjoint: grad_out read once, the weight
+    gradient written once instead)."""
+    b = counts[0] * n * 4 + sum(counts[i] * (i + 1) * 4 for i in range(1, len(counts)))
+    wbytes = counts[0] * 4 if wmode == "vertex_max" else (sum(counts) * 4 if wmode == "explicit" else 0)
+    b += wbytes + B * d * T * 4
+    if backward:
+        b += wbytes  # the gradient has the shape of the weights
+    return b
+
+
+def cubical_bytes(cx, d: int, T: int) -> int:
+    return int(cx.total_voxels) + int(cx.axis.numel()) * 4 + cx.B * d * T * 4
 
 
 def settle(fn, seconds=0.5):
@@ -114,6 +143,22 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def kernel_ms(W, fn, reps):
+    """Average HIP-event duration of the library's main kernels (forward
+    histogram, adjoint) per launch, recorded on their own stream."""
+    import torch
+    W.profile_enable(True)
+    W.profile_read(reset=True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    p = W.profile_read(reset=True)
+    W.profile_enable(False)
+    f = p["fwd_ms"] / p["fwd_launches"] if p["fwd_launches"] else None
+    b = p["bwd_ms"] / p["bwd_launches"] if p["bwd_launches"] else None
+    return f, b, p
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_03909_amd", "csrc")
@@ -124,9 +169,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(name: str):
+def load_counters(name: str):
     """HBM traffic per launch measured with rocprofv3 counters for the current
-    kernel sources (profiles/<name>.json), or None."""
+    kernel sources (profiles/<name>.json), or None when the sources changed."""
     path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
@@ -134,18 +179,391 @@ def load_traffic(name: str):
         rec = json.load(f)
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
 
+
+def roofline(kernel: str, ops: int, bytes_alg: int, k_ms: float, calib, profile_name: str,
+             lds_atomics: int = 0, step_ms: float = None):
+    """VALU-issue roofline of one kernel launch: algorithmic lane-ops over the
+    kernel's duration (capped below by the whole step's time when the step is
+    that kernel alone), the algorithmic-bytes HBM fraction, the measured
+    counter traffic when available, and the LDS atomic rate."""
+    t_ms = k_ms if step_ms is None else min(k_ms, step_ms)
+    t = t_ms * 1e-3
+    ach = ops / t / 1e12
+    gbps = bytes_alg / t / 1e9
+    rec = load_counters(profile_name)
+    r = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
+         "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
+         "kernel": kernel, "kernel_ms": t_ms, "alg_ops_per_launch": ops,
+         "hbm_alg_bytes_per_launch": bytes_alg, "hbm_achieved_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS}
+    if calib and calib.get("copy_GBps"):
+        r["hbm_frac_of_measured_copy"] = gbps / calib["copy_GBps"]
+    if rec:
+        r["counter_GBps"] = rec["traffic_bytes_per_launch"] / t / 1e9
+        r["counter_hbm_frac"] = r["counter_GBps"] / HBM_PEAK_GBPS
+        if rec.get("sq"):
+            r["counters"] = rec["sq"]
+    if lds_atomics:
+        r["lds_atomics_per_s"] = lds_atomics / t
+        if calib and calib.get("lds_add_per_s"):
+            r["lds_atomic_frac_of_measured"] = {k: lds_atomics / t / v for k, v in calib["lds_add_per_s"].items()}
+    return r
+
+
+# ---------------------------------------------------------------------------
+# calibration: achievable HBM copy and conflict-free LDS atomics
+# ---------------------------------------------------------------------------
+
+def calibrate(W):
+    import torch
+    from paper_2511_03909_amd import _lib as L
+    lib = L.lib()
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        L.check(lib.wect_calib_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream), "copy")
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.check(lib.wect_calib_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream), "copy")
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    out["copy_GBps"] = 2 * nbytes / (ms * 1e-3) / 1e9  # read + write
+    out["copy_bytes"] = nbytes
+    del src, dst
+    blocks, reps = 2048, 4096
+    rates = {}
+    for kind, name, width in ((0, "u32", 4), (1, "u64", 8), (2, "f32", 4)):
+        buf = torch.empty(blocks * 64 * width, dtype=torch.uint8, device="cuda")
+        r = reps if kind != 2 else reps // 16
+        L.check(lib.wect_calib_lds_atomics(kind, blocks, r, buf.data_ptr(), stream), "lds")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        L.check(lib.wect_calib_lds_atomics(kind, blocks, r, buf.data_ptr(), stream), "lds")
+        e1.record()
+        torch.cuda.synchronize()
+        rates[name] = blocks * 1024 * r / (e0.elapsed_time(e1) * 1e-3)
+    out["lds_add_per_s"] = rates
+    out["note"] = ("copy: one 1 GiB device copy (wect_calib_copy), read + write bytes over its HIP-event time; "
+                   "LDS: lane-level conflict-free atomic adds per second (wect_calib_lds_atomics, 2048 blocks of "
+                   "1024 threads)")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def run_volumes3d(W, a, calib, single=True):
+    """3D cubical batch: 16 volumes, 512 directions, T = 256, one batched forward."""
+    import torch
+    import synth
+    w = synth.cfg4()
+    cx = W.CubicalBatch.from_host(w.complexes, device="cuda")
+    g = W.Grid(w.dirs, w.thr, device="cuda")
+    d, T, B = g.d, g.T, cx.B
+    cells = sum(cubical_cell_count(C) for C in w.complexes)
+    nverts = sum(included_vertices(C) for C in w.complexes)
+    out = torch.empty((B, d, T), dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, g)), dtype=torch.uint8, device="cuda")
+
+    def step():
+        W.wect_forward(cx, g, out=out, ws=ws)
+
+    settle(step)
+    sec = timed(step, a.steps, a.warmup)
+    kf, _, _ = kernel_ms(W, step, max(5, a.steps // 2))
+    res = {"workload": w.name, "items": d * cells, "cells": cells, "included_vertices": nverts, "ms": sec * 1e3,
+           "items_per_s": d * cells / sec,
+           "roofline": roofline("k_cub_fwd<3, vertex-max>", cubical_ops(nverts, 3, T, d), cubical_bytes(cx, d, T),
+                                kf, calib, "cubical_fwd_3d_16vol_64-192_d512_T256", lds_atomics=nverts * d,
+                                step_ms=sec * 1e3)}
+    if single:
+        singles = [W.CubicalBatch.from_host([C], device="cuda") for C in w.complexes]
+        outs = [torch.empty((1, d, T), dtype=torch.int32, device="cuda") for _ in singles]
+        ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(s, g) for s in singles)), dtype=torch.uint8, device="cuda")
+        t1 = timed(lambda: [W.wect_forward(s, g, out=o, ws=ws1) for s, o in zip(singles, outs)], 2, 1)
+        res["one_per_launch"] = {"ms": t1 * 1e3, "items_per_s": d * cells / t1, "batched_speedup": t1 / sec}
+    return res, w
+
+
+def run_images2d(W, a, calib, single=True):
+    """2D cubical batch: 256 images 128^2, 64 directions, T = 128."""
+    import torch
+    import synth
+    w = synth.cfg2()
+    cx = W.CubicalBatch.from_host(w.complexes, device="cuda")
+    g = W.Grid(w.dirs, w.thr, device="cuda")
+    d, T, B = g.d, g.T, cx.B
+    cells = sum(cubical_cell_count(C) for C in w.complexes)
+    nverts = sum(included_vertices(C) for C in w.complexes)
+    out = torch.empty((B, d, T), dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, g)), dtype=torch.uint8, device="cuda")
+
+    def step():
+        W.wect_forward(cx, g, out=out, ws=ws)
+
+    settle(step)
+    sec = timed(step, max(20, a.steps), a.warmup)
+    kf, _, _ = kernel_ms(W, step, 20)
+    res = {"workload": w.name, "items": d * cells, "ms": sec * 1e3, "items_per_s": d * cells / sec,
+           "roofline": roofline("k_cub_fwd<2, vertex-max>", cubical_ops(nverts, 2, T, d), cubical_bytes(cx, d, T),
+                                kf, calib, "cubical_fwd_2d_256x128x128_d64_T128", lds_atomics=nverts * d,
+                                step_ms=sec * 1e3)}
+    if single:
+        singles = [W.CubicalBatch.from_host([C], device="cuda") for C in w.complexes]
+        outs = [torch.empty((1, d, T), dtype=torch.int32, device="cuda") for _ in singles]
+        ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(s, g) for s in singles)), dtype=torch.uint8, device="cuda")
+        t1 = timed(lambda: [W.wect_forward(s, g, out=o, ws=ws1) for s, o in zip(singles, outs)], 5, 2)
+        res["one_per_launch"] = {"ms": t1 * 1e3, "items_per_s": d * cells / t1, "batched_speedup": t1 / sec}
+    return res, w
+
+
+def run_kuhn3d(W, a, calib):
+    """3D simplicial Kuhn mesh 64^3, float32 weights per simplex, 256
+    directions, T = 256: forward, and the adjoint to the simplex weights."""
+    import torch
+    import synth
+    w = synth.cfg3()
+    cx = W.SimplicialBatch.from_host(w.complexes, device="cuda")
+    g = W.Grid(w.dirs, w.thr, device="cuda")
+    d, T = g.d, g.T
+    counts = list(cx.counts)
+    items = d * sum(counts)
+    out = torch.empty((1, d, T), dtype=torch.float32, device="cuda")
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, g, True)), dtype=torch.uint8, device="cuda")
+    gout = torch.randn((1, d, T), device="cuda")
+    grads = [torch.empty(k, dtype=torch.float32, device="cuda") for k in counts]
+
+    def fwd():
+        W.wect_forward(cx, g, out=out, ws=ws)
+
+    def fwdbwd():
+        W.wect_batched(cx, g, gout, out=out, grads=grads, ws=ws)
+
+    settle(fwd)
+    t_f = timed(fwd, 10, 2)
+    t_fb = timed(fwdbwd, 10, 2)
+    kf, kb, _ = kernel_ms(W, fwdbwd, 5)
+    ops = simplicial_ops(counts, 3, T, d)
+    return {"workload": w.name, "items": items, "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3,
+            "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
+            "roofline_fwd": roofline("k_simp_fwd<3, explicit, float>", ops,
+                                     simplicial_bytes(counts, 3, 1, d, T, "explicit"), kf, calib,
+                                     "simplicial_fwd_3d_kuhn64_d256_T256", lds_atomics=sum(counts) * d),
+            "roofline_bwd": roofline("k_simp_bwd<3, explicit>", ops,
+                                     simplicial_bytes(counts, 3, 1, d, T, "explicit", backward=True), kb, calib,
+                                     "simplicial_bwd_3d_kuhn64_d256_T256")}
+
+
+def run_diffbatch(W, a, calib, single=True):
+    """Differentiation batch: 64 Freudenthal complexes (10k-200k vertices),
+    vertex-max float32 weights, 128 directions, T = 128: forward, forward +
+    adjoint to the vertex weights, and the pair as one HIP graph."""
+    import torch
+    import synth
+    w = synth.cfg5()
+    cx = W.SimplicialBatch.from_host(w.complexes, device="cuda")
+    g = W.Grid(w.dirs, w.thr, device="cuda")
+    d, T, B = g.d, g.T, cx.B
+    counts = list(cx.counts)
+    items = d * sum(counts)
+    gout = torch.randn((B, d, T), device="cuda")
+    out = torch.empty((B, d, T), dtype=torch.float32, device="cuda")
+    gv = torch.empty(counts[0], dtype=torch.float32, device="cuda")
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, g, True)), dtype=torch.uint8, device="cuda")
+
+    def fwd():
+        W.wect_batched(cx, g, None, out=out, ws=ws)
+
+    def fwdbwd():
+        W.wect_batched(cx, g, gout, out=out, grads=gv, ws=ws)
+
+    settle(fwd)
+    t_f = timed(fwd, 10, 2)
+    t_fb = timed(fwdbwd, 10, 2)
+    kf, kb, _ = kernel_ms(W, fwdbwd, 5)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fwdbwd()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(graph):
+        fwdbwd()
+    t_g = timed(graph.replay, 10, 2)
+    ops = simplicial_ops(counts, 2, T, d)
+    res = {"workload": w.name, "items": items, "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3,
+           "fwd_bwd_graph_ms": t_g * 1e3, "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
+           "roofline_fwd": roofline("k_simp_fwd<2, vertex-max, float>", ops,
+                                    simplicial_bytes(counts, 2, B, d, T, "vertex_max"), kf, calib,
+                                    "simplicial_fwd_2d_freudenthal_batch64_d128_T128", lds_atomics=sum(counts) * d),
+           "roofline_bwd": roofline("k_simp_bwd<2, vertex-max>", ops,
+                                    simplicial_bytes(counts, 2, B, d, T, "vertex_max", backward=True), kb, calib,
+                                    "simplicial_bwd_2d_freudenthal_batch64_d128_T128")}
+    if single:
+        singles = [W.SimplicialBatch.from_host([K], device="cuda") for K in w.complexes]
+        ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(c, g, True) for c in singles)), dtype=torch.uint8,
+                          device="cuda")
+        go1 = [gout[b:b + 1].contiguous() for b in range(B)]
+        o1 = [torch.empty((1, d, T), dtype=torch.float32, device="cuda") for _ in singles]
+        gv1 = [torch.empty(c.counts[0], dtype=torch.float32, device="cuda") for c in singles]
+        t_f1 = timed(lambda: [W.wect_batched(c, g, None, out=o, ws=ws1) for c, o in zip(singles, o1)], 3, 1)
+        t_fb1 = timed(lambda: [W.wect_batched(c, g, gg, out=o, grads=v, ws=ws1)
+                               for c, gg, o, v in zip(singles, go1, o1, gv1)], 3, 1)
+        res["one_per_launch"] = {"fwd_ms": t_f1 * 1e3, "fwd_bwd_ms": t_fb1 * 1e3,
+                                 "fwd_batched_speedup": t_f1 / t_f, "fwd_bwd_batched_speedup": t_fb1 / t_fb}
+    return res, (w, cx, g, gout)
+
+
+def run_mesh2d(W, a, calib):
+    """Small 2D mesh (32 x 32 vertices), 32 directions, T = 64: launch-bound."""
+    import torch
+    import synth
+    w = synth.cfg1()
+    cx = W.SimplicialBatch.from_host(w.complexes, device="cuda")
+    g = W.Grid(w.dirs, w.thr, device="cuda")
+    items = g.d * sum(cx.counts)
+    out = torch.empty((1, g.d, g.T), dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, g)), dtype=torch.uint8, device="cuda")
+    t = timed(lambda: W.wect_forward(cx, g, out=out, ws=ws), 200, 20)
+    return {"workload": w.name, "items": items, "us_per_call": t * 1e6, "items_per_s": items / t,
+            "note": "bound by launch latency: 1.9e5 items per call"}
+
+
+def run_more(W, a, res, diff):
+    """Workloads beyond the scope rows: the general-filter WECF of the
+    differentiation batch, the Freudenthal builder, the image ECF, and the
+    sigmoid relaxation."""
+    import numpy as np
+    import torch
+    import synth
+    w5, cx5, g5, gout = diff
+    it5 = g5.d * sum(cx5.counts)
+    F5 = (cx5.coords @ g5.dirs.t()).contiguous()
+    o5w = torch.empty((cx5.B, F5.shape[1], g5.T), dtype=torch.float32, device="cuda")
+    ws5w = torch.empty(max(1, W.wecf_workspace_bytes(cx5, F5.shape[1], g5.T)), dtype=torch.uint8, device="cuda")
+    t_w = timed(lambda: W.wecf_forward(cx5, F5, g5.thr, out=o5w, ws=ws5w), 5, 1)
+    res["wecf_filter_array_diffbatch_m128"] = {"fwd_ms": t_w * 1e3, "items_per_s": it5 / t_w}
+    del F5, o5w, ws5w
+    thr5 = w5.thr.astype(np.float64)
+    lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
+    os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device="cuda")
+    t_build = timed(lambda: W.lower_star_index(cx5, cache=False), 2, 1)
+    index5 = W.lower_star_index(cx5)
+    relax = {"lam": lam5, "index_build_ms": t_build * 1e3}
+    for name, index in (("cells", None), ("lower_star", index5)):
+        wss = torch.empty(max(1, W.smooth_workspace_bytes(cx5, g5, lam5, index)), dtype=torch.uint8, device="cuda")
+        t_sf = timed(lambda: W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss, index=index), 3, 1)
+        t_sb = timed(lambda: W.smooth_backward(cx5, g5, lam5, gout, index=index), 3, 1)
+        relax[name] = {"fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3}
+        del wss
+    res["relaxation_diffbatch_lam_spacing2"] = relax
+    del index5, os5
+    w2 = synth.cfg2()
+    cxf = W.CubicalBatch.from_host(w2.complexes, device="cuda")
+    g2 = W.Grid(w2.dirs, w2.thr, device="cuda")
+    t_b = timed(lambda: W.freudenthal_from_images(cxf), 10, 2)
+    sbf = W.freudenthal_from_images(cxf)
+    of = torch.empty((sbf.B, g2.d, g2.T), dtype=torch.float32, device="cuda")
+    wsf = torch.empty(max(1, W.wect_workspace_bytes(sbf, g2)), dtype=torch.uint8, device="cuda")
+    t_fw = timed(lambda: W.wect_forward(sbf, g2, out=of, ws=wsf), 10, 2)
+    res["freudenthal_images2d"] = {"build_ms": t_b * 1e3, "simplices": sum(sbf.counts), "wect_ms": t_fw * 1e3}
+    del cxf, sbf, of, wsf
+    ecf = {}
+    for shape in ((8192, 8192), (512, 512, 512)):
+        C = synth.uniform_image(shape, 0)
+        cxe = W.CubicalBatch.from_host([C], device="cuda")
+        wse = torch.empty(max(1, W.image_ecf_workspace_bytes(cxe)), dtype=torch.uint8, device="cuda")
+        npx = int(np.prod(shape))
+        for Te in (1000, 10000):
+            thr_e = torch.as_tensor(synth.ecf_thresholds(Te), device="cuda")
+            oe = torch.empty((1, Te), dtype=torch.int32, device="cuda")
+            te = timed(lambda: W.image_ecf(cxe, thr_e, out=oe, ws=wse), 10, 2)
+            ecf["x".join(str(v) for v in shape) + f"_T{Te}"] = {"ms": te * 1e3, "Gpix_per_s": npx / te / 1e9}
+        del cxe, wse
+    res["image_ecf_uniform"] = ecf
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle baseline on a bounded sample of the headline workload
+# ---------------------------------------------------------------------------
+
+def _oracle_task(args):
+    C, dirs, thr, dir_index = args
+    import oracle
+    oracle.wect(C, dirs, thr, dir_index=dir_index)
+    return len(dir_index)
+
+
+def host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, cells_of):
+    """The oracle (unchanged, numpy) on all host cores: a process pool over
+    (volume, 4 directions) tasks, 2 tasks per volume; and on one core: the
+    three smallest volumes, 4 directions each."""
+    import numpy as np
+    import synth
+    tasks = [(C, w.dirs, w.thr, list(range(k * 64, k * 64 + 4))) for C in w.complexes for k in (0, 1)]
+    cores = host_cores()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        tiny = synth.random_tiny_cubical(0, (4, 3, 2))
+        pool.map(_oracle_task, [(tiny, w.dirs[:1], w.thr[:4], [0])] * cores)  # start the workers
+        t0 = time.perf_counter()
+        pool.map(_oracle_task, tasks, chunksize=1)
+        t_all = time.perf_counter() - t0
+    items_all = sum(cells_of[i // 2] * 4 for i in range(len(tasks)))
+    small = list(np.argsort([C.intensity.size for C in w.complexes])[:3])
+    t0 = time.perf_counter()
+    for b in small:
+        _oracle_task((w.complexes[b], w.dirs, w.thr, [0, 1, 2, 3]))
+    t_one = time.perf_counter() - t0
+    items_one = sum(cells_of[b] * 4 for b in small)
+    return {"value": items_all / t_all, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"all 16 volumes x 8 of 512 directions ({len(tasks)} tasks of 4 directions), "
+                      f"{t_all:.1f} s wall on a pool of {cores} processes",
+            "one_core": {"value": items_one / t_one, "unit": UNIT, "cores": 1,
+                         "sample": f"the 3 smallest volumes x 4 directions, {t_one:.1f} s"},
+            "host": {"nproc": os.cpu_count(), "usable": cores, "model": cpu_model()}}
+
+
+# ---------------------------------------------------------------------------
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-single", action="store_true",
-                    help="skip the one-complex-per-launch comparison (profiling the batched kernel alone)")
+    ap.add_argument("--no-single", action="store_true", help="skip the one-complex-per-launch comparisons")
+    ap.add_argument("--no-calibrate", action="store_true", help="skip the copy / LDS atomic calibration")
+    ap.add_argument("--only", choices=WORKLOADS, default=None, help="run one workload only (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration for profiling runs)")
     a = ap.parse_args(argv)
@@ -154,337 +572,72 @@ def main(argv=None):
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import synth
+    from paper_2511_03909_amd import _lib as L
     from paper_2511_03909_amd import api as W
 
     torch.cuda.set_device(0)
-    dev = "cuda"
     if a.copy_calibration:
-        src_t = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)   # 512 MiB
+        src_t = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")   # 512 MiB
         dst_t = torch.empty_like(src_t)
         for _ in range(3):
-            dst_t.copy_(src_t)
+            L.check(L.lib().wect_calib_copy(dst_t.data_ptr(), src_t.data_ptr(), src_t.numel() * 4,
+                                            torch.cuda.current_stream().cuda_stream), "copy")
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": src_t.numel() * 4, "launches": 3}), flush=True)
         del src_t, dst_t
+    calib = None if (a.no_calibrate or a.only) else calibrate(W)
 
-    # ---------------- headline: cubical 2D batch, batched forward ----------------
-    w = synth.cfg2()
-    cx = W.CubicalBatch.from_host(w.complexes, device=dev)
-    grid = W.Grid(w.dirs, w.thr, device=dev)
-    d, T, B = grid.d, grid.T, cx.B
-    cells = sum(cubical_cell_count(C) for C in w.complexes)
-    nverts = sum(included_vertices(C) for C in w.complexes)
-    items = d * cells
-    out = torch.empty((B, d, T), dtype=torch.int32, device=dev)
-    ws = torch.empty(max(1, W.wect_workspace_bytes(cx, grid)), dtype=torch.uint8, device=dev)
+    if a.only:
+        fn = {"volumes3d": lambda: run_volumes3d(W, a, None, single=False)[0],
+              "images2d": lambda: run_images2d(W, a, None, single=False)[0],
+              "kuhn3d": lambda: run_kuhn3d(W, a, None),
+              "diffbatch": lambda: run_diffbatch(W, a, None, single=False)[0],
+              "mesh2d": lambda: run_mesh2d(W, a, None)}[a.only]
+        print(json.dumps({"only": a.only, "result": fn(), "kernel_sources": kernel_source_hash()}), flush=True)
+        return
 
-    def step():
-        W.wect_forward(cx, grid, out=out, ws=ws)
-
-    settle(step)
-    sec = timed(step, a.steps, a.warmup)
-    # live kernel timing of the dominant (histogram) kernel with HIP events on its stream
-    W.profile_enable(True)
-    W.profile_read(reset=True)
-    nprof = max(10, a.steps)
-    for _ in range(nprof):
-        step()
-    torch.cuda.synchronize()
-    prof = W.profile_read(reset=True)
-    W.profile_enable(False)
-    k_ms = prof["fwd_ms"] / max(1, prof["fwd_launches"])
-    # cold runs: before each, a 1 GiB write evicts the inputs from the caches
-    # (L2 and the 256 MiB Infinity Cache), then one step is timed with events
-    flush = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
-    cold = []
-    for _ in range(5):
-        flush.fill_(1.0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        step()
-        e1.record()
-        torch.cuda.synchronize()
-        cold.append(e0.elapsed_time(e1))
-    del flush
-
-    # algorithmic work of the histogram kernel (per launch)
-    # VALU lane-ops per included vertex x direction (top-corner rule, n = 2):
-    #   (n-1) add + ceil(log2(T+1)) search + 1 select + 1 add
-    ops_per_vd = (2 - 1) + math.ceil(math.log2(T + 1)) + 1 + 1
-    alg_ops = ops_per_vd * nverts * d
-    # algorithmic HBM bytes: read every voxel once (uint8) + the axes, write the int32 output once
-    alg_bytes = cx.total_voxels * 1 + int(cx.axis.numel()) * 4 + B * d * T * 4
-    traffic = load_traffic("cubical_fwd_2d_256x128x128_d64_T128")
-    roofline = {
-        "bound": "alu",
-        "achieved": alg_ops / (k_ms * 1e-3) / 1e12,
-        "peak": VALU_PEAK_TOPS,
-        "unit": "TOP/s",
-        "frac": (alg_ops / (k_ms * 1e-3) / 1e12) / VALU_PEAK_TOPS,
-        "traffic": traffic,
-        "kernel": "k_cub_fwd<2, vertex-max>",
-        "kernel_ms": k_ms,
-        "alg_ops_per_launch": alg_ops,
-        "hbm_alg_bytes_per_launch": alg_bytes,
-        "hbm_frac": (alg_bytes / (k_ms * 1e-3) / 1e9) / HBM_PEAK_GBPS,
-        "hbm_achieved_GBps": alg_bytes / (k_ms * 1e-3) / 1e9,
-        # one LDS atomic add per included vertex and direction (lane-level)
-        "lds_atomics_per_s": nverts * d / (k_ms * 1e-3),
-    }
+    head, w4 = run_volumes3d(W, a, calib, single=not a.no_single)
+    sec = head["ms"] * 1e-3
     result = {
         "metric": METRIC,
-        "value": items / sec,
+        "value": head["items_per_s"],
         "unit": UNIT,
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": sec * 1e3,
+        "ms_per_step": head["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32",
         "data": "synthetic",
-        "config": {"workload": w.name, "images": B, "side": 128, "directions": d, "thresholds": T,
-                   "cells": cells, "included_vertices": nverts, "items_per_step": items,
-                   "mode": "batched forward, one call for all images"},
-        "roofline": roofline,
-        "cold_ms_per_step": sorted(cold)[len(cold) // 2],
+        "config": {"workload": w4.name, "volumes": len(w4.complexes), "sides": "64-192 per axis",
+                   "directions": int(w4.dirs.shape[0]), "thresholds": int(w4.thr.shape[0]),
+                   "cells": head["cells"], "included_vertices": head["included_vertices"],
+                   "items_per_step": head["items"], "mode": "batched forward, one call for all volumes"},
+        "roofline": head["roofline"],
+        "calibration": calib,
+        "kernel_sources": kernel_source_hash(),
     }
-
-    result["kernel_sources"] = kernel_source_hash()
-
-    # ---------------- one complex per launch (same images) ----------------
-    if a.no_single:
-        print(json.dumps(result), flush=True)
-        return
-    singles = [W.CubicalBatch.from_host([C], device=dev) for C in w.complexes]
-    outs = [torch.empty((1, d, T), dtype=torch.int32, device=dev) for _ in singles]
-    ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(s, grid) for s in singles)), dtype=torch.uint8,
-                      device=dev)
-
-    def step_single():
-        for s, o in zip(singles, outs):
-            W.wect_forward(s, grid, out=o, ws=ws1)
-
-    sec1 = timed(step_single, max(3, a.steps // 5), 2)
-    result["one_per_launch"] = {"value": items / sec1, "ms_per_step": sec1 * 1e3,
-                                "batched_speedup": sec1 / sec}
-
+    if "one_per_launch" in head:
+        result["one_per_launch"] = head["one_per_launch"]
+    print(json.dumps({"progress": "headline done", "ms_per_step": head["ms"]}), file=sys.stderr, flush=True)
     if not a.no_extras:
-        extras = {}
-        # differentiation workload: batched forward + adjoint to vertex weights
-        w5 = synth.cfg5()
-        cx5 = W.SimplicialBatch.from_host(w5.complexes, device=dev)
-        g5 = W.Grid(w5.dirs, w5.thr, device=dev)
-        n5 = sum(cx5.counts)
-        it5 = g5.d * n5
-        gout = torch.randn((cx5.B, g5.d, g5.T), device=dev)
-        o5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device=dev)
-        gv5 = torch.empty(cx5.counts[0], dtype=torch.float32, device=dev)
-        ws5 = torch.empty(max(1, W.wect_workspace_bytes(cx5, g5, True)), dtype=torch.uint8, device=dev)
-        t_fb = timed(lambda: W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5), 10, 2)
-        t_f = timed(lambda: W.wect_batched(cx5, g5, None, out=o5, ws=ws5), 10, 2)
-        # graph-captured forward + backward
-        graph = torch.cuda.CUDAGraph()
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5)
-        torch.cuda.current_stream().wait_stream(s)
-        with torch.cuda.graph(graph):
-            W.wect_batched(cx5, g5, gout, out=o5, grads=gv5, ws=ws5)
-        t_g = timed(graph.replay, 10, 2)
-        # the same 64 complexes, one call per complex (forward, and forward + backward)
-        singles5 = [W.SimplicialBatch.from_host([K], device=dev) for K in w5.complexes]
-        ws5s = torch.empty(max(1, max(W.wect_workspace_bytes(c, g5, True) for c in singles5)), dtype=torch.uint8,
-                           device=dev)
-        go5 = [gout[b:b + 1].contiguous() for b in range(cx5.B)]
-        o5s = [torch.empty((1, g5.d, g5.T), dtype=torch.float32, device=dev) for _ in singles5]
-        gv5s = [torch.empty(c.counts[0], dtype=torch.float32, device=dev) for c in singles5]
-        t_f1 = timed(lambda: [W.wect_batched(c, g5, None, out=o, ws=ws5s) for c, o in zip(singles5, o5s)], 3, 1)
-        t_fb1 = timed(lambda: [W.wect_batched(c, g5, gg, out=o, grads=gv, ws=ws5s)
-                               for c, gg, o, gv in zip(singles5, go5, o5s, gv5s)], 3, 1)
-        extras["differentiation_batch64"] = {
-            "workload": w5.name, "items": it5, "fwd_items_per_s": it5 / t_f, "fwd_bwd_items_per_s": it5 / t_fb,
-            "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_graph_ms": t_g * 1e3,
-            "one_per_launch": {"fwd_ms": t_f1 * 1e3, "fwd_bwd_ms": t_fb1 * 1e3,
-                               "fwd_batched_speedup": t_f1 / t_f, "fwd_bwd_batched_speedup": t_fb1 / t_fb}}
-        # the same complexes through the general vertex-filter WECF, with the filter values
-        # given as an array (here the heights of the 128 directions, formed on the device)
-        F5 = (cx5.coords @ g5.dirs.t()).contiguous()
-        o5w = torch.empty((cx5.B, F5.shape[1], g5.T), dtype=torch.float32, device=dev)
-        ws5w = torch.empty(max(1, W.wecf_workspace_bytes(cx5, F5.shape[1], g5.T)), dtype=torch.uint8, device=dev)
-        t_w = timed(lambda: W.wecf_forward(cx5, F5, g5.thr, out=o5w, ws=ws5w), 5, 1)
-        extras["differentiation_batch64"]["wecf_filter_array_m128"] = {
-            "fwd_ms": t_w * 1e3, "items_per_s": it5 / t_w,
-            "note": "filter values read from a [V, 128] array instead of formed from coordinates"}
-        del singles5, o5s, gv5s, go5, ws5s, F5, o5w, ws5w
-        # sigmoid relaxation of the same batch (lam x threshold spacing = 2): forward, and
-        # the adjoint to coordinates, directions and vertex weights; per-cell kernels and the
-        # vertex-centric kernels over the lower-star index (built once per topology)
-        thr5 = w5.thr.astype(np.float64)
-        lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
-        os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device=dev)
-        t_build = timed(lambda: W.lower_star_index(cx5, cache=False), 3, 1)
-        index5 = W.lower_star_index(cx5)
-        # algorithmic lane-ops: per sigmoid window term, forward sub, mul, exp2, add, reciprocal,
-        # weight product, rounding to the fixed-point grid, accumulate = 8; adjoint the same up to
-        # the reciprocal, then two products and two accumulations = 9.  Per coface row and direction
-        # (vertex-centric kernels): the other vertices' heights (2n - 1 each), one comparison each,
-        # one accumulation.
-        nrow_ops = sum((dm + 1) * cx5.counts[dm] * (dm * (2 * cx5.n - 1) + dm + 1)
-                       for dm in range(1, cx5.top_dim + 1)) * g5.d
-        terms_cells = relaxation_terms(cx5, g5, lam5)
-        terms_verts = relaxation_terms(cx5, g5, lam5, vertices_only=True)
-        relax = {"lam": lam5, "index_build_ms": t_build * 1e3, "index_bytes": int(index5.numel()),
-                 "note": "sigmoid window of |lam (t - h)| <= 17, about 17 thresholds per window; adjoint to "
-                         "coordinates [V,2], directions [128,2] and vertex weights"}
-        for name, index, terms, extra_ops in (("cells", None, terms_cells, 0),
-                                              ("lower_star", index5, terms_verts, nrow_ops)):
-            wss = torch.empty(max(1, W.smooth_workspace_bytes(cx5, g5, lam5, index)), dtype=torch.uint8, device=dev)
-            t_sf = timed(lambda: W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss, index=index), 5, 1)
-            t_sb = timed(lambda: W.smooth_backward(cx5, g5, lam5, gout, index=index), 5, 1)
-            W.profile_enable(True)
-            W.profile_read(reset=True)
-            for _ in range(5):
-                W.smooth_forward(cx5, g5, lam5, out=os5, ws=wss, index=index)
-                W.smooth_backward(cx5, g5, lam5, gout, index=index)
-            torch.cuda.synchronize()
-            ps = W.profile_read(reset=True)
-            W.profile_enable(False)
-            kf_ms = ps["fwd_ms"] / max(1, ps["fwd_launches"])
-            kb_ms = ps["bwd_ms"] / max(1, ps["bwd_launches"])
-            of, ob = 8 * terms + extra_ops, 9 * terms + extra_ops
-            relax[name] = {
-                "fwd_ms": t_sf * 1e3, "bwd_ms": t_sb * 1e3, "fwd_kernel_ms": kf_ms, "bwd_kernel_ms": kb_ms,
-                "fwd_items_per_s": it5 / t_sf, "bwd_items_per_s": it5 / t_sb, "window_terms": terms,
-                "roofline_fwd": {"bound": "alu", "achieved": of / (kf_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
-                                 "unit": "TOP/s", "frac": of / (kf_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
-                "roofline_bwd": {"bound": "alu", "achieved": ob / (kb_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS,
-                                 "unit": "TOP/s", "frac": ob / (kb_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS}}
-            del wss
-        if not a.no_cpu:
-            # the float64 oracle on a bounded sample: the smallest complex, 8 directions
-            from oracle import smooth as osm
-            b0 = int(np.argmin([K.coords.shape[0] for K in w5.complexes]))
-            t0 = time.perf_counter()
-            osm.smooth_wect(w5.complexes[b0], w5.dirs[:8], w5.thr, lam5)
-            tc = time.perf_counter() - t0
-            relax["cpu_oracle"] = {"value": 8 * sum(w5.complexes[b0].counts()) / tc, "unit": "simplex·directions/s",
-                                   "cores": 1, "kind": "oracle",
-                                   "sample": f"complex {b0} ({sum(w5.complexes[b0].counts())} simplices), "
-                                             f"8 directions, {tc:.1f} s"}
-        extras["differentiation_batch64"]["relaxation_lam_spacing2"] = relax
-        del cx5, o5, gv5, ws5, gout, os5, index5
-        # the relaxation on the 3D Kuhn mesh (tetrahedra; 74 cofaces per inner vertex), vertex-centric
-        w3r = synth.cfg3()
-        cx3r = W.SimplicialBatch.from_host(w3r.complexes, device=dev)
-        g3r = W.Grid(w3r.dirs, w3r.thr, device=dev)
-        t3r = w3r.thr.astype(np.float64)
-        lam3 = float(np.float32(2.0 * (t3r.size - 1) / (t3r[-1] - t3r[0])))
-        idx3 = W.lower_star_index(cx3r)
-        o3r = torch.empty((1, g3r.d, g3r.T), dtype=torch.float32, device=dev)
-        ws3r = torch.empty(max(1, W.smooth_workspace_bytes(cx3r, g3r, lam3, idx3)), dtype=torch.uint8, device=dev)
-        go3 = torch.randn((1, g3r.d, g3r.T), device=dev)
-        t3f = timed(lambda: W.smooth_forward(cx3r, g3r, lam3, out=o3r, ws=ws3r, index=idx3), 3, 1)
-        t3b = timed(lambda: W.smooth_backward(cx3r, g3r, lam3, go3, index=idx3), 3, 1)
-        it3r = g3r.d * sum(cx3r.counts)
-        extras["relaxation_3d_kuhn64"] = {"workload": w3r.name, "lam": lam3, "fwd_ms": t3f * 1e3,
-                                          "bwd_ms": t3b * 1e3, "items": it3r, "fwd_items_per_s": it3r / t3f,
-                                          "path": "lower_star"}
-        del cx3r, idx3, o3r, ws3r, go3
-        # 3D simplicial, float32 weights
-        w3 = synth.cfg3()
-        cx3 = W.SimplicialBatch.from_host(w3.complexes, device=dev)
-        g3 = W.Grid(w3.dirs, w3.thr, device=dev)
-        it3 = g3.d * sum(cx3.counts)
-        o3 = torch.empty((1, g3.d, g3.T), dtype=torch.float32, device=dev)
-        ws3 = torch.empty(max(1, W.wect_workspace_bytes(cx3, g3)), dtype=torch.uint8, device=dev)
-        t3 = timed(lambda: W.wect_forward(cx3, g3, out=o3, ws=ws3), 5, 1)
-        extras["simplicial_3d_kuhn64"] = {"workload": w3.name, "items": it3, "items_per_s": it3 / t3,
-                                          "ms": t3 * 1e3}
-        del cx3, o3, ws3
-        # 2D simplicial, small: launch-latency bound
-        w1 = synth.cfg1()
-        cx1 = W.SimplicialBatch.from_host(w1.complexes, device=dev)
-        g1 = W.Grid(w1.dirs, w1.thr, device=dev)
-        it1 = g1.d * sum(cx1.counts)
-        o1 = torch.empty((1, g1.d, g1.T), dtype=torch.int32, device=dev)
-        ws1b = torch.empty(max(1, W.wect_workspace_bytes(cx1, g1)), dtype=torch.uint8, device=dev)
-        t1 = timed(lambda: W.wect_forward(cx1, g1, out=o1, ws=ws1b), 50, 5)
-        extras["simplicial_2d_32x32"] = {"workload": w1.name, "items": it1, "items_per_s": it1 / t1,
-                                         "us_per_call": t1 * 1e6}
-        # 3D cubical, 16 volumes of uneven size, one call
-        w4 = synth.cfg4()
-        cx4 = W.CubicalBatch.from_host(w4.complexes, device=dev)
-        g4 = W.Grid(w4.dirs, w4.thr, device=dev)
-        cells4 = sum(cubical_cell_count(C) for C in w4.complexes)
-        it4 = g4.d * cells4
-        o4 = torch.empty((cx4.B, g4.d, g4.T), dtype=torch.int32, device=dev)
-        ws4 = torch.empty(max(1, W.wect_workspace_bytes(cx4, g4)), dtype=torch.uint8, device=dev)
-        t4 = timed(lambda: W.wect_forward(cx4, g4, out=o4, ws=ws4), 3, 1)
-        singles4 = [W.CubicalBatch.from_host([C], device=dev) for C in w4.complexes]
-        o4s = [torch.empty((1, g4.d, g4.T), dtype=torch.int32, device=dev) for _ in singles4]
-        ws4s = torch.empty(max(1, max(W.wect_workspace_bytes(c, g4) for c in singles4)), dtype=torch.uint8,
-                           device=dev)
-        t41 = timed(lambda: [W.wect_forward(c, g4, out=o, ws=ws4s) for c, o in zip(singles4, o4s)], 2, 1)
-        extras["cubical_3d_16vol"] = {"workload": w4.name, "items": it4, "items_per_s": it4 / t4, "ms": t4 * 1e3,
-                                      "one_per_launch_ms": t41 * 1e3, "batched_speedup": t41 / t4}
-        del cx4, o4, ws4, singles4, o4s, ws4s
-        # the headline images as weighted Freudenthal complexes built on the device
-        # (vertex weights = intensities), then their WECT through the simplicial path
-        cxf = W.CubicalBatch.from_host(w.complexes, device=dev)
-        t_build = timed(lambda: W.freudenthal_from_images(cxf), 10, 2)
-        sbf = W.freudenthal_from_images(cxf)
-        nf = sum(sbf.counts)
-        of = torch.empty((sbf.B, d, T), dtype=torch.float32, device=dev)
-        wsf = torch.empty(max(1, W.wect_workspace_bytes(sbf, grid)), dtype=torch.uint8, device=dev)
-        t_fw = timed(lambda: W.wect_forward(sbf, grid, out=of, ws=wsf), 10, 2)
-        extras["freudenthal_2d_256x128x128"] = {
-            "workload": "headline images as Freudenthal complexes (every pixel a vertex, vertex-max weights)",
-            "build_ms": t_build * 1e3, "simplices": nf, "wect_ms": t_fw * 1e3, "items_per_s": d * nf / t_fw}
-        del cxf, sbf, of, wsf
-        # ECF of an image (intensity as the vertex filter), uniform intensities as in the
-        # paper's throughput measurement; pixels (voxels) per second at 1,000 and 10,000 thresholds
-        ecf = {}
-        for shape in ((2048, 2048), (4096, 4096), (8192, 8192), (128, 128, 128), (256, 256, 256), (512, 512, 512)):
-            C = synth.uniform_image(shape, 0)
-            cxe = W.CubicalBatch.from_host([C], device=dev)
-            wse = torch.empty(max(1, W.image_ecf_workspace_bytes(cxe)), dtype=torch.uint8, device=dev)
-            npx = int(np.prod(shape))
-            key = "x".join(str(v) for v in shape)
-            for Te in (1000, 10000):
-                thr_e = torch.as_tensor(synth.ecf_thresholds(Te), device=dev)
-                oe = torch.empty((1, Te), dtype=torch.int32, device=dev)
-                te = timed(lambda: W.image_ecf(cxe, thr_e, out=oe, ws=wse), 20, 3)
-                ecf[f"{key}_T{Te}"] = {"ms": te * 1e3, "Gpix_per_s": npx / te / 1e9,
-                                       "hbm_GBps_at_1B_per_px": npx / te / 1e9}
-            del cxe, wse
-        extras["image_ecf"] = {"workload": "uniform uint8 intensities, every pixel a vertex, unweighted ECF",
-                               "results": ecf}
-        result["extras"] = extras
-
-    # ---------------- CPU oracle on a bounded sample of the headline workload ----------------
+        configs = {}
+        configs["images2d"], _ = run_images2d(W, a, calib, single=not a.no_single)
+        configs["kuhn3d"] = run_kuhn3d(W, a, calib)
+        configs["diffbatch"], diff = run_diffbatch(W, a, calib, single=not a.no_single)
+        configs["mesh2d"] = run_mesh2d(W, a, calib)
+        print(json.dumps({"progress": "configs done"}), file=sys.stderr, flush=True)
+        more = {}
+        run_more(W, a, more, diff)
+        result["configs"] = configs
+        result["extras"] = more
     if not a.no_cpu:
-        import oracle
-        # images in strided order (0, 8, 16, ..., 1, 9, ...) until about 10 s of CPU time or all are done
-        order = [b for r in range(8) for b in range(r, B, 8)]
-        sample = []
-        t0 = time.perf_counter()
-        for b in order:
-            oracle.wect(w.complexes[b], w.dirs, w.thr)
-            sample.append(b)
-            if time.perf_counter() - t0 >= 10.0:
-                break
-        tc = time.perf_counter() - t0
-        it_cpu = d * sum(cubical_cell_count(w.complexes[b]) for b in sample)
-        result["cpu_baseline"] = {"value": it_cpu / tc, "unit": UNIT, "cores": 1, "kind": "oracle",
-                                  "sample": f"{len(sample)} of {B} images (strided order), all {d} directions, "
-                                            f"{tc:.1f} s, numpy single thread (no BLAS calls)"}
+        cells_of = [cubical_cell_count(C) for C in w4.complexes]
+        result["cpu_baseline"] = cpu_baseline(w4, cells_of)
     print(json.dumps(result), flush=True)
 
 

@@ -403,6 +403,11 @@ const char* wect_status_string(wect_status s);
  *   tile means a smaller histogram, so more blocks per compute unit or a
  *   larger staging area, at the price of one pass over the cells per tile.
  *   Values above what fits are lowered to the largest tile that fits.
+ * directions_per_lane: the direction tile of the cubical forward is 64 times
+ *   this (0 = automatic: 2 when d > 64 and two histogram columns per lane fit
+ *   LDS, else 1; 1 or 2 to choose).  With 2, every staged voxel (its 3^n
+ *   neighbourhood and combined weights) serves two directions per lane.
+ *   Simplicial complexes always use 1.
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */
@@ -412,6 +417,7 @@ typedef struct {
   int32_t min_items_per_block;
   int32_t decomposition;
   int32_t threshold_tile;
+  int32_t directions_per_lane;
 } wect_launch;
 
 wect_status wect_set_launch(const wect_launch* l);
@@ -428,6 +434,26 @@ wect_status wect_get_launch(wect_launch* l);
 wect_status wect_profile_enable(int on);
 wect_status wect_profile_read(double* fwd_ms, int64_t* fwd_launches,
                               double* bwd_ms, int64_t* bwd_launches, int reset);
+
+/*
+ * Measurement helpers (not part of the transform), used to calibrate what the
+ * kernels are measured against.
+ *
+ * wect_calib_copy: copies `bytes` bytes from src to dst (device pointers,
+ *   16-byte aligned, not overlapping) with one plain kernel of 16-byte loads
+ *   and stores: the achievable HBM copy bandwidth, and the copy of known size
+ *   against which the FETCH_SIZE / WRITE_SIZE counters are scaled.
+ * wect_calib_lds_atomics: `blocks` blocks of 1024 threads; every thread
+ *   issues `reps` LDS atomic adds into its lane's column of a 64 x 64 table,
+ *   so the 64 lanes of a wavefront hit 64 consecutive words (the access
+ *   pattern of the histogram kernels).  kind 0: 32-bit integer add, 1: 64-bit
+ *   integer add, 2: float32 add.  out: device array of blocks * 64 elements of
+ *   that width (row 0 of every block's table), overwritten.  Lane-level adds
+ *   per second = blocks * 1024 * reps / (kernel time).
+ * Both only enqueue on hip_stream; WECT_ERR_ARG on bad arguments.
+ */
+wect_status wect_calib_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+wect_status wect_calib_lds_atomics(int32_t kind, int32_t blocks, int32_t reps, void* out, void* hip_stream);
 
 /* Library version string, e.g. "wect 0.1 gfx950". */
 const char* wect_version(void);

@@ -37,7 +37,7 @@ class WectGrid(ctypes.Structure):
 
 class WectLaunch(ctypes.Structure):
     _fields_ = [("block", c_int32), ("blocks_per_cu", c_int32), ("min_items_per_block", c_int32),
-                ("decomposition", c_int32), ("threshold_tile", c_int32)]
+                ("decomposition", c_int32), ("threshold_tile", c_int32), ("directions_per_lane", c_int32)]
 
 
 class WectError(RuntimeError):
@@ -83,6 +83,10 @@ def lib() -> ctypes.CDLL:
     L.wect_profile_enable.restype = c_int
     L.wect_profile_read.argtypes = [P(c_double), P(c_int64), P(c_double), P(c_int64), c_int]
     L.wect_profile_read.restype = c_int
+    L.wect_calib_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+    L.wect_calib_copy.restype = c_int
+    L.wect_calib_lds_atomics.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_void_p]
+    L.wect_calib_lds_atomics.restype = c_int
     L.wect_version.argtypes = []
     L.wect_version.restype = c_char_p
     L.wect_last_error.argtypes = []

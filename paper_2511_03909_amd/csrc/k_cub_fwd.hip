@@ -137,11 +137,13 @@ __device__ __forceinline__ void cub_weights(const CubFetch<N>& f, int include_ab
   }
 }
 
-// Forward over the voxels [lo, hi) of complex b for one direction tile: the
-// neighbourhoods of tile t+1 are loaded while the histogram of tile t runs.
-template <int N, int WM, bool FAST>
-__device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, float sx, float sy, float sz,
-                              int orth, uint32_t* hist, float* stage, int* counter, const Thr& th) {
+// Forward over the voxels [lo, hi) of complex b for one direction tile (DPL
+// directions per lane): the neighbourhoods of tile t+1 are loaded while the
+// histogram of tile t runs.
+template <int N, int WM, bool FAST, int DPL>
+__device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, const float (&sx)[DPL],
+                              const float (&sy)[DPL], const float (&sz)[DPL], const int (&orth)[DPL],
+                              uint32_t* hist, float* stage, int* counter, const Thr& th) {
   using L = CubLayout<N>;
   const int tid = threadIdx.x, lane = tid & (W - 1);
   const int wave = uniform(tid >> 6), nw = blockDim.x >> 6;
@@ -202,22 +204,31 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, fl
     f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
     __syncthreads();
     const int ne = uniform(*counter);
-    const float* Wl = stage + L::COFF + orth;  // the lane's combined weight within an entry
-    hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
-                                 [&](int e, float& h, uint32_t& w) {
-                                   h = height<N>(stage + e * L::STRIDE, sx, sy, sz);
-                                   w = bitcast<uint32_t>(Wl[e * L::STRIDE]);
-                                 });
+    if constexpr (DPL == 1) {
+      const float* Wl = stage + L::COFF + orth[0];  // the lane's combined weight within an entry
+      hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
+                                   [&](int e, float& h, uint32_t& w) {
+                                     h = height<N>(stage + e * L::STRIDE, sx[0], sy[0], sz[0]);
+                                     w = bitcast<uint32_t>(Wl[e * L::STRIDE]);
+                                   });
+    } else {
+      hist_entries2<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
+                                    [&](int e, int k, float& h, uint32_t& w) {
+                                      const float* E = stage + e * L::STRIDE;
+                                      h = height<N>(E, sx[k], sy[k], sz[k]);
+                                      w = bitcast<uint32_t>(E[L::COFF + orth[k]]);
+                                    });
+    }
     __syncthreads();
   }
 }
 
-template <int N, int WM>
+template <int N, int WM, int DPL>
 __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = p.T;
   uint32_t* hist = (uint32_t*)smem;
-  size_t off = (size_t)(T + 1) * W * 4;
+  size_t off = (size_t)(T + 1) * W * DPL * 4;
   float* P = (float*)(smem + off);
   off += align_up((size_t)(T + 1) * 4, 16);
   int* counter = (int*)(smem + off);
@@ -225,7 +236,7 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
   float* stage = (float*)(smem + off);
   Thr th;
   setup_thresholds(p.thr, T, P, th);
-  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = 0u;
+  for (int i = threadIdx.x; i < (T + 1) * W * DPL; i += blockDim.x) hist[i] = 0u;
   __syncthreads();
 
   const int k = blockIdx.x;
@@ -242,11 +253,15 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
     const int t = (int)((pos - base) / nb);
     const int64_t e0 = (pos - base) - (int64_t)t * nb;
     const int64_t e1 = mn64(nb, e0 + (end - pos));
-    float sx, sy, sz;
-    load_dir(p, t * W + lane, sx, sy, sz);
-    const int orth = (sx < 0.0f ? 1 : 0) | (sy < 0.0f ? 2 : 0) | (sz < 0.0f ? 4 : 0);
-    if (th.fast) cub_fwd_range<N, WM, true>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
-    else cub_fwd_range<N, WM, false>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    float sx[DPL], sy[DPL], sz[DPL];
+    int orth[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+      load_dir(p, t * W * DPL + j * W + lane, sx[j], sy[j], sz[j]);
+      orth[j] = (sx[j] < 0.0f ? 1 : 0) | (sy[j] < 0.0f ? 2 : 0) | (sz[j] < 0.0f ? 4 : 0);
+    }
+    if (th.fast) cub_fwd_range<N, WM, true, DPL>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    else cub_fwd_range<N, WM, false, DPL>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
     end_group<uint32_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, 0);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;
@@ -257,18 +272,23 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
 
 }  // namespace
 
-template <int N, int WM>
+template <int N, int WM, int DPL>
 static hipError_t launch_cub_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
-  if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cub_fwd<N, WM>), dim3(p.G), dim3(block), lds, s, p);
+  if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM, DPL>, lds); e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cub_fwd<N, WM, DPL>), dim3(p.G), dim3(block), lds, s, p);
   return hipGetLastError();
 }
 
+template <int DPL>
+static hipError_t launch_cub_fwd_d(const Params& p, int block, size_t lds, hipStream_t s) {
+  if (p.n == 2) return p.wmode == WM_ONES ? launch_cub_fwd_t<2, WM_ONES, DPL>(p, block, lds, s)
+                                          : launch_cub_fwd_t<2, WM_VMAX, DPL>(p, block, lds, s);
+  return p.wmode == WM_ONES ? launch_cub_fwd_t<3, WM_ONES, DPL>(p, block, lds, s)
+                            : launch_cub_fwd_t<3, WM_VMAX, DPL>(p, block, lds, s);
+}
+
 hipError_t launch_forward_cub(const Params& p, int block, size_t lds, hipStream_t s) {
-  if (p.n == 2) return p.wmode == WM_ONES ? launch_cub_fwd_t<2, WM_ONES>(p, block, lds, s)
-                                          : launch_cub_fwd_t<2, WM_VMAX>(p, block, lds, s);
-  return p.wmode == WM_ONES ? launch_cub_fwd_t<3, WM_ONES>(p, block, lds, s)
-                            : launch_cub_fwd_t<3, WM_VMAX>(p, block, lds, s);
+  return p.dpl == 2 ? launch_cub_fwd_d<2>(p, block, lds, s) : launch_cub_fwd_d<1>(p, block, lds, s);
 }
 
 }  // namespace wect

@@ -38,23 +38,25 @@ __global__ __launch_bounds__(256) void k_slot_sum(Params p) {
   const int g = blockIdx.x;
   const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & (W - 1);
-  const int T = p.T;
+  const int T = p.T, RW = W * p.dpl;
   if (q >= T) return;
   int64_t kfirst, klast;
   group_slots(p, g, kfirst, klast);
   if (klast - kfirst + 1 <= kFusedSlots) return;
-  const ACC* src = (const ACC*)p.partial + (int64_t)q * W + lane;
-  const int64_t slot_stride = (int64_t)T * W;
-  ACC v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-  int64_t kk = kfirst;
-  for (; kk + 3 <= klast; kk += 4) {
-    v0 += src[(kk + g) * slot_stride];
-    v1 += src[(kk + 1 + g) * slot_stride];
-    v2 += src[(kk + 2 + g) * slot_stride];
-    v3 += src[(kk + 3 + g) * slot_stride];
+  const int64_t slot_stride = (int64_t)T * RW;
+  for (int c = lane; c < RW; c += W) {
+    const ACC* src = (const ACC*)p.partial + (int64_t)q * RW + c;
+    ACC v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    int64_t kk = kfirst;
+    for (; kk + 3 <= klast; kk += 4) {
+      v0 += src[(kk + g) * slot_stride];
+      v1 += src[(kk + 1 + g) * slot_stride];
+      v2 += src[(kk + 2 + g) * slot_stride];
+      v3 += src[(kk + 3 + g) * slot_stride];
+    }
+    for (; kk <= klast; ++kk) v0 += src[(kk + g) * slot_stride];
+    ((ACC*)p.dsum)[((int64_t)g * T + q) * RW + c] = (v0 + v1) + (v2 + v3);
   }
-  for (; kk <= klast; ++kk) v0 += src[(kk + g) * slot_stride];
-  ((ACC*)p.dsum)[((int64_t)g * T + q) * W + lane] = (v0 + v1) + (v2 + v3);
 }
 
 // Per group (complex, direction tile): sum its slots (or read its dsum row),
@@ -76,7 +78,9 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
   const int LS = T + 1;  // padded row of the transposed result
   OT* L = (OT*)smem;     // [64][T+1]
   ACC* tot = (ACC*)(smem + align_up((size_t)W * LS * sizeof(OT), 16));  // [16][64]
-  const int g = blockIdx.x;
+  // block = (group g, 64-column half h of its dpl * 64 columns)
+  const int g = blockIdx.x / p.dpl, h = blockIdx.x - g * p.dpl;
+  const int RW = W * p.dpl;
   const int gpc = p.ntiles;
   const int b = g / gpc, t = g % gpc;
   const int lane = threadIdx.x & (W - 1), r = threadIdx.x >> 6;
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
   const int q0 = min(T, r * chunk), nq = min(T, q0 + chunk) - q0;
   int fexp = 0;
   if constexpr (sizeof(ACC) == 8) fexp = fixed_exp(p);
-  const int64_t slot_stride = (int64_t)T * W;
+  const int64_t slot_stride = (int64_t)T * RW;
   int64_t kfirst = 0, klast = -1;
   group_slots(p, g, kfirst, klast);
   if (kfirst == klast) return;  // one block covered the whole group and wrote its output
@@ -96,15 +100,15 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
 #pragma unroll
     for (int j = 0; j < PC; ++j) v[j] = 0;
     if (from_dsum) {
-      const ACC* src = (const ACC*)p.dsum + (int64_t)g * slot_stride + (int64_t)q * W + lane;
+      const ACC* src = (const ACC*)p.dsum + (int64_t)g * slot_stride + (int64_t)q * RW + h * W + lane;
 #pragma unroll
-      for (int j = 0; j < PC; ++j) v[j] = src[min(j, n - 1) * W];
+      for (int j = 0; j < PC; ++j) v[j] = src[min(j, n - 1) * RW];
     } else {
       for (int64_t kk = kfirst; kk <= klast; ++kk) {
-        const ACC* src = (const ACC*)p.partial + (kk + g) * slot_stride + (int64_t)q * W + lane;
+        const ACC* src = (const ACC*)p.partial + (kk + g) * slot_stride + (int64_t)q * RW + h * W + lane;
         ACC x[PC];
 #pragma unroll
-        for (int j = 0; j < PC; ++j) x[j] = src[min(j, n - 1) * W];
+        for (int j = 0; j < PC; ++j) x[j] = src[min(j, n - 1) * RW];
 #pragma unroll
         for (int j = 0; j < PC; ++j) v[j] += x[j];
       }
@@ -159,8 +163,9 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
       }
   }
   __syncthreads();
-  const int dv = min(W, p.d - t * W);
-  OT* out = (OT*)p.out + ((int64_t)b * p.d + (int64_t)t * W) * p.ldo;
+  const int dir0 = t * RW + h * W;
+  const int dv = min(W, p.d - dir0);
+  OT* out = (OT*)p.out + ((int64_t)b * p.d + (int64_t)dir0) * p.ldo;
   for (int i = threadIdx.x; i < dv * T; i += blockDim.x) {
     const int pp = i / T, q = i - pp * T;
     out[(int64_t)pp * p.ldo + q] = L[pp * LS + q];
@@ -302,8 +307,8 @@ __global__ void k_validate(Params p, int* flags) {
 }  // namespace
 
 
-size_t forward_lds_fixed(int T, int kind, int acc_bytes) {
-  size_t hist = (size_t)(T + 1) * W * acc_bytes;
+size_t forward_lds_fixed(int T, int kind, int acc_bytes, int dpl) {
+  size_t hist = (size_t)(T + 1) * W * dpl * acc_bytes;
   size_t pairs = ((size_t)(T + 1) * 4 + 15) / 16 * 16;
   (void)kind;
   return hist + pairs + 16;
@@ -337,7 +342,7 @@ static hipError_t launch_reduce_t(const Params& p, hipStream_t s) {
   }
   const size_t lds = reduce_lds_bytes(p.T);
   if (hipError_t e = set_lds_limit(k_reduce_scan<ACC>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_reduce_scan<ACC>), dim3(groups), dim3(1024), lds, s, p);
+  hipLaunchKernelGGL((k_reduce_scan<ACC>), dim3(groups * p.dpl), dim3(1024), lds, s, p);
   return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ std::atomic<int> g_bpc{0};  // 0: as many as LDS and wave slots allow
 std::atomic<int> g_min_items{256};
 std::atomic<int> g_decomp{0};  // wect_launch.decomposition
 std::atomic<int> g_ttile{0};   // wect_launch.threshold_tile (0: automatic)
+std::atomic<int> g_dpl{0};     // wect_launch.directions_per_lane (0: automatic)
 
 // measurement
 std::atomic<int> g_profile{0};
@@ -109,9 +110,9 @@ int acc_bytes_of(const wect_complex* c, bool smooth) {
 }
 
 void fwd_stage_lds(const wect_complex* c, const wect_grid* g, int block, int* stage, size_t* lds,
-                   bool smooth = false) {
+                   bool smooth = false, int dpl = 1) {
   const int acc_bytes = acc_bytes_of(c, smooth);
-  const size_t fixed = wect::forward_lds_fixed(g->T, c->kind, acc_bytes);
+  const size_t fixed = wect::forward_lds_fixed(g->T, c->kind, acc_bytes, dpl);
   const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
   int st = fixed + 64 * entry > kLdsLimit ? 0 : (int)std::min<size_t>(block, (kLdsLimit - fixed) / entry) / 64 * 64;
   *stage = st;
@@ -122,12 +123,12 @@ void fwd_stage_lds(const wect_complex* c, const wect_grid* g, int block, int* st
 // they reach 16 or more resident wavefronts per CU (several independent blocks
 // overlap their staging and histogram phases); otherwise the size with the
 // most resident wavefronts (32 wave slots and 160 KiB of LDS per CU) wins.
-int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only, bool smooth) {
+int auto_block(const wect_complex* c, const wect_grid* g, bool bwd_only, bool smooth, int dpl) {
   if (bwd_only || g->T <= 0) return 1024;
   auto waves_of = [&](int b) {
     int stage = 0;
     size_t lds = 0;
-    fwd_stage_lds(c, g, b, &stage, &lds, smooth);
+    fwd_stage_lds(c, g, b, &stage, &lds, smooth, dpl);
     if (stage == 0) return 0;
     const int by_lds = (int)((160 * 1024) / (lds + 1024));
     return std::min(32 / (b / kW), by_lds) * (b / kW);
@@ -286,7 +287,19 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     if (c->dtype != WECT_F32 || c->wmode == WECT_W_ONES) return WECT_ERR_ARG;
   }
 
-  const int ntiles = (int)ceil_div(g->d, kW);
+  // directions per lane of the forward: two (a tile of 128 directions, so
+  // that every staged voxel serves two directions per lane) for cubical
+  // complexes with more than one 64-direction tile, when two histogram
+  // columns per lane fit LDS with 256 staged voxels; else one
+  int dpl = 1;
+  if (need_fwd && c->kind == WECT_CUBICAL && !smooth && !ls && g->T > 0) {
+    const int user = g_dpl.load();
+    const bool fits2 = wect::forward_lds_fixed(g->T, c->kind, 4, 2) +
+                           256 * wect::forward_entry_bytes(c->kind, c->n) <= kLdsLimit;
+    dpl = (user == 2 || (user == 0 && g->d > kW)) && fits2 ? 2 : 1;
+  }
+  p.dpl = dpl;
+  const int ntiles = (int)ceil_div(g->d, kW * dpl);
   DeviceInfo di;
   const bool have_dev = device_info(&di);
   const int cus = have_dev ? di.cus : 256;
@@ -303,7 +316,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
     auto fits_stage = [&](int t, size_t nst) {
       return ls ? wect::smooth_ls_forward_lds_bytes(t, 256) <= kLdsLimit
-                : wect::forward_lds_fixed(t, c->kind, acc_bytes) + nst * entry <= kLdsLimit;
+                : wect::forward_lds_fixed(t, c->kind, acc_bytes, dpl) + nst * entry <= kLdsLimit;
     };
     tt_fwd = choose_tile(g->T, [&](int t) { return fits_stage(t, 64); }, [&](int t) { return fits_stage(t, 256); });
     if (tt_fwd == 0) return WECT_ERR_UNSUPPORTED;
@@ -329,7 +342,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     block = block ? std::min(block, fit) : fit;
     if (block == 0) block = 256;
   } else if (!block) {
-    block = auto_group ? 1024 : auto_block(c, &gt, need_bwd && !need_fwd, smooth);
+    block = auto_group ? 1024 : auto_block(c, &gt, need_bwd && !need_fwd, smooth, dpl);
   }
   pl->block = block;
   pl->elems = elems;
@@ -356,7 +369,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
       lds = wect::smooth_ls_forward_lds_bytes(tt_fwd, block);
       if (lds > kLdsLimit) stage = 0;
     } else {
-      fwd_stage_lds(c, &gt, block, &stage, &lds, smooth);
+      fwd_stage_lds(c, &gt, block, &stage, &lds, smooth, dpl);
     }
     if (stage == 0) return WECT_ERR_UNSUPPORTED;
     pl->stage_fwd = stage;
@@ -374,7 +387,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->S_fwd = S;
     p.group_mode = pl->group_mode ? 1 : 0;
     const int64_t slots = pl->group_mode ? 0 : G + groups;
-    const size_t slot_bytes = (size_t)tt_fwd * kW * acc_bytes;
+    const size_t slot_bytes = (size_t)tt_fwd * kW * dpl * acc_bytes;
     // Slots a group may have (blocks meeting its stream range).  A batch's
     // per-complex sizes are on the device: the kernels decide per group, and
     // the separate slot summation is launched when the average group has many
@@ -750,6 +763,7 @@ wect_status ecf_plan(const wect_complex* c, int32_t T, const float* thr, EcfPlan
   if (c->include_above < -1 || c->include_above > 255) return WECT_ERR_ARG;
   Params& p = pl->p;
   std::memset(&p, 0, sizeof(p));
+  p.dpl = 1;
   p.kind = WECT_CUBICAL;
   p.n = c->n;
   p.B = c->B;
@@ -775,6 +789,10 @@ wect_status ecf_plan(const wect_complex* c, int32_t T, const float* thr, EcfPlan
 }
 
 }  // namespace
+
+namespace wect {
+void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+}  // namespace wect
 
 extern "C" {
 
@@ -863,8 +881,10 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (l->blocks_per_cu < 0 || l->blocks_per_cu > 64 || l->min_items_per_block < 0) return WECT_ERR_ARG;
   if (l->decomposition < 0 || l->decomposition > 2) return WECT_ERR_ARG;
   if (l->threshold_tile < 0) return WECT_ERR_ARG;
+  if (l->directions_per_lane < 0 || l->directions_per_lane > 2) return WECT_ERR_ARG;
   g_decomp.store(l->decomposition);
   g_ttile.store(l->threshold_tile);
+  g_dpl.store(l->directions_per_lane);
   g_block.store(l->block);
   g_bpc.store(l->blocks_per_cu);
   g_min_items.store(l->min_items_per_block ? l->min_items_per_block : 256);
@@ -878,6 +898,7 @@ wect_status wect_get_launch(wect_launch* l) {
   l->min_items_per_block = g_min_items.load();
   l->decomposition = g_decomp.load();
   l->threshold_tile = g_ttile.load();
+  l->directions_per_lane = g_dpl.load();
   return WECT_OK;
 }
 
@@ -969,6 +990,7 @@ wect_status wect_freudenthal_build(const wect_complex* c, float* coords, float* 
   if (c->total_voxels > 0 && (!c->intensity || !coords || !vweights || !edges || !tris)) return WECT_ERR_ARG;
   Params p;
   std::memset(&p, 0, sizeof(p));
+  p.dpl = 1;
   p.kind = WECT_CUBICAL;
   p.n = 2;
   p.B = c->B;

@@ -284,6 +284,67 @@ __device__ __forceinline__ void hist_entries(ACC* col, int first, int step, int 
   }
 }
 
+// As hist_entries for entries that serve two directions per lane (a tile of
+// 128 directions: column `lane` for the first, `lane + 64` for the second,
+// rows 128 wide).  entry(e, k, h, w) gives the height and weight of entry e
+// for the lane's k-th direction.  The index mode switch is per wavefront as
+// in hist_entries, counted over both directions.
+template <bool FAST, typename ACC, typename Entry>
+__device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int ne, const Thr& th, int* arith,
+                                              Entry entry) {
+  constexpr int RW = 2 * W;
+  int e = first;
+  if constexpr (FAST) {
+    while (*arith && e + 1 < ne) {
+      const int stop = min(ne - 1, e + 32 * step);
+      int fixes = 0, pairs = 0;
+      for (; e < stop; e += step) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          float h0, h1;
+          ACC w0, w1;
+          entry(e, k, h0, w0);
+          entry(e + 1, k, h1, w1);
+          int b0, b1;
+          const bool ok0 = thr_arith(h0, th, b0);
+          const bool ok1 = thr_arith(h1, th, b1);
+          if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
+            ++fixes;
+            if (!ok0) b0 = thr_near(h0, b0, th);
+            if (!ok1) b1 = thr_near(h1, b1, th);
+          }
+          ++pairs;
+          lds_add(&col[b0 * RW + k * W], w0);
+          lds_add(&col[b1 * RW + k * W], w1);
+        }
+      }
+      if (4 * fixes > pairs) *arith = 0;
+    }
+  }
+  for (; e + 1 < ne; e += step) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      float h0, h1;
+      ACC w0, w1;
+      entry(e, k, h0, w0);
+      entry(e + 1, k, h1, w1);
+      const int b0 = thr_index<FAST>(h0, th);
+      const int b1 = thr_index<FAST>(h1, th);
+      lds_add(&col[b0 * RW + k * W], w0);
+      lds_add(&col[b1 * RW + k * W], w1);
+    }
+  }
+  if (e < ne) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      float h0;
+      ACC w0;
+      entry(e, k, h0, w0);
+      lds_add(&col[thr_index<FAST>(h0, th) * RW + k * W], w0);
+    }
+  }
+}
+
 // Logistic sigmoid 1 / (1 + 2^-x) of x = lam (thr - h) log2(e); also returns
 // e = 2^-x, from which sig (1 - sig) = e sig^2 follows without cancellation.
 __device__ __forceinline__ float sigmoid2(float x, float& e) {
@@ -590,14 +651,15 @@ __device__ __forceinline__ float max_height(const float* E, float sx, float sy, 
   return h;
 }
 
+// Histogram rows are W * p.dpl columns wide (p.dpl directions per lane).
 template <typename ACC>
 __device__ void flush_hist(const Params& p, ACC* hist, int64_t slot) {
   __syncthreads();
-  const int T = p.T;
-  ACC* dst = (ACC*)p.partial + slot * (int64_t)T * W;
-  for (int i = threadIdx.x; i < T * W; i += blockDim.x) dst[i] = hist[i];
+  const int T = p.T, RW = W * p.dpl;
+  ACC* dst = (ACC*)p.partial + slot * (int64_t)T * RW;
+  for (int i = threadIdx.x; i < T * RW; i += blockDim.x) dst[i] = hist[i];
   __syncthreads();
-  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = ACC(0);
+  for (int i = threadIdx.x; i < (T + 1) * RW; i += blockDim.x) hist[i] = ACC(0);
   __syncthreads();
 }
 
@@ -626,38 +688,42 @@ __device__ void finish_group(const Params& p, ACC* hist, int b, int t, int fexp)
   using O = OutOf<ACC>;
   using OT = typename O::T;
   __syncthreads();
-  const int T = p.T;
+  const int T = p.T, RW = W * p.dpl;
   const int lane = threadIdx.x & (W - 1), r = threadIdx.x >> 6, R = blockDim.x >> 6;
   const int chunk = ((T + R - 1) / R + 3) & ~3;  // a multiple of 4 rows
   const int q0 = min(T, r * chunk), q1 = min(T, q0 + chunk);
-  ACC run = 0;
-  for (int q = q0; q < q1; ++q) {
-    run += hist[q * W + lane];
-    hist[q * W + lane] = run;
-  }
-  __syncthreads();
-  ACC off = 0;
-  for (int rr = 0; rr < r; ++rr) {
-    const int e = min(T, (rr + 1) * chunk);
-    if (e > rr * chunk) off += hist[(e - 1) * W + lane];
-  }
-  const int dir = t * W + lane;
-  if (dir < p.d && q0 < q1) {
-    OT* o = (OT*)p.out + ((int64_t)b * p.d + dir) * p.ldo;
-    if ((T & 3) == 0 && (p.ldo & 3) == 0 && (reinterpret_cast<uintptr_t>(p.out) & 15) == 0) {
-      // rows start 16-byte aligned and q0 is a multiple of 4
-      for (int q = q0; q < q1; q += 4) {
-        OT v[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = O::conv(hist[(q + j) * W + lane] + off, fexp);
-        *(uint4*)(o + q) = *(const uint4*)v;
-      }
-    } else {
-      for (int q = q0; q < q1; ++q) o[q] = O::conv(hist[q * W + lane] + off, fexp);
+  for (int c = lane; c < RW; c += W) {
+    ACC run = 0;
+    for (int q = q0; q < q1; ++q) {
+      run += hist[q * RW + c];
+      hist[q * RW + c] = run;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < (T + 1) * W; i += blockDim.x) hist[i] = ACC(0);
+  for (int c = lane; c < RW; c += W) {
+    ACC off = 0;
+    for (int rr = 0; rr < r; ++rr) {
+      const int e = min(T, (rr + 1) * chunk);
+      if (e > rr * chunk) off += hist[(e - 1) * RW + c];
+    }
+    const int dir = t * RW + c;
+    if (dir < p.d && q0 < q1) {
+      OT* o = (OT*)p.out + ((int64_t)b * p.d + dir) * p.ldo;
+      if ((T & 3) == 0 && (p.ldo & 3) == 0 && (reinterpret_cast<uintptr_t>(p.out) & 15) == 0) {
+        // rows start 16-byte aligned and q0 is a multiple of 4
+        for (int q = q0; q < q1; q += 4) {
+          OT v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = O::conv(hist[(q + j) * RW + c] + off, fexp);
+          *(uint4*)(o + q) = *(const uint4*)v;
+        }
+      } else {
+        for (int q = q0; q < q1; ++q) o[q] = O::conv(hist[q * RW + c] + off, fexp);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (T + 1) * RW; i += blockDim.x) hist[i] = ACC(0);
   __syncthreads();
 }
 

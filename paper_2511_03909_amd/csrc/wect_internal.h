@@ -37,7 +37,9 @@ struct Params {
   const float* thr;      // the launch's thresholds (first entry of its tile)
   int32_t ldo;           // row stride of out and grad_out: the request's full threshold count
   // decomposition
-  int32_t ntiles;        // direction tiles of 64 (forward) / per group (backward)
+  int32_t ntiles;        // direction tiles of 64 * dpl (forward) / per group (backward)
+  int32_t dpl;           // directions per lane: 1, or 2 (cubical forward: a tile of 128 directions, two
+                         // histogram columns per lane, so each staged voxel serves both)
   int32_t G;             // blocks of the main kernel
   int64_t S;             // stream length: sum over groups of the stream elements
   int32_t stage;         // staged entries per tile (<= blockDim.x)
@@ -121,12 +123,15 @@ constexpr int kLsChunk = 8192;  // elements per block of the build's scan
 
 // LDS bytes of the forward kernels: fixed part (histogram, thresholds) plus
 // forward_entry_bytes per staged entry; of the backward kernel in total.
-size_t forward_lds_fixed(int T, int kind, int acc_bytes);
+size_t forward_lds_fixed(int T, int kind, int acc_bytes, int dpl = 1);
 size_t forward_entry_bytes(int kind, int n);
 size_t backward_lds_bytes(int T, int stage, int dg);
 size_t smooth_backward_lds_bytes(int T, int stage);
 
 constexpr int kAbsmaxSlots = 256;  // 64 blocks x 4 weight arrays
+
+// Records the description returned by wect_last_error() on the calling thread.
+void set_last_error(const char* msg);
 
 // Validation flags (bit set = failure).
 enum : int { kFlagIndex = 1, kFlagThr = 2, kFlagNonfinite = 4 };

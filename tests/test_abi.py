@@ -158,11 +158,12 @@ def test_launch_shape_roundtrip(lib):
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 3))) == L.WECT_ERR_ARG
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, -1))) == L.WECT_ERR_ARG
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, -5))) == L.WECT_ERR_ARG
-    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77))) == L.WECT_OK
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77, 3))) == L.WECT_ERR_ARG
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77, 2))) == L.WECT_OK
     now = L.WectLaunch()
     lib.wect_get_launch(ctypes.byref(now))
     assert (now.block, now.blocks_per_cu, now.min_items_per_block, now.decomposition,
-            now.threshold_tile) == (512, 2, 1024, 2, 77)
+            now.threshold_tile, now.directions_per_lane) == (512, 2, 1024, 2, 77, 2)
     assert lib.wect_set_launch(ctypes.byref(before)) == L.WECT_OK
 
 
@@ -193,6 +194,36 @@ def test_workspace_grows_with_batch(lib):
     # most about 600 (int32), and the partial slots are sized for one tile
     big = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(L.WectGrid(FAKE, 100, 100000, FAKE)), 0)
     assert 0 < big <= slots * 700 * 64 * 4 + 256
+
+
+def test_two_directions_per_lane_doubles_the_slot_width(lib):
+    """Cubical forward with 130 directions: one lane per direction gives 3
+    tiles of 64, two per lane 2 tiles of 128 (slots twice as wide); a
+    simplicial request ignores the setting."""
+    before = L.WectLaunch()
+    lib.wect_get_launch(ctypes.byref(before))
+    c = L.WectComplex()
+    c.kind, c.n, c.B, c.wmode, c.dtype = L.WECT_CUBICAL, 2, 1, L.WECT_W_VERTEX_MAX, L.WECT_I32
+    c.shape, c.axis, c.intensity, c.total_voxels = FAKE, FAKE, FAKE, 5000
+    g = _grid(d=130, T=40)
+    try:
+        sizes = {}
+        for dpl in (1, 2):
+            assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, dpl))) == L.WECT_OK
+            sizes[dpl] = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
+        # partial slots (blocks + groups) and slot sums (groups), each T x 64 dpl x 4 bytes; blocks of at
+        # least 64 stream items (tiles x voxels), at most 256 (one per compute unit without a device)
+        for dpl, tiles in ((1, 3), (2, 2)):
+            blocks = min(256, -(-tiles * 5000 // 64))
+            assert sizes[dpl] == (blocks + 2 * tiles) * 40 * 64 * dpl * 4
+        s = _simplicial()
+        per = []
+        for dpl in (1, 2):
+            assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, dpl))) == L.WECT_OK
+            per.append(lib.wect_workspace_bytes(ctypes.byref(s), ctypes.byref(g), 0))
+        assert per[0] == per[1]
+    finally:
+        lib.wect_set_launch(ctypes.byref(before))
 
 
 def test_threshold_tile_sets_the_slot_size(lib):

@@ -196,3 +196,31 @@ def test_wecf_many_thresholds(W):
     for i in range(3):
         x = gw[i].cpu().numpy()
         assert np.all(np.abs(x - ref[i]) <= 1e-5 * bound[i] + 1e-6), (i, np.abs(x - ref[i]).max())
+
+
+@pytest.mark.parametrize("d", [65, 128, 130, 300])
+def test_two_directions_per_lane_cubical(W, d):
+    """The cubical forward with a tile of 128 directions (two histogram columns
+    per lane) gives the bits of one direction per lane, on images and volumes
+    of uneven shapes with an empty member, in both decompositions, also with
+    threshold tiles; and matches the oracle."""
+    ims = [synth.random_tiny_cubical(s, shp, include_above=70) for s, shp in
+           enumerate(((21, 9), (3, 17), (40, 33), (8, 8)))]
+    ims.insert(1, synth.Cubical(np.zeros((5, 6), np.uint8), [synth.cubical_axis(6), synth.cubical_axis(5)], 70, True))
+    vols = [synth.random_tiny_cubical(s, shp, include_above=60) for s, shp in
+            enumerate(((9, 7, 5), (3, 8, 2), (12, 10, 6)))]
+    thr = synth.uniform_thresholds(61, 1.9)
+    try:
+        for batch, dirs in ((ims, synth.s1_directions(d)), (vols, synth.fibonacci_directions(d))):
+            for dec in (1, 2):
+                for tt in (0, 16):
+                    res = []
+                    for dpl in (1, 2):
+                        _say(f"cubical n={batch[0].n} d={d} decomposition={dec} tile={tt} directions/lane={dpl}")
+                        W.set_launch(decomposition=dec, threshold_tile=tt, directions_per_lane=dpl)
+                        res.append(gpu_wect(W, batch, dirs, thr))
+                    assert np.array_equal(res[0], res[1])
+            for b, C in enumerate(batch):
+                assert_match(res[1][b], oracle.wect(C, dirs, thr), C, f"d={d} complex {b}")
+    finally:
+        W.set_launch()
