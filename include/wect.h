@@ -151,6 +151,22 @@ wect_status wect_forward(const wect_complex* c, const wect_grid* g, void* out,
                          void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * wect_forward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * wect_forward with ws / ws_bytes dropped: the workspace is a static device
+ * array of 64 MiB inside the library, one per device, held by each device the
+ * library runs on until the process ends.  A request whose workspace
+ * (wect_workspace_bytes(c, g, 0)) exceeds 64 MiB returns WECT_ERR_WORKSPACE
+ * (wect_last_error() gives the sizes) and enqueues nothing.  The call itself
+ * allocates nothing (no hipMalloc, no library allocation); the first call on
+ * a device looks up that device's array address.  Calls that overlap on one
+ * device (concurrent streams or threads) share the array and race: serialise
+ * them.  Nothing in the array needs clearing between calls.
+ */
+wect_status wect_forward_noalloc(const wect_complex* c, const wect_grid* g, void* out, void* hip_stream);
+
+/*
  * Adjoint of the forward with respect to the weights (simplicial, float32
  * weights).  The forward is linear in the cell weights, so for
  * L = sum_{b,p,q} grad_out[b][p][q] * out[b][p][q]:

@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
     L.wect_workspace_bytes.restype = c_size_t
     L.wect_forward.argtypes = [P(WectComplex), P(WectGrid), c_void_p, c_void_p, c_size_t, c_void_p]
     L.wect_forward.restype = c_int
+    L.wect_forward_noalloc.argtypes = [P(WectComplex), P(WectGrid), c_void_p, c_void_p]
+    L.wect_forward_noalloc.restype = c_int
     L.wect_backward.argtypes = [P(WectComplex), P(WectGrid), c_void_p, P(c_void_p), c_void_p, c_void_p,
                                 c_size_t, c_void_p]
     L.wect_backward.restype = c_int
