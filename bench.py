@@ -159,30 +159,40 @@ def kernel_ms(W, fn, reps):
     return f, b, p
 
 
-def kernel_source_hash() -> str:
+# the sources that decide what a profiled kernel does (its translation unit,
+# the shared device helpers, the host runtime that plans its launches)
+KERNEL_SOURCES = {
+    "cub_fwd": ["k_cub_fwd.hip", "k_reduce.hip", "wect_device.h", "wect_internal.h", "wect_api.cpp"],
+    "simp_fwd": ["k_simp_fwd.hip", "k_reduce.hip", "wect_device.h", "wect_internal.h", "wect_api.cpp"],
+    "simp_bwd": ["k_simp_bwd.hip", "wect_device.h", "wect_internal.h", "wect_api.cpp"],
+}
+
+
+def kernel_source_hash(which: str = None) -> str:
+    """Hash of the kernel sources: all of them, or those of one kernel family."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2511_03909_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    files = KERNEL_SOURCES[which] if which else [f for f in os.listdir(csrc) if f.endswith((".hip", ".cpp", ".h"))]
+    for f in sorted(files):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_counters(name: str):
+def load_counters(name: str, family: str):
     """HBM traffic per launch measured with rocprofv3 counters for the current
-    kernel sources (profiles/<name>.json), or None when the sources changed."""
+    sources of the kernel family (profiles/<name>.json), or None when they changed."""
     path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hash") != kernel_source_hash(family):
         return None
     return rec
 
 
-def roofline(kernel: str, ops: int, bytes_alg: int, k_ms: float, calib, profile_name: str,
+def roofline(kernel: str, ops: int, bytes_alg: int, k_ms: float, calib, profile_name: str, family: str,
              lds_atomics: int = 0, step_ms: float = None):
     """VALU-issue roofline of one kernel launch: algorithmic lane-ops over the
     kernel's duration (capped below by the whole step's time when the step is
@@ -192,7 +202,7 @@ def roofline(kernel: str, ops: int, bytes_alg: int, k_ms: float, calib, profile_
     t = t_ms * 1e-3
     ach = ops / t / 1e12
     gbps = bytes_alg / t / 1e9
-    rec = load_counters(profile_name)
+    rec = load_counters(profile_name, family)
     r = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
          "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
          "kernel": kernel, "kernel_ms": t_ms, "alg_ops_per_launch": ops,
@@ -283,7 +293,7 @@ def run_volumes3d(W, a, calib, single=True):
     res = {"workload": w.name, "items": d * cells, "cells": cells, "included_vertices": nverts, "ms": sec * 1e3,
            "items_per_s": d * cells / sec,
            "roofline": roofline("k_cub_fwd<3, vertex-max>", cubical_ops(nverts, 3, T, d), cubical_bytes(cx, d, T),
-                                kf, calib, "cubical_fwd_3d_16vol_64-192_d512_T256", lds_atomics=nverts * d,
+                                kf, calib, "cubical_fwd_3d_16vol_64-192_d512_T256", "cub_fwd", lds_atomics=nverts * d,
                                 step_ms=sec * 1e3)}
     if single:
         singles = [W.CubicalBatch.from_host([C], device="cuda") for C in w.complexes]
@@ -315,7 +325,7 @@ def run_images2d(W, a, calib, single=True):
     kf, _, _ = kernel_ms(W, step, 20)
     res = {"workload": w.name, "items": d * cells, "ms": sec * 1e3, "items_per_s": d * cells / sec,
            "roofline": roofline("k_cub_fwd<2, vertex-max>", cubical_ops(nverts, 2, T, d), cubical_bytes(cx, d, T),
-                                kf, calib, "cubical_fwd_2d_256x128x128_d64_T128", lds_atomics=nverts * d,
+                                kf, calib, "cubical_fwd_2d_256x128x128_d64_T128", "cub_fwd", lds_atomics=nverts * d,
                                 step_ms=sec * 1e3)}
     if single:
         singles = [W.CubicalBatch.from_host([C], device="cuda") for C in w.complexes]
@@ -357,10 +367,10 @@ def run_kuhn3d(W, a, calib):
             "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
             "roofline_fwd": roofline("k_simp_fwd<3, explicit, float>", ops,
                                      simplicial_bytes(counts, 3, 1, d, T, "explicit"), kf, calib,
-                                     "simplicial_fwd_3d_kuhn64_d256_T256", lds_atomics=sum(counts) * d),
+                                     "simplicial_fwd_3d_kuhn64_d256_T256", "simp_fwd", lds_atomics=sum(counts) * d),
             "roofline_bwd": roofline("k_simp_bwd<3, explicit>", ops,
                                      simplicial_bytes(counts, 3, 1, d, T, "explicit", backward=True), kb, calib,
-                                     "simplicial_bwd_3d_kuhn64_d256_T256")}
+                                     "simplicial_bwd_3d_kuhn64_d256_T256", "simp_bwd")}
 
 
 def run_diffbatch(W, a, calib, single=True):
@@ -404,10 +414,10 @@ def run_diffbatch(W, a, calib, single=True):
            "fwd_bwd_graph_ms": t_g * 1e3, "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
            "roofline_fwd": roofline("k_simp_fwd<2, vertex-max, float>", ops,
                                     simplicial_bytes(counts, 2, B, d, T, "vertex_max"), kf, calib,
-                                    "simplicial_fwd_2d_freudenthal_batch64_d128_T128", lds_atomics=sum(counts) * d),
+                                    "simplicial_fwd_2d_freudenthal_batch64_d128_T128", "simp_fwd", lds_atomics=sum(counts) * d),
            "roofline_bwd": roofline("k_simp_bwd<2, vertex-max>", ops,
                                     simplicial_bytes(counts, 2, B, d, T, "vertex_max", backward=True), kb, calib,
-                                    "simplicial_bwd_2d_freudenthal_batch64_d128_T128")}
+                                    "simplicial_bwd_2d_freudenthal_batch64_d128_T128", "simp_bwd")}
     if single:
         singles = [W.SimplicialBatch.from_host([K], device="cuda") for K in w.complexes]
         ws1 = torch.empty(max(1, max(W.wect_workspace_bytes(c, g, True) for c in singles)), dtype=torch.uint8,
