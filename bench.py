@@ -196,14 +196,17 @@ def roofline(kernel: str, ops: int, bytes_alg: int, k_ms: float, calib, profile_
              lds_atomics: int = 0, step_ms: float = None):
     """VALU-issue roofline of one kernel launch: algorithmic lane-ops over the
     kernel's duration (capped below by the whole step's time when the step is
-    that kernel alone), the algorithmic-bytes HBM fraction, the measured
-    counter traffic when available, and the LDS atomic rate."""
+    that kernel alone), the same over the whole step (every kernel of the call,
+    e.g. the voxel records of the cubical forward), the algorithmic-bytes HBM
+    fraction, the measured counter traffic when available, and the LDS atomic
+    rate."""
     t_ms = k_ms if step_ms is None else min(k_ms, step_ms)
     t = t_ms * 1e-3
     ach = ops / t / 1e12
     gbps = bytes_alg / t / 1e9
     rec = load_counters(profile_name, family)
     r = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
+         "step_frac": (ops / (step_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS) if step_ms else None,
          "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
          "kernel": kernel, "kernel_ms": t_ms, "alg_ops_per_launch": ops,
          "hbm_alg_bytes_per_launch": bytes_alg, "hbm_achieved_GBps": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS}

@@ -156,8 +156,9 @@ wect_status wect_forward(const wect_complex* c, const wect_grid* g, void* out,
  * harnesses that forbid allocation).  Same arguments, results and errors as
  * wect_forward with ws / ws_bytes dropped: the workspace is a static device
  * array of 64 MiB inside the library, one per device, held by each device the
- * library runs on until the process ends.  A request whose workspace
- * (wect_workspace_bytes(c, g, 0)) exceeds 64 MiB returns WECT_ERR_WORKSPACE
+ * library runs on until the process ends.  It is planned without the cubical
+ * forward's per-voxel records (wect_launch.cubical_records), so it needs only
+ * the partial histograms.  A request whose workspace exceeds 64 MiB returns WECT_ERR_WORKSPACE
  * (wect_last_error() gives the sizes) and enqueues nothing.  The call itself
  * allocates nothing (no hipMalloc, no library allocation); the first call on
  * a device looks up that device's array address.  Calls that overlap on one
@@ -424,6 +425,12 @@ const char* wect_status_string(wect_status s);
  *   LDS, else 1; 1 or 2 to choose).  With 2, every staged voxel (its 3^n
  *   neighbourhood and combined weights) serves two directions per lane.
  *   Simplicial complexes always use 1.
+ * cubical_records: 0 = automatic, 1 = off, 2 = on.  When on, the cubical
+ *   forward first forms every voxel's 2^n combined weights once into records
+ *   (8 bytes per voxel in 2D, 16 in 3D, part of the workspace) and stages
+ *   those instead of the voxel's 3^n neighbourhood; automatic turns it on when
+ *   a voxel would otherwise be staged more than once (several direction or
+ *   threshold tiles).  wect_forward_noalloc never uses records.
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */
@@ -434,6 +441,7 @@ typedef struct {
   int32_t decomposition;
   int32_t threshold_tile;
   int32_t directions_per_lane;
+  int32_t cubical_records;
 } wect_launch;
 
 wect_status wect_set_launch(const wect_launch* l);

@@ -2,6 +2,8 @@
 
 #include "wect_device.h"
 
+#include <type_traits>
+
 namespace wect {
 namespace {
 
@@ -137,10 +139,91 @@ __device__ __forceinline__ void cub_weights(const CubFetch<N>& f, int include_ab
   }
 }
 
+// Voxel records: the 2^N combined weights of a voxel as int16 (|weight| is at
+// most 2^(N-1) * 255 < 2^15), in grid order, all zero for a voxel that is not a
+// vertex.  With several direction or threshold tiles the forward would stage
+// every voxel once per tile; k_cub_records forms them once per call and the
+// forward's staging then loads one 8- or 16-byte record per voxel instead of
+// its 3^N neighbourhood.
+template <int N>
+struct CubRec {
+  using R = typename std::conditional<N == 2, uint2, uint4>::type;
+  static constexpr int NO = 1 << N;
+  R r;
+  float cx, cy, cz;
+  bool valid;
+
+  __device__ __forceinline__ void load(const R* rec, const float* ax0, const float* ax1, const float* ax2, int n0,
+                                       int n1, int n2, int i0, int i1, int i2, uint32_t v, bool active) {
+    valid = active;
+    if (active) r = rec[v];
+    i0 = min(i0, n0 - 1);
+    i1 = min(i1, n1 - 1);
+    i2 = min(i2, n2 - 1);
+    cx = ax0[i0];
+    cy = ax1[i1];
+    cz = N == 3 ? ax2[i2] : 0.0f;
+  }
+  // combined weights; false when all are zero (or the voxel is not staged)
+  __device__ __forceinline__ bool weights(int32_t* cw) const {
+    if (!valid) return false;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(&r);
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 0; k < NO / 2; ++k) {
+      any |= w[k];
+      cw[2 * k] = (int32_t)(int16_t)(w[k] & 0xffffu);
+      cw[2 * k + 1] = (int32_t)w[k] >> 16;
+    }
+    return any != 0;
+  }
+};
+
+// One thread per voxel of the batch: its complex (binary search over the
+// voxel offsets), its grid position, its neighbourhood and its records.
+template <int N, int WM>
+__global__ __launch_bounds__(256) void k_cub_records(Params p) {
+  using RT = typename CubRec<N>::R;
+  constexpr int NO = 1 << N;
+  RT* rec = (RT*)p.cub_rec;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < p.total_voxels; g += stride) {
+    int b = 0;
+    if (p.grid_off) {
+      int lo = 0, hi = p.B - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.grid_off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+      }
+      b = lo;
+    }
+    const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = N == 3 ? p.shape[3 * b + 2] : 1;
+    const int64_t goff = off_or(p.grid_off, b, p.total_voxels);
+    const int64_t aoff = p.axis_off ? p.axis_off[b] : 0;
+    const uint32_t v = (uint32_t)(g - goff);
+    const int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
+    const int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
+    const float* ax0 = p.axis + aoff;
+    CubFetch<N> f;
+    f.load(p.intensity + goff, ax0, ax0 + n0, ax0 + n0 + n1, n0, n1, n2, i0, i1, i2, true);
+    int32_t cw[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) cw[o] = 0;
+    if (f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) cub_weights<N, WM>(f, p.include_above, cw);
+    uint32_t w[NO / 2];
+#pragma unroll
+    for (int k = 0; k < NO / 2; ++k) w[k] = ((uint32_t)cw[2 * k] & 0xffffu) | ((uint32_t)cw[2 * k + 1] << 16);
+    RT out;
+    __builtin_memcpy(&out, w, sizeof(RT));
+    rec[g] = out;
+  }
+}
+
 // Forward over the voxels [lo, hi) of complex b for one direction tile (DPL
-// directions per lane): the neighbourhoods of tile t+1 are loaded while the
-// histogram of tile t runs.
-template <int N, int WM, bool FAST, int DPL>
+// directions per lane): the neighbourhoods (or records, PRE) of tile t+1 are
+// loaded while the histogram of tile t runs.
+template <int N, int WM, bool FAST, int DPL, bool PRE>
 __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, const float (&sx)[DPL],
                               const float (&sy)[DPL], const float (&sz)[DPL], const int (&orth)[DPL],
                               uint32_t* hist, float* stage, int* counter, const Thr& th) {
@@ -164,14 +247,22 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
   uint32_t v = (uint32_t)(lo + tid);
   int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
   int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
-  CubFetch<N> f;
-  f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
+  using Fetch = typename std::conditional<PRE, CubRec<N>, CubFetch<N>>::type;
+  const typename CubRec<N>::R* rec = (const typename CubRec<N>::R*)p.cub_rec + goff;
+  Fetch f;
+  auto fetch = [&](bool active) {
+    if constexpr (PRE) f.load(rec, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v, active);
+    else f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, active);
+  };
+  fetch(v < (uint32_t)hi && tid < TS);
   for (int64_t t0 = lo; t0 < hi; t0 += TS) {
     if (tid == 0) *counter = 0;
     __syncthreads();
     bool keep = false;
     int32_t cw[L::NO];
-    if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
+    if constexpr (PRE) {
+      keep = f.weights(cw);
+    } else if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
       cub_weights<N, WM>(f, p.include_above, cw);
       bool nz = false;
 #pragma unroll
@@ -201,7 +292,7 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     i1 -= carry ? n1 : 0;
     i2 += (int)s2 + carry;
     v += ts;
-    f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v < (uint32_t)hi && tid < TS);
+    fetch(v < (uint32_t)hi && tid < TS);
     __syncthreads();
     const int ne = uniform(*counter);
     if constexpr (DPL == 1) {
@@ -223,7 +314,7 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
   }
 }
 
-template <int N, int WM, int DPL>
+template <int N, int WM, int DPL, bool PRE>
 __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = p.T;
@@ -260,8 +351,8 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
       load_dir(p, t * W * DPL + j * W + lane, sx[j], sy[j], sz[j]);
       orth[j] = (sx[j] < 0.0f ? 1 : 0) | (sy[j] < 0.0f ? 2 : 0) | (sz[j] < 0.0f ? 4 : 0);
     }
-    if (th.fast) cub_fwd_range<N, WM, true, DPL>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
-    else cub_fwd_range<N, WM, false, DPL>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    if (th.fast) cub_fwd_range<N, WM, true, DPL, PRE>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    else cub_fwd_range<N, WM, false, DPL, PRE>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
     end_group<uint32_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, 0);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;
@@ -274,8 +365,13 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
 
 template <int N, int WM, int DPL>
 static hipError_t launch_cub_fwd_t(const Params& p, int block, size_t lds, hipStream_t s) {
-  if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM, DPL>, lds); e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cub_fwd<N, WM, DPL>), dim3(p.G), dim3(block), lds, s, p);
+  if (p.cub_rec) {
+    if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM, DPL, true>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cub_fwd<N, WM, DPL, true>), dim3(p.G), dim3(block), lds, s, p);
+  } else {
+    if (hipError_t e = set_lds_limit(k_cub_fwd<N, WM, DPL, false>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cub_fwd<N, WM, DPL, false>), dim3(p.G), dim3(block), lds, s, p);
+  }
   return hipGetLastError();
 }
 
@@ -285,6 +381,20 @@ static hipError_t launch_cub_fwd_d(const Params& p, int block, size_t lds, hipSt
                                           : launch_cub_fwd_t<2, WM_VMAX, DPL>(p, block, lds, s);
   return p.wmode == WM_ONES ? launch_cub_fwd_t<3, WM_ONES, DPL>(p, block, lds, s)
                             : launch_cub_fwd_t<3, WM_VMAX, DPL>(p, block, lds, s);
+}
+
+hipError_t launch_cub_records(const Params& p, hipStream_t s) {
+  if (p.total_voxels <= 0) return hipSuccess;
+  int64_t blocks = (p.total_voxels + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (p.n == 2) {
+    if (p.wmode == WM_ONES) hipLaunchKernelGGL((k_cub_records<2, WM_ONES>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_cub_records<2, WM_VMAX>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+  } else {
+    if (p.wmode == WM_ONES) hipLaunchKernelGGL((k_cub_records<3, WM_ONES>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_cub_records<3, WM_VMAX>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_forward_cub(const Params& p, int block, size_t lds, hipStream_t s) {

@@ -58,6 +58,7 @@ std::atomic<int> g_min_items{256};
 std::atomic<int> g_decomp{0};  // wect_launch.decomposition
 std::atomic<int> g_ttile{0};   // wect_launch.threshold_tile (0: automatic)
 std::atomic<int> g_dpl{0};     // wect_launch.directions_per_lane (0: automatic)
+std::atomic<int> g_rec{0};     // wect_launch.cubical_records (0: automatic, 1: off, 2: on)
 
 // measurement
 std::atomic<int> g_profile{0};
@@ -87,6 +88,7 @@ struct Plan {
   size_t lds_fwd = 0, lds_bwd = 0;
   size_t partial_bytes = 0, dsum_bytes = 0, absmax_bytes = 0;
   size_t vb_bytes = 0;        // general-filter WECF: threshold indices of the filter values
+  size_t rec_bytes = 0;       // cubical: per-voxel records of combined weights
   bool split = false;
   bool group_mode = false;
   size_t ws_fwd = 0, ws_bwd = 0;
@@ -200,7 +202,7 @@ int choose_tile(int T, FMin fits_min, FGood fits_good) {
 // smooth: forward of the sigmoid relaxation (fixed-point accumulation for
 // every weight mode, float32 output); its adjoint is planned by smooth_plan.
 wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, bool need_bwd, Plan* pl,
-                      bool smooth = false, bool ls = false) {
+                      bool smooth = false, bool ls = false, bool lean = false) {
   if (!c || !g) return WECT_ERR_ARG;
   if (c->kind != WECT_SIMPLICIAL && c->kind != WECT_CUBICAL) return WECT_ERR_ARG;
   if (c->B < 1) return WECT_ERR_ARG;
@@ -398,7 +400,16 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->dsum_bytes = pl->split ? align256((size_t)groups * slot_bytes) : 0;
     const bool absmax = acc_bytes == 8 && c->wmode != WECT_W_ONES;  // unit weights: M = 1
     pl->absmax_bytes = absmax ? align256(wect::kAbsmaxSlots * sizeof(float)) : 0;
-    pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes;
+    // Cubical: when every voxel would be staged more than once (several
+    // direction or threshold tiles), its combined weights are formed once per
+    // call into per-voxel records (8 or 16 bytes per voxel of workspace) and
+    // the forward stages records instead of neighbourhoods.  Not in lean plans
+    // (the workspace then stays at the partial histograms).
+    const int64_t reuse = (int64_t)ntiles * ceil_div(g->T, tt_fwd);
+    const int rec_knob = g_rec.load();
+    if (c->kind == WECT_CUBICAL && !lean && rec_knob != 1 && (reuse >= 2 || rec_knob == 2))
+      pl->rec_bytes = align256((size_t)c->total_voxels * (c->n == 3 ? 16 : 8));
+    pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes + pl->rec_bytes;
     p.nabsmax = absmax ? wect::kAbsmaxSlots : 0;
     p.cells_total = (double)std::max<int64_t>(cells, 1);
   }
@@ -472,6 +483,7 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   p.split = pl.split ? 1 : 0;
   p.absmax = pl.absmax_bytes ? reinterpret_cast<float*>(w8 + pl.partial_bytes + pl.dsum_bytes) : nullptr;
   p.vbuckets = pl.vb_bytes ? w8 + pl.partial_bytes + pl.dsum_bytes + pl.absmax_bytes : nullptr;
+  p.cub_rec = pl.rec_bytes ? w8 + pl.partial_bytes + pl.dsum_bytes + pl.absmax_bytes : nullptr;
   p.G = pl.G_fwd;
   p.S = pl.S_fwd;
   p.stage = pl.stage_fwd;
@@ -479,6 +491,9 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   const bool prof = g_profile.load() != 0;
   if (p.nabsmax > 0) {
     if (hipError_t e = wect::launch_absmax(p, s); e != hipSuccess) return device_error(e, "abs-max kernel");
+  }
+  if (p.cub_rec && p.S > 0) {
+    if (hipError_t e = wect::launch_cub_records(p, s); e != hipSuccess) return device_error(e, "voxel records kernel");
   }
   for (int q0 = 0; q0 < Tfull; q0 += pl.tt_fwd) {
     p.T = std::min(pl.tt_fwd, Tfull - q0);
@@ -792,6 +807,20 @@ wect_status ecf_plan(const wect_complex* c, int32_t T, const float* thr, EcfPlan
 
 namespace wect {
 void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
+size_t workspace_bytes_lean(const wect_complex* c, const wect_grid* g) {
+  Plan pl;
+  if (make_plan(c, g, true, false, &pl, false, false, true) != WECT_OK) return 0;
+  return pl.ws_fwd;
+}
+
+wect_status forward_lean(const wect_complex* c, const wect_grid* g, void* out, void* ws, size_t ws_bytes,
+                         void* hip_stream) {
+  Plan pl;
+  wect_status st = make_plan(c, g, true, false, &pl, false, false, true);
+  if (st != WECT_OK) return st;
+  return run_forward(pl, out, ws, ws_bytes, (hipStream_t)hip_stream);
+}
 }  // namespace wect
 
 extern "C" {
@@ -882,6 +911,8 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (l->decomposition < 0 || l->decomposition > 2) return WECT_ERR_ARG;
   if (l->threshold_tile < 0) return WECT_ERR_ARG;
   if (l->directions_per_lane < 0 || l->directions_per_lane > 2) return WECT_ERR_ARG;
+  if (l->cubical_records < 0 || l->cubical_records > 2) return WECT_ERR_ARG;
+  g_rec.store(l->cubical_records);
   g_decomp.store(l->decomposition);
   g_ttile.store(l->threshold_tile);
   g_dpl.store(l->directions_per_lane);
@@ -899,6 +930,7 @@ wect_status wect_get_launch(wect_launch* l) {
   l->decomposition = g_decomp.load();
   l->threshold_tile = g_ttile.load();
   l->directions_per_lane = g_dpl.load();
+  l->cubical_records = g_rec.load();
   return WECT_OK;
 }
 

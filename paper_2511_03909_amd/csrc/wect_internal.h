@@ -31,6 +31,7 @@ struct Params {
   const int64_t* axis_off;
   int64_t total_voxels;
   int32_t include_above;
+  void* cub_rec;         // cubical: per-voxel records of combined weights (k_cub_records), or null
   // sampling grid
   const float* dirs;
   int32_t d, T;          // T: thresholds of this launch (one tile of the request's thresholds)
@@ -86,6 +87,9 @@ hipError_t launch_forward_main(const Params& p, int block, size_t lds_bytes, hip
 // the two kinds of forward main kernel, which launch_forward_main dispatches to
 hipError_t launch_forward_simp(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 hipError_t launch_forward_cub(const Params& p, int block, size_t lds_bytes, hipStream_t s);
+// Per-voxel records of the cubical forward (p.cub_rec, total_voxels entries of
+// 8 (n = 2) or 16 (n = 3) bytes).
+hipError_t launch_cub_records(const Params& p, hipStream_t s);
 hipError_t launch_forward_reduce(const Params& p, hipStream_t s);
 hipError_t launch_backward_main(const Params& p, int block, size_t lds_bytes, hipStream_t s);
 // Adjoint of the sigmoid relaxation (p.G blocks over p.S = ntiles * cells).
@@ -132,6 +136,19 @@ constexpr int kAbsmaxSlots = 256;  // 64 blocks x 4 weight arrays
 
 // Records the description returned by wect_last_error() on the calling thread.
 void set_last_error(const char* msg);
+
+}  // namespace wect
+
+#include "wect.h"
+
+namespace wect {
+
+// wect_workspace_bytes(c, g, 0) / wect_forward for a plan whose workspace holds
+// the partial histograms only (no per-voxel records of the cubical forward):
+// the allocation-free entry point's plan.
+size_t workspace_bytes_lean(const wect_complex* c, const wect_grid* g);
+wect_status forward_lean(const wect_complex* c, const wect_grid* g, void* out, void* ws, size_t ws_bytes,
+                         void* hip_stream);
 
 // Validation flags (bit set = failure).
 enum : int { kFlagIndex = 1, kFlagThr = 2, kFlagNonfinite = 4 };

@@ -1,8 +1,10 @@
 // wect_forward_noalloc: the forward with its workspace in a static device
 // array, for callers that cannot allocate device memory.
 //
-// The forward's workspace (partial histograms of blocks that share a group,
-// their sums, the per-block maxima of |w| for float weights) lives here in a
+// The forward is planned without the per-voxel records of the cubical
+// forward, so its workspace (partial histograms of blocks that share a group,
+// their sums, the per-block maxima of |w| for float weights) stays small; it
+// lives here in a
 // file-scope device array of kScratchBytes.  Its device address is looked up
 // once per device, with that device current, and kept per device: in host
 // code the array's name is only a host-side stand-in.  Every call on one GPU
@@ -55,7 +57,7 @@ extern "C" {
 
 wect_status wect_forward_noalloc(const wect_complex* c, const wect_grid* g, void* out, void* hip_stream) {
   if (!c || !g) return WECT_ERR_ARG;
-  const size_t need = wect_workspace_bytes(c, g, 0);
+  const size_t need = wect::workspace_bytes_lean(c, g);
   hipError_t err = hipSuccess;
   void* ws = scratch_address(&err);
   if (!ws) {
@@ -71,7 +73,7 @@ wect_status wect_forward_noalloc(const wect_complex* c, const wect_grid* g, void
     wect::set_last_error(msg);
     return WECT_ERR_WORKSPACE;
   }
-  return wect_forward(c, g, out, ws, kScratchBytes, hip_stream);
+  return wect::forward_lean(c, g, out, ws, kScratchBytes, hip_stream);
 }
 
 }  // extern "C"

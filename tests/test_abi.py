@@ -208,8 +208,8 @@ def test_two_directions_per_lane_doubles_the_slot_width(lib):
     g = _grid(d=130, T=40)
     try:
         sizes = {}
-        for dpl in (1, 2):
-            assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, dpl))) == L.WECT_OK
+        for dpl in (1, 2):  # without the per-voxel records
+            assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, dpl, 1))) == L.WECT_OK
             sizes[dpl] = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
         # partial slots (blocks + groups) and slot sums (groups), each T x 64 dpl x 4 bytes; blocks of at
         # least 64 stream items (tiles x voxels), at most 256 (one per compute unit without a device)
@@ -222,6 +222,31 @@ def test_two_directions_per_lane_doubles_the_slot_width(lib):
             assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, dpl))) == L.WECT_OK
             per.append(lib.wect_workspace_bytes(ctypes.byref(s), ctypes.byref(g), 0))
         assert per[0] == per[1]
+    finally:
+        lib.wect_set_launch(ctypes.byref(before))
+
+
+def test_cubical_records_add_16_bytes_per_voxel(lib):
+    """3D cubical forward with 130 directions (two tiles of 128): the voxel
+    records (16 bytes per voxel) are on by default and add exactly their size
+    to the workspace; off, or with one tile of directions, they are not
+    there."""
+    before = L.WectLaunch()
+    lib.wect_get_launch(ctypes.byref(before))
+    c = L.WectComplex()
+    c.kind, c.n, c.B, c.wmode, c.dtype = L.WECT_CUBICAL, 3, 1, L.WECT_W_VERTEX_MAX, L.WECT_I32
+    c.shape, c.axis, c.intensity, c.total_voxels = FAKE, FAKE, FAKE, 5000
+    try:
+        ws = {}
+        for rec in (0, 1, 2):
+            assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, rec))) == L.WECT_OK
+            ws[rec] = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(_grid(d=130, T=40)), 0)
+        assert ws[0] == ws[2] == ws[1] + (5000 * 16 + 255) // 256 * 256
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 0))) == L.WECT_OK
+        one = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(_grid(d=64, T=40)), 0)
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 1))) == L.WECT_OK
+        assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(_grid(d=64, T=40)), 0) == one
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 3))) == L.WECT_ERR_ARG
     finally:
         lib.wect_set_launch(ctypes.byref(before))
 

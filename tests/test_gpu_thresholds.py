@@ -201,9 +201,10 @@ def test_wecf_many_thresholds(W):
 @pytest.mark.parametrize("d", [65, 128, 130, 300])
 def test_two_directions_per_lane_cubical(W, d):
     """The cubical forward with a tile of 128 directions (two histogram columns
-    per lane) gives the bits of one direction per lane, on images and volumes
-    of uneven shapes with an empty member, in both decompositions, also with
-    threshold tiles; and matches the oracle."""
+    per lane) and with per-voxel records staged instead of neighbourhoods gives
+    the bits of the plain kernel, on images and volumes of uneven shapes with
+    an empty member, in both decompositions, also with threshold tiles; and
+    matches the oracle."""
     ims = [synth.random_tiny_cubical(s, shp, include_above=70) for s, shp in
            enumerate(((21, 9), (3, 17), (40, 33), (8, 8)))]
     ims.insert(1, synth.Cubical(np.zeros((5, 6), np.uint8), [synth.cubical_axis(6), synth.cubical_axis(5)], 70, True))
@@ -215,11 +216,14 @@ def test_two_directions_per_lane_cubical(W, d):
             for dec in (1, 2):
                 for tt in (0, 16):
                     res = []
-                    for dpl in (1, 2):
-                        _say(f"cubical n={batch[0].n} d={d} decomposition={dec} tile={tt} directions/lane={dpl}")
-                        W.set_launch(decomposition=dec, threshold_tile=tt, directions_per_lane=dpl)
+                    for dpl, rec in ((1, 1), (2, 1), (1, 2), (2, 2)):
+                        _say(f"cubical n={batch[0].n} d={d} decomposition={dec} tile={tt} directions/lane={dpl} "
+                             f"records={rec}")
+                        W.set_launch(decomposition=dec, threshold_tile=tt, directions_per_lane=dpl,
+                                     cubical_records=rec)
                         res.append(gpu_wect(W, batch, dirs, thr))
-                    assert np.array_equal(res[0], res[1])
+                    for r in res[1:]:
+                        assert np.array_equal(res[0], r)
             for b, C in enumerate(batch):
                 assert_match(res[1][b], oracle.wect(C, dirs, thr), C, f"d={d} complex {b}")
     finally:
