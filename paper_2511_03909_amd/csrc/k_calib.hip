@@ -12,12 +12,22 @@
 
 namespace {
 
-// 16-byte loads and stores, grid-stride; a tail of fewer than 16 bytes is
-// copied byte by byte by the first thread.
+// 16-byte loads and stores, four per thread in flight (each thread copies
+// elements i, i + s, i + 2s, i + 3s of a grid-stride step of 4s), then the
+// remainder one at a time; a tail of fewer than 16 bytes is copied byte by
+// byte by the first thread.
 __global__ __launch_bounds__(256) void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16,
                                               unsigned char* dtail, const unsigned char* stail, int ntail) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+  const size_t s = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * s < n16; i += 4 * s) {
+    const uint4 a = src[i], b = src[i + s], c = src[i + 2 * s], d = src[i + 3 * s];
+    dst[i] = a;
+    dst[i + s] = b;
+    dst[i + 2 * s] = c;
+    dst[i + 3 * s] = d;
+  }
+  for (; i < n16; i += s) dst[i] = src[i];
   if (blockIdx.x == 0 && threadIdx.x == 0)
     for (int k = 0; k < ntail; ++k) dtail[k] = stail[k];
 }
@@ -57,8 +67,8 @@ wect_status wect_calib_copy(void* dst, const void* src, size_t bytes, void* hip_
     return WECT_ERR_ARG;
   const size_t n16 = bytes / 16;
   const int ntail = (int)(bytes - n16 * 16);
-  size_t blocks = (n16 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  size_t blocks = (n16 + 1023) / 1024;  // about four elements per thread
+  if (blocks > 16384) blocks = 16384;
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, (uint4*)dst,
                      (const uint4*)src, n16, (unsigned char*)dst + n16 * 16, (const unsigned char*)src + n16 * 16,

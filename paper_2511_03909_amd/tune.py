@@ -10,9 +10,8 @@ per compute unit and a larger staging area, at the price of re-reading the
 cells).  Results are cached in a JSON file keyed by a signature of the request
 (kind, ambient dimension, batch size, total cells rounded to a power of two,
 directions, thresholds, dtype), so a workload of the same shape reuses the
-choice.
-
-The direction tile is one wavefront (64 directions, one per lane).
+choice.  Last, for cubical requests with more than 64 directions, it times one
+and two directions per lane (a direction tile of 64 or 128).
 
     from paper_2511_03909_amd import tune
     shape = tune.tune(cx, grid)        # times, caches, applies
@@ -72,7 +71,8 @@ def _save(path: str, data: Dict[str, dict]) -> None:
 def apply(shape: Optional[dict]) -> None:
     if shape:
         api.set_launch(shape["block"], shape["blocks_per_cu"], shape["min_items_per_block"],
-                       shape.get("decomposition", 0), shape.get("threshold_tile", 0))
+                       shape.get("decomposition", 0), shape.get("threshold_tile", 0),
+                       shape.get("directions_per_lane", 0))
     else:
         api.set_launch()
 
@@ -83,6 +83,14 @@ def tile_candidates(T: int) -> Tuple[int, ...]:
     if T < 96:
         return (0,)
     return (0, -(-T // 2), -(-T // 3))
+
+
+def lane_candidates(cx, grid) -> Tuple[int, ...]:
+    """Directions per lane tried for cubical requests with more than one
+    64-direction tile (automatic is 2 there): 1 and 2."""
+    if isinstance(cx, api.CubicalBatch) and grid.d > 64:
+        return (1, 2)
+    return ()
 
 
 def lookup(cx, grid, cache: str = DEFAULT_CACHE) -> Optional[dict]:
@@ -109,26 +117,31 @@ def tune(cx, grid, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES,
     before = api.get_launch()
     results = []
 
-    def run(block, bpc, mi, dec, tt):
-        api.set_launch(block, bpc, mi, dec, tt)
+    def run(block, bpc, mi, dec, tt, dpl):
+        api.set_launch(block, bpc, mi, dec, tt, dpl)
         t1 = _time_forward(cx, grid, 1)
         r = reps or max(2, min(50, int(0.05 / max(t1, 1e-6))))
-        results.append((_time_forward(cx, grid, r), block, bpc, mi, dec, tt))
+        results.append((_time_forward(cx, grid, r), block, bpc, mi, dec, tt, dpl))
 
     try:
         for block, bpc, mi, dec in candidates:
-            run(block, bpc, mi, dec, 0)
-        _, block, bpc, mi, dec, _ = min(results)
+            run(block, bpc, mi, dec, 0, 0)
+        _, block, bpc, mi, dec, _, _ = min(results)
         for tt in tile_candidates(grid.T)[1:]:
-            run(block, bpc, mi, dec, tt)
+            run(block, bpc, mi, dec, tt, 0)
+        _, block, bpc, mi, dec, tt, _ = min(results)
+        for dpl in lane_candidates(cx, grid):
+            run(block, bpc, mi, dec, tt, dpl)
     finally:
         api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"],
-                       before["decomposition"], before["threshold_tile"])
-    t, block, bpc, mi, dec, tt = min(results)
+                       before["decomposition"], before["threshold_tile"], before["directions_per_lane"],
+                       before["cubical_records"])
+    t, block, bpc, mi, dec, tt, dpl = min(results)
     best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "decomposition": dec,
-            "threshold_tile": tt, "ms": t * 1e3,
+            "threshold_tile": tt, "directions_per_lane": dpl, "ms": t * 1e3,
             "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "decomposition": e,
-                       "threshold_tile": x, "ms": s * 1e3} for s, b, c, m, e, x in results]}
+                       "threshold_tile": x, "directions_per_lane": y, "ms": s * 1e3}
+                      for s, b, c, m, e, x, y in results]}
     if cache:
         data = _load(cache)
         data[signature(cx, grid)] = best

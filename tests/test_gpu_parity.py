@@ -538,7 +538,7 @@ def test_autotuner_caches_and_keeps_results(W, tmp_path):
         assert tune.lookup(cx, g, cache) is not None
         # four shapes, then the threshold tiles with the fastest of them
         assert best["block"] in (256, 512, 1024)
-        assert len(best["tried"]) == 4 + len(tune.tile_candidates(g.T)) - 1
+        assert len(best["tried"]) == 4 + len(tune.tile_candidates(g.T)) - 1 + len(tune.lane_candidates(cx, g))
         assert best["threshold_tile"] in tune.tile_candidates(g.T)
         assert np.array_equal(W.wect_forward(cx, g).cpu().numpy(), ref)
     finally:
