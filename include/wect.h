@@ -120,13 +120,6 @@ typedef struct {
   int64_t total_voxels;             /* sum of n0*n1*n2 over the batch */
   int32_t include_above;            /* voxel is a vertex iff intensity > include_above (-1: all) */
   int32_t reserved;
-
-  /* ---- optional (simplicial): region index of this topology written by
-          wect_region_build, or NULL.  When set, the forward of wect_forward,
-          wect_forward_noalloc and wect_batched reads the cells region by
-          region (same results, same bits); the adjoint does not use it. ---- */
-  const void* cell_index;
-  size_t cell_index_bytes;
 } wect_complex;
 
 /* Sampling grid of the transform: d directions s_p (rows, used as stored,
@@ -393,43 +386,6 @@ wect_status wect_smooth_ls_backward(const wect_complex* c, const wect_grid* g, f
                                     size_t index_bytes, const float* grad_out, float* grad_coords,
                                     float* grad_dirs, float* const grad_w[4], float* grad_vertex,
                                     void* hip_stream);
-
-/*
- * Region index of a simplicial complex (or CSR batch) for the forward.  A
- * cell's threshold index is the largest of its vertices' indices (the index is
- * monotone, as in the correctness proof of Algorithm 1), so the index of a
- * vertex can be computed once and shared by every cell that contains it.
- * Region k of complex b owns its vertices k R .. k R + R - 1 (local ids;
- * R = 64 when top_dim is 3, else 384) and holds every cell whose lowest vertex
- * it owns; the other vertices of those cells are the region's halo.  Per
- * region and direction tile the forward computes the threshold index of each
- * owned and halo vertex once into an LDS table, then reads each cell's
- * vertices from it.  Work per cell and direction: one table read per vertex,
- * a maximum and the histogram add, instead of every vertex's height and index.
- *
- * Layout (device memory owned by the caller, sections 256-byte aligned): a
- * header, each complex's first region, per dimension >= 1 the region offsets,
- * the cell rows in region order and each cell's local vertex ids (uint16:
- * owned vertex v -> v - k R, halo vertex -> owned count + its rank among the
- * region's halo vertices in ascending order), and per region its halo (global
- * vertex rows).  Cells of a region are in no fixed order.
- *
- * wect_region_bytes: size of the index for the complex's counts (0 on invalid
- *   metadata).  It depends only on B, the counts and top_dim.
- * wect_region_build: writes the index (at least wect_region_bytes(c) bytes,
- *   256-byte aligned) on `hip_stream`: eight kernels (no allocation), then it
- *   waits for them and reads the build status.  WECT_ERR_UNSUPPORTED when a
- *   region's cells reference more than 16384 vertices above the region or a
- *   region would need more than 65536 local vertices (a mesh whose vertex
- *   numbering has no locality, or vertices of very high degree: use the forward
- *   without the index).  Reads the simplex lists and offsets only, so one build
- *   serves every call on the same topology (coordinates and weights may change);
- *   vertex ids must be valid (wect_validate).  Set wect_complex.cell_index /
- *   cell_index_bytes to use it; an index built for another topology gives
- *   wrong results (reads stay inside the index and the complex's arrays).
- */
-size_t wect_region_bytes(const wect_complex* c);
-wect_status wect_region_build(const wect_complex* c, void* index, size_t index_bytes, void* hip_stream);
 
 /*
  * Synchronous data check on `hip_stream`: CSR offsets and shapes consistent

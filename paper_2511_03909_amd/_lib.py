@@ -28,7 +28,6 @@ class WectComplex(ctypes.Structure):
         ("simplices", c_void_p * 4), ("simp_off", c_void_p * 4), ("weights", c_void_p * 4),
         ("shape", c_void_p), ("grid_off", c_void_p), ("intensity", c_void_p), ("axis", c_void_p),
         ("axis_off", c_void_p), ("total_voxels", c_int64), ("include_above", c_int32), ("reserved", c_int32),
-        ("cell_index", c_void_p), ("cell_index_bytes", c_size_t),
     ]
 
 
@@ -130,10 +129,6 @@ def lib() -> ctypes.CDLL:
     L.wect_smooth_ls_backward.argtypes = [P(WectComplex), P(WectGrid), c_float, c_void_p, c_size_t, c_void_p,
                                           c_void_p, c_void_p, P(c_void_p), c_void_p, c_void_p]
     L.wect_smooth_ls_backward.restype = c_int
-    L.wect_region_bytes.argtypes = [P(WectComplex)]
-    L.wect_region_bytes.restype = c_size_t
-    L.wect_region_build.argtypes = [P(WectComplex), c_void_p, c_size_t, c_void_p]
-    L.wect_region_build.restype = c_int
     _lib = L
     return L
 

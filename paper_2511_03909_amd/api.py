@@ -18,7 +18,7 @@ __all__ = [
     "Grid", "SimplicialBatch", "CubicalBatch", "wect_workspace_bytes", "wect_forward", "wect_backward",
     "wect_batched", "wect_validate", "set_launch", "get_launch", "profile_enable", "profile_read",
     "WECTFunction", "wect", "WECT", "smooth_workspace_bytes", "smooth_forward", "smooth_backward",
-    "SmoothWECTFunction", "smooth_wect", "SmoothWECT", "lower_star_index", "region_index", "wecf_backward",
+    "SmoothWECTFunction", "smooth_wect", "SmoothWECT", "lower_star_index", "wecf_backward",
 ]
 
 _WMODES = {"ones": L.WECT_W_ONES, "explicit": L.WECT_W_EXPLICIT, "vertex_max": L.WECT_W_VERTEX_MAX}
@@ -68,7 +68,6 @@ class SimplicialBatch:
         self.B = int(B)
         self.n = int(coords.shape[1])
         self.device = coords.device
-        self.cell_index = None  # region index of this topology (region_index), used by the forward
         if wmode == "ones":
             self.dtype = L.WECT_I32
         elif wmode == "vertex_max":
@@ -86,7 +85,6 @@ class SimplicialBatch:
     def with_weights(self, weights) -> "SimplicialBatch":
         s = SimplicialBatch(self.coords, self.simplices, self.wmode, list(weights), self.vert_off,
                             self.simp_off, self.B)
-        s.cell_index = self.cell_index  # same topology
         return s
 
     @classmethod
@@ -134,9 +132,6 @@ class SimplicialBatch:
             c.simplices[i] = _ptr(self.simplices[i]) if 1 <= i <= self.top_dim else None
             c.simp_off[i] = _ptr(self.simp_off[i]) if (1 <= i <= self.top_dim and self.simp_off) else None
             c.weights[i] = _ptr(self.weights[i]) if i < len(self.weights) else None
-        if self.cell_index is not None:
-            c.cell_index = _ptr(self.cell_index)
-            c.cell_index_bytes = int(self.cell_index.numel())
         return c
 
 
@@ -551,25 +546,6 @@ def lower_star_index(cx, cache: bool = True) -> torch.Tensor:
             "wect_lower_star_build")
     if cache:
         cx._lower_star = idx
-    return idx
-
-
-def region_index(cx, attach: bool = True) -> torch.Tensor:
-    """Device buffer holding the region index of a simplicial batch (see
-    wect_region_build); with ``attach`` the batch's forward uses it."""
-    saved, cx.cell_index = cx.cell_index, None
-    try:
-        c = cx.struct()
-    finally:
-        cx.cell_index = saved
-    nbytes = int(L.lib().wect_region_bytes(ctypes.byref(c)))
-    if nbytes == 0:
-        raise L.WectError(L.WECT_ERR_ARG, "wect_region_bytes")
-    idx = torch.empty(nbytes, dtype=torch.uint8, device=cx.device)
-    L.check(L.lib().wect_region_build(ctypes.byref(c), _ptr(idx), ctypes.c_size_t(nbytes), _stream(cx.device)),
-            "wect_region_build")
-    if attach:
-        cx.cell_index = idx
     return idx
 
 

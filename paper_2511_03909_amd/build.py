@@ -23,7 +23,7 @@ ARCH = "gfx950"
 
 # kernel translation units are compiled in parallel, then linked with the host runtime
 SOURCES = ["k_simp_fwd.hip", "k_cub_fwd.hip", "k_reduce.hip", "k_simp_bwd.hip", "k_smooth_bwd.hip",
-           "k_lower_star.hip", "k_region.hip", "k_image.hip", "wect_static.hip", "k_calib.hip", "wect_api.cpp"]
+           "k_lower_star.hip", "k_image.hip", "wect_static.hip", "k_calib.hip", "wect_api.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

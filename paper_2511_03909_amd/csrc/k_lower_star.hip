@@ -24,6 +24,19 @@ namespace {
 // through per-vertex cursors.  The order of a vertex's entries follows the
 // atomics; no result depends on it.
 
+// complex of simplex row r of dimension dim: largest b with simp_off[dim][b] <= r
+__device__ __forceinline__ int complex_of_row(const Params& p, int dim, int64_t r) {
+  const int64_t* so = p.simp_off[dim];
+  if (!so) return 0;
+  int lo = 0, hi = p.B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (so[mid] <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Global rows of the dim+1 vertices of simplex (dim, r); entries past dim are 0.
 __device__ __forceinline__ void simplex_rows(const Params& p, int dim, int64_t r, int32_t (&g)[4]) {
   const int b = complex_of_row(p, dim, r);

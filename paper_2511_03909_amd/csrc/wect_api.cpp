@@ -198,23 +198,6 @@ int choose_tile(int T, FMin fits_min, FGood fits_good) {
   return balanced_tile(T, tmax);
 }
 
-// Rows of the region forward's table of vertex threshold indices that fit
-// LDS next to the histogram of T thresholds and `chunk` staged cells (a
-// multiple of 64, at most 1024), and the rows a region typically needs: its
-// R owned vertices plus a halo of about one more row of vertices in a 2D
-// mesh, three in a 3D one.
-int rg_cap(int T, int acc_bytes, int chunk) {
-  const size_t fixed = wect::region_forward_lds_bytes(T, 0, chunk, acc_bytes);
-  if (fixed >= kLdsLimit) return 0;
-  const size_t per_row = wect::region_forward_lds_bytes(T, 1, chunk, acc_bytes) - fixed;
-  const int cap = (int)std::min<size_t>(1024, (kLdsLimit - fixed) / per_row) / 64 * 64;
-  return cap;
-}
-int rg_rows_wanted(int top_dim) {
-  const int R = wect::region_size(top_dim);
-  return top_dim >= 3 ? 4 * R : 2 * R + 64;
-}
-
 // Check host metadata and build the plan.  need_bwd: backward requested.
 // smooth: forward of the sigmoid relaxation (fixed-point accumulation for
 // every weight mode, float32 output); its adjoint is planned by smooth_plan.
@@ -300,17 +283,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     elems = c->total_voxels;
   }
   const int64_t cells = elems;
-  const int64_t elems_bwd = elems;  // the adjoint streams cells
-  // Region index attached: the forward's stream runs over vertices (a block
-  // takes the regions whose first vertex it holds); the adjoint is unchanged.
-  const bool rg = need_fwd && !smooth && !ls && c->kind == WECT_SIMPLICIAL && c->cell_index != nullptr;
-  wect::RgLayout rgl{};
-  if (rg) {
-    rgl = wect::rg_layout(c->B, c->count[0], c->count, c->top_dim);
-    if (c->cell_index_bytes < rgl.total || (reinterpret_cast<uintptr_t>(c->cell_index) & 255)) return WECT_ERR_ARG;
-    wect::rg_bind(p, const_cast<void*>(c->cell_index), rgl);
-  }
-  if (ls || rg) elems = c->count[0];  // vertex-centric and region kernels: one stream element per vertex
+  if (ls) elems = c->count[0];  // vertex-centric kernels: one stream element per vertex
   if (need_bwd) {
     if (c->kind != WECT_SIMPLICIAL) return WECT_ERR_UNSUPPORTED;
     if (c->dtype != WECT_F32 || c->wmode == WECT_W_ONES) return WECT_ERR_ARG;
@@ -344,7 +317,6 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     const int acc_bytes = acc_bytes_of(c, smooth);
     const size_t entry = wect::forward_entry_bytes(c->kind, c->n);
     auto fits_stage = [&](int t, size_t nst) {
-      if (rg) return t <= 256 && rg_cap(t, acc_bytes, 256) >= rg_rows_wanted(c->top_dim);
       return ls ? wect::smooth_ls_forward_lds_bytes(t, 256) <= kLdsLimit
                 : wect::forward_lds_fixed(t, c->kind, acc_bytes, dpl) + nst * entry <= kLdsLimit;
     };
@@ -365,9 +337,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   const bool auto_group = need_fwd && decomp == 0 && g->T > 0 && S_fwd > 0 && groups_fwd >= cus &&
                           S_fwd >= groups_fwd * 8 * 1024;
   int block = g_block.load();
-  if (rg) {
-    if (!block) block = 1024;
-  } else if (ls) {
+  if (ls) {
     // the coface rows of the vertex-centric kernels grow with the block:
     // at most the largest block that fits, also for a block set by the caller
     const int fit = ls_block(tt_fwd, false);
@@ -396,25 +366,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     const int acc_bytes = acc_bytes_of(c, smooth);
     int stage = 0;
     size_t lds = 0;
-    if (rg) {  // the table of vertex threshold indices, then each wavefront's staged batch
-      // the largest batch (cells per wavefront) that leaves the table its
-      // wanted rows, else 16 cells and whatever table fits
-      const int nwaves = block / kW;
-      int wb = 16, cap = rg_cap(tt_fwd, acc_bytes, nwaves * 16);
-      for (int b : {64, 48, 32, 24}) {
-        const int cp = rg_cap(tt_fwd, acc_bytes, nwaves * b);
-        if (cp >= rg_rows_wanted(c->top_dim)) {
-          wb = b;
-          cap = cp;
-          break;
-        }
-      }
-      if (cap < 64) return WECT_ERR_UNSUPPORTED;
-      p.rg_cap = cap;
-      p.rg_chunk = wb;
-      stage = wb;
-      lds = wect::region_forward_lds_bytes(tt_fwd, cap, nwaves * wb, acc_bytes);
-    } else if (ls) {  // per-wavefront coface rows instead of a block staging tile
+    if (ls) {  // per-wavefront coface rows instead of a block staging tile
       stage = block;
       lds = wect::smooth_ls_forward_lds_bytes(tt_fwd, block);
       if (lds > kLdsLimit) stage = 0;
@@ -481,7 +433,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     pl->ngd = (int)ceil_div(ntiles, dg);
     pl->stage_bwd = stage;
     pl->lds_bwd = wect::backward_lds_bytes(tt, stage, dg);
-    const int64_t S = (int64_t)pl->ngd * elems_bwd;
+    const int64_t S = (int64_t)pl->ngd * elems;
     const int64_t max_blocks = (int64_t)cus * blocks_per_cu(pl->lds_bwd);
     int64_t G = std::min<int64_t>(max_blocks, std::max<int64_t>(1, ceil_div(S, min_items)));
     G = std::min<int64_t>(G, std::max<int64_t>(S, 1));
@@ -554,9 +506,8 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
     if (p.S > 0) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (prof && record(&e0, s) != hipSuccess) return WECT_ERR_DEVICE;
-      const hipError_t le = p.rg   ? wect::launch_region_forward(p, pl.block, pl.lds_fwd, s)
-                            : p.ls ? wect::launch_smooth_ls_forward(p, pl.block, pl.lds_fwd, s)
-                                   : wect::launch_forward_main(p, pl.block, pl.lds_fwd, s);
+      const hipError_t le = p.ls ? wect::launch_smooth_ls_forward(p, pl.block, pl.lds_fwd, s)
+                                 : wect::launch_forward_main(p, pl.block, pl.lds_fwd, s);
       if (le != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
         return device_error(le, "forward kernel");
@@ -587,7 +538,6 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
   } else {
     for (int i = 0; i < 4; ++i) p.grad_w[i] = grad_w ? grad_w[i] : nullptr;
   }
-  p.rg = 0;  // the adjoint streams cells (a region index serves the forward only)
   p.dg = pl.dg;
   p.ngroups_dir = pl.ngd;
   p.G = pl.G_bwd;
@@ -655,7 +605,6 @@ wect_status wecf_plan(const wect_complex* c, const float* fvals, int32_t m, cons
   wect_complex cc = *c;
   cc.n = 1;
   cc.coords = &kStandIn;
-  cc.cell_index = nullptr;  // the region forward is for height filters only
   const wect_grid gg = {&kStandIn, m, T, (thr || !sizing) ? thr : &kStandIn};
   if (wect_status st = make_plan(&cc, &gg, !bwd, bwd, pl); st != WECT_OK) return st;
   pl->p.n = 0;
@@ -1127,54 +1076,6 @@ wect_status wect_lower_star_build(const wect_complex* c, void* index, size_t ind
   wect::ls_bind(pl.p, index, L);
   if (hipError_t e = wect::launch_lower_star_build(pl.p, L, static_cast<hipStream_t>(hip_stream)); e != hipSuccess)
     return device_error(e, "lower-star index build");
-  return WECT_OK;
-}
-
-// Region index: layout from host counts (the topology's metadata must be valid).
-wect_status rg_check(const wect_complex* c, wect::RgLayout* L) {
-  if (!c || c->kind != WECT_SIMPLICIAL) return WECT_ERR_ARG;
-  wect_complex cc = *c;
-  cc.cell_index = nullptr;
-  const wect_grid g0 = {nullptr, 0, 0, nullptr};
-  Plan pl;
-  if (wect_status st = make_plan(&cc, &g0, false, false, &pl); st != WECT_OK) return st;
-  for (int i = 1; i <= c->top_dim; ++i)
-    if (c->count[i] > INT32_MAX) return WECT_ERR_UNSUPPORTED;  // cell rows are stored as int32
-  *L = wect::rg_layout(c->B, c->count[0], c->count, c->top_dim);
-  return WECT_OK;
-}
-
-size_t wect_region_bytes(const wect_complex* c) {
-  wect::RgLayout L;
-  if (rg_check(c, &L) != WECT_OK) return 0;
-  return L.total;
-}
-
-wect_status wect_region_build(const wect_complex* c, void* index, size_t index_bytes, void* hip_stream) {
-  wect::RgLayout L;
-  if (wect_status st = rg_check(c, &L); st != WECT_OK) return st;
-  if (!index || index_bytes < L.total || (reinterpret_cast<uintptr_t>(index) & 255)) return WECT_ERR_ARG;
-  wect_complex cc = *c;
-  cc.cell_index = nullptr;
-  const wect_grid g0 = {nullptr, 0, 0, nullptr};
-  Plan pl;
-  if (wect_status st = make_plan(&cc, &g0, false, false, &pl); st != WECT_OK) return st;
-  wect::rg_bind(pl.p, index, L);
-  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (hipError_t e = wect::launch_region_build(pl.p, L, s); e != hipSuccess)
-    return device_error(e, "region index build");
-  int64_t hdr[4] = {0, 0, 0, 0};
-  if (hipError_t e = hipMemcpyAsync(hdr, pl.p.rg_hdr, sizeof(hdr), hipMemcpyDeviceToHost, s); e != hipSuccess)
-    return device_error(e, "region index status");
-  if (hipError_t e = hipStreamSynchronize(s); e != hipSuccess) return device_error(e, "region index build");
-  if (hdr[2] != 0) {
-    snprintf(g_last_error, sizeof(g_last_error),
-             "region index: %s (largest halo %lld vertices)",
-             (hdr[2] & 1) ? "a region references more than 16384 vertices above it"
-                          : "a region needs more than 65536 local vertices",
-             (long long)hdr[3]);
-    return WECT_ERR_UNSUPPORTED;
-  }
   return WECT_OK;
 }
 

@@ -466,7 +466,7 @@ __device__ __forceinline__ float sum_scatter8(const float (&v)[8]) {
 // Number of stream elements (cells handled one by one) of the complexes
 // before complex b: all simplices of all dimensions, or all voxels.
 __device__ __forceinline__ int64_t cum_elems(const Params& p, int b) {
-  if (p.ls || p.rg) {  // vertex-centric and region kernels: one stream element per vertex
+  if (p.ls) {  // vertex-centric kernels: one stream element per vertex
     if (!p.vert_off) return b == 0 ? 0 : p.count[0];
     return p.vert_off[b];
   }
@@ -495,19 +495,6 @@ __device__ __forceinline__ int find_complex(const Params& p, int64_t pos, int gp
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if ((int64_t)gpc * cum_elems(p, mid) <= pos) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// complex of simplex row r of dimension dim: largest b with simp_off[dim][b] <= r
-__device__ __forceinline__ int complex_of_row(const Params& p, int dim, int64_t r) {
-  const int64_t* so = p.simp_off[dim];
-  if (!so) return 0;
-  int lo = 0, hi = p.B - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (so[mid] <= r) lo = mid;
     else hi = mid - 1;
   }
   return lo;

@@ -76,24 +76,6 @@ struct Params {
   int64_t* ls_row;               // [entries]: the coface's row within its dimension
   uint32_t* ls_mask;             // [entries]: the coface's other vertices as bits over the vertex's edges
   int32_t* ls_nbc;               // [V]: the vertex's edge count when every coface maps to bits, else -1
-  // region index (simplicial forward through per-region tables of vertex
-  // threshold indices): the stream runs over vertices, a block takes the
-  // regions whose first vertex lies in its range
-  int32_t rg;                    // 1: cells are read region by region from the index
-  int32_t rg_R;                  // vertices owned by a region (the last one of a complex may own fewer)
-  int32_t rg_cap;                // forward: rows of the LDS table of threshold indices
-  int32_t rg_chunk;              // forward: cells per wavefront batch
-  int64_t rg_nrmax;              // bound on the number of regions: ceil(V / R) + B
-  int64_t* rg_hdr;               // [8]: [0] R, [1] regions, [2] build status bits, [3] largest halo
-  int64_t* rg_reg;               // [B+1] first region of each complex
-  int64_t* rg_coff[4];           // [nrmax+1] per dimension >= 1: each region's first cell in region order
-  int64_t* rg_cnt;               // build: [4][nrmax+1] counts, then fill cursors ([0]: halo reference counts)
-  int32_t* rg_perm[4];           // [count[i]]: row (within dimension i) of each cell in region order
-  void* rg_rec[4];               // [count[i]]: local vertex ids as uint16 (edges: 2, triangles and tetrahedra: 4,
-                                 // the third repeated for triangles)
-  int64_t* rg_hoff;              // [nrmax+1] start of each region's halo list (room for every reference)
-  int32_t* rg_hcnt;              // [nrmax] halo vertices of each region
-  int32_t* rg_halo;              // global rows of each region's halo vertices, ascending
 };
 
 // Sigmoid terms with |lam (thr - h)| > kSmoothW are taken as 0 (below) or 1
@@ -142,23 +124,6 @@ hipError_t launch_smooth_ls_backward(const Params& p, int block, size_t lds_byte
 size_t smooth_ls_forward_lds_bytes(int T, int block);
 size_t smooth_ls_backward_lds_bytes(int T, int block);
 constexpr int kLsChunk = 8192;  // elements per block of the build's scan
-
-// Region index: cells grouped by the region of their lowest vertex, a region
-// being R consecutive vertices of one complex plus the other vertices its
-// cells use (its halo), each cell stored as local vertex ids (uint16).
-struct RgLayout {
-  size_t hdr, reg, coff[4], cnt, perm[4], rec[4], hoff, hcnt, halo, total;
-  int64_t nrmax, nhalo;
-  int R;
-};
-int region_size(int top_dim);
-RgLayout rg_layout(int B, int64_t V, const int64_t count[4], int top_dim);
-void rg_bind(Params& p, void* base, const RgLayout& L);
-hipError_t launch_region_build(const Params& p, const RgLayout& L, hipStream_t s);
-hipError_t launch_region_forward(const Params& p, int block, size_t lds_bytes, hipStream_t s);
-size_t region_forward_lds_bytes(int T, int cap, int chunk, int acc_bytes);
-constexpr int kRgCand = 16384;    // halo references a region may have (sorted in LDS by the build)
-constexpr int kRgMaxLocal = 65535;  // local vertex ids are uint16
 
 // LDS bytes of the forward kernels: fixed part (histogram, thresholds) plus
 // forward_entry_bytes per staged entry; of the backward kernel in total.

@@ -397,44 +397,6 @@ def test_lower_star_metadata(lib):
                                        None, None) == L.WECT_ERR_ARG
 
 
-def _region_layout_bytes(B, counts, top_dim):
-    """Size of the region index from its documented layout (include/wect.h)."""
-    a = lambda x: (x + 255) // 256 * 256
-    R = 64 if top_dim >= 3 else 384
-    nrmax = (counts[0] + R - 1) // R + B
-    o = a(64) + a((B + 1) * 8) + a(4 * (nrmax + 1) * 8)
-    for i in range(1, top_dim + 1):
-        o += a((nrmax + 1) * 8) + a(counts[i] * 4) + a(counts[i] * (4 if i == 1 else 8))
-    nhalo = sum(i * counts[i] for i in range(1, top_dim + 1))
-    return o + a((nrmax + 1) * 8) + a(nrmax * 4) + a(max(nhalo, 1) * 4)
-
-
-def test_region_metadata(lib):
-    """The region index: its size follows the documented layout; a missing,
-    short or misaligned index is refused before any launch, by the build and
-    by the forward."""
-    c, g = _simplicial(), _grid()
-    nb = lib.wect_region_bytes(ctypes.byref(c))
-    assert nb == _region_layout_bytes(1, [3, 3, 1], 2)
-    big = _simplicial(top_dim=3)
-    big.count[0], big.count[1], big.count[2], big.count[3] = 1000, 6000, 9000, 4000
-    big.simplices[3] = FAKE
-    assert lib.wect_region_bytes(ctypes.byref(big)) == _region_layout_bytes(1, [1000, 6000, 9000, 4000], 3)
-    assert lib.wect_region_build(ctypes.byref(c), None, nb, None) == L.WECT_ERR_ARG
-    assert lib.wect_region_build(ctypes.byref(c), FAKE, nb - 1, None) == L.WECT_ERR_ARG
-    assert lib.wect_region_build(ctypes.byref(c), FAKE + 16, nb, None) == L.WECT_ERR_ARG  # not 256-aligned
-    cub = L.WectComplex()
-    cub.kind, cub.n, cub.B = L.WECT_CUBICAL, 2, 1
-    assert lib.wect_region_bytes(ctypes.byref(cub)) == 0
-    # the forward with an attached index that is too small or misaligned
-    ws = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0)
-    c.cell_index, c.cell_index_bytes = FAKE, nb - 1
-    assert _fwd(lib, c, g, ws=FAKE, nbytes=max(ws, 16)) == L.WECT_ERR_ARG
-    c.cell_index, c.cell_index_bytes = FAKE + 16, nb
-    assert _fwd(lib, c, g, ws=FAKE, nbytes=max(ws, 16)) == L.WECT_ERR_ARG
-    assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(g), 0) == 0
-
-
 def test_bench_refuses_more_than_one_gpu():
     """bench.py runs on one GPU: --gpus 2 exits with a message, before touching a device."""
     import json
