@@ -567,6 +567,152 @@ def cpu_baseline(w, cells_of):
 
 # ---------------------------------------------------------------------------
 
+# ---------------------------------------------------------------------------
+# profile summaries (profiles/<name>.md and .json) from rocprofv3 output
+# ---------------------------------------------------------------------------
+
+# (profile name, workload, kernel name prefix, source family, roofline key of the --only result)
+PROFILES = (
+    ("cubical_fwd_3d_16vol_64-192_d512_T256", "volumes3d", "k_cub_fwd<3", "cub_fwd", "roofline"),
+    ("cubical_fwd_2d_256x128x128_d64_T128", "images2d", "k_cub_fwd<2", "cub_fwd", "roofline"),
+    ("simplicial_fwd_3d_kuhn64_d256_T256", "kuhn3d", "k_simp_fwd<3", "simp_fwd", "roofline_fwd"),
+    ("simplicial_bwd_3d_kuhn64_d256_T256", "kuhn3d", "k_simp_bwd<3", "simp_bwd", "roofline_bwd"),
+    ("simplicial_fwd_2d_freudenthal_batch64_d128_T128", "diffbatch", "k_simp_fwd<2", "simp_fwd", "roofline_fwd"),
+    ("simplicial_bwd_2d_freudenthal_batch64_d128_T128", "diffbatch", "k_simp_bwd<2", "simp_bwd", "roofline_bwd"),
+)
+SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+               "SQ_WAIT_INST_LDS SQ_ACTIVE_INST_VALU")
+
+
+def profile_commands(w: str) -> dict:
+    """The rocprofv3 runs behind a workload's profiles (REPO = repository root
+    on the GPU machine; outputs under REPO/gpurun_out)."""
+    run = f"python3 -u $REPO/bench.py --only {w}"
+    return {
+        "stats": f"cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/prof_{w} "
+                 f"-o {w} -- {run} --steps 10 --warmup 2",
+        "FETCH_SIZE": f"cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d "
+                      f"$REPO/gpurun_out/pmc_FETCH_SIZE_{w} -o pmc -- {run} --steps 3 --warmup 1 --copy-calibration",
+        "WRITE_SIZE": f"cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d "
+                      f"$REPO/gpurun_out/pmc_WRITE_SIZE_{w} -o pmc -- {run} --steps 3 --warmup 1 --copy-calibration",
+        "sq": f"cd /tmp && rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d $REPO/gpurun_out/pmc_sq_{w} -o pmc "
+              f"-- {run} --steps 3 --warmup 1",
+    }
+
+
+def _csv_rows(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _last_json(path):
+    with open(path) as f:
+        lines = [ln for ln in f.read().splitlines() if ln.startswith("{")]
+    return json.loads(lines[-1])
+
+
+def _kname(full: str) -> str:
+    """A kernel's name without return type, namespaces and argument list."""
+    import re
+    return re.sub(r"\([^()]*\)\s*$", "", full).split("::")[-1]
+
+
+def _counter_means(path: str, prefix: str) -> tuple:
+    """Per-dispatch mean of every counter of the kernels whose short name
+    starts with prefix, and the number of dispatches."""
+    import collections
+    vals = collections.defaultdict(list)
+    for r in _csv_rows(path):
+        if _kname(r["Kernel_Name"]).startswith(prefix):
+            vals[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    n = max((len(v) for v in vals.values()), default=0)
+    return {k: sum(v) / len(v) for k, v in vals.items()}, n
+
+
+def write_profiles(src: str, bench_log: str) -> None:
+    """Summaries of the rocprofv3 runs in src (profile_commands) and the
+    default bench line in bench_log, for the current kernel sources."""
+    live = _last_json(bench_log)
+    out_dir = os.path.join(ROOT, "profiles")
+    for name, w, prefix, family, key in PROFILES:
+        only = _last_json(os.path.join(src, f"only_{w}.log"))["result"]
+        roof = only[key]
+        cmds = profile_commands(w)
+        stats = _csv_rows(os.path.join(src, f"prof_{w}", f"{w}_kernel_stats.csv"))
+        main_k = [r for r in stats if _kname(r["Name"]).startswith(prefix)]
+        main_k = max(main_k, key=lambda r: float(r["TotalDurationNs"]))
+        kname = main_k["Name"]
+        kshort = _kname(kname)
+        copy = {}
+        traffic = {}
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            path = os.path.join(src, f"pmc_{c}_{w}", "pmc_counter_collection.csv")
+            cm, _ = _counter_means(path, "k_copy")
+            copy[c] = cm[c]
+            km, n = _counter_means(path, kshort)
+            traffic[c] = (km[c], n)
+        ff = 536870912 / (copy["FETCH_SIZE"] * 1024)
+        wf = 536870912 / (copy["WRITE_SIZE"] * 1024)
+        fetch = traffic["FETCH_SIZE"][0] * 1024 * ff
+        write = traffic["WRITE_SIZE"][0] * 1024 * wf
+        sq, nsq = _counter_means(os.path.join(src, f"pmc_sq_{w}", "pmc_counter_collection.csv"), kshort)
+        sq["launches"] = nsq
+        alg_bytes = float(roof["hbm_alg_bytes_per_launch"])
+        ops = float(roof["alg_ops_per_launch"])
+        avg_us = float(main_k["AverageNs"]) / 1e3
+        rec = {"workload": w, "kernel": kname, "source_hash": kernel_source_hash(family),
+               "source_files": KERNEL_SOURCES[family], "rocprof_average_us": avg_us,
+               "commands": [cmds["stats"], cmds["FETCH_SIZE"], cmds["WRITE_SIZE"], cmds["sq"]],
+               "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+               "traffic_bytes_per_launch": fetch + write,
+               "copy_calibration": {"bytes": 536870912, "fetch_kib_raw": copy["FETCH_SIZE"],
+                                    "write_kib_raw": copy["WRITE_SIZE"], "fetch_factor": ff, "write_factor": wf},
+               "launches_counted": {"fetch": traffic["FETCH_SIZE"][1], "write": traffic["WRITE_SIZE"][1]},
+               "alg_bytes_per_launch": alg_bytes, "sq": sq}
+        with open(os.path.join(out_dir, name + ".json"), "w") as f:
+            json.dump(rec, f, indent=1)
+        tot = sum(float(r["TotalDurationNs"]) for r in stats)
+        L = [f"# rocprofv3: {name} (MI355X)", "", "Kernel statistics, command (REPO = repository root on the GPU box):",
+             "", "    " + cmds["stats"], "", "| kernel | calls | average (us) | min (us) | max (us) | share |",
+             "|---|---|---|---|---|---|"]
+        for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]:
+            nm = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
+            L.append(f"| {nm} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / tot:.1f} % |")
+        cyc = 4 * sq.get("SQ_INSTS_VALU", 0) / 1024
+        kc = avg_us * 1e-6 * 2.4e9
+        L += ["", "## HBM traffic of the main kernel (rocprofv3 --pmc, one counter per run)", "",
+              "    " + cmds["FETCH_SIZE"], "    " + cmds["WRITE_SIZE"], "",
+              f"- copy calibration: a 512 MiB device copy (wect_calib_copy) read {copy['FETCH_SIZE']:.1f} KiB "
+              f"(FETCH_SIZE) and wrote {copy['WRITE_SIZE']:.1f} KiB (WRITE_SIZE): factors {ff:.4f} and {wf:.4f}",
+              f"- `{kshort}` per launch: fetch {fetch / 1e6:.3f} MB, write {write / 1e6:.3f} MB (scaled), "
+              f"{traffic['FETCH_SIZE'][1]} launches",
+              f"- algorithmic bytes per launch: {alg_bytes / 1e6:.3f} MB; counter / algorithmic = "
+              f"{(fetch + write) / alg_bytes:.2f}", "",
+              "## Instruction counters of the main kernel (rocprofv3 --pmc, SQ block)", "", "    " + cmds["sq"], "",
+              f"- per launch ({nsq} launches): {sq.get('SQ_INSTS_VALU', 0):.4g} VALU, {sq.get('SQ_INSTS_LDS', 0):.4g} "
+              f"LDS, {sq.get('SQ_INSTS_SALU', 0):.4g} scalar wavefront instructions; {sq.get('SQ_WAVES', 0):.0f} "
+              f"wavefronts",
+              f"- VALU issue: {cyc:.4g} cycles per SIMD (4 cycles per wavefront instruction, 1024 SIMDs) against "
+              f"{kc:.4g} cycles of the kernel at 2.4 GHz: {100 * cyc / kc:.0f} % busy",
+              f"- {64 * sq.get('SQ_INSTS_VALU', 0) / ops:.2f} VALU lane-instructions per algorithmic lane-op "
+              f"({ops:.4g} algorithmic lane-ops per launch)"]
+        # the same workload in the default bench run
+        lr = live["roofline"] if w == "volumes3d" else live["configs"][w][key]
+        step = {"volumes3d": live["ms_per_step"], "images2d": live["configs"]["images2d"]["ms"]}.get(w)
+        if step is None:
+            step = live["configs"][w]["fwd_ms" if key == "roofline_fwd" else "fwd_bwd_ms"]
+        L += ["", f"Live measurement in the default `python bench.py` run on the same sources: `{lr['kernel']}` "
+              f"{lr['kernel_ms'] * 1e3:.1f} us per launch with HIP events on its stream (rocprofv3 average above: "
+              f"{avg_us:.1f} us); {step * 1e3:.1f} us per step; {lr['alg_ops_per_launch']:.4g} algorithmic lane-ops "
+              f"per launch = {lr['frac']:.3f} of the 39.3 T lane-ops/s VALU peak; "
+              f"{lr['hbm_alg_bytes_per_launch'] / 1e6:.2f} MB algorithmic HBM bytes = {lr['hbm_frac']:.4f} of 8 TB/s."]
+        with open(os.path.join(out_dir, name + ".md"), "w") as f:
+            f.write("\n".join(L) + "\n")
+        print(f"wrote profiles/{name}.md/.json", flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -579,7 +725,12 @@ def main(argv=None):
     ap.add_argument("--only", choices=WORKLOADS, default=None, help="run one workload only (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration for profiling runs)")
+    ap.add_argument("--write-profiles", nargs=2, metavar=("RESULTS_DIR", "BENCH_LOG"), default=None,
+                    help="write profiles/*.md/.json from rocprofv3 output (no GPU needed)")
     a = ap.parse_args(argv)
+    if a.write_profiles:
+        write_profiles(*a.write_profiles)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
