@@ -465,7 +465,21 @@ def run_more(W, a, res, diff):
     ws5w = torch.empty(max(1, W.wecf_workspace_bytes(cx5, F5.shape[1], g5.T)), dtype=torch.uint8, device="cuda")
     t_w = timed(lambda: W.wecf_forward(cx5, F5, g5.thr, out=o5w, ws=ws5w), 5, 1)
     res["wecf_filter_array_diffbatch_m128"] = {"fwd_ms": t_w * 1e3, "items_per_s": it5 / t_w}
-    del F5, o5w, ws5w
+    # one filter column (Algorithm 1 with a single vertex filter: the first
+    # direction's heights), with 64 cells per wavefront instruction and without
+    F1 = F5[:, :1].contiguous()
+    o1 = torch.empty((cx5.B, 1, g5.T), dtype=torch.float32, device="cuda")
+    one = {}
+    for name, packing in (("packed", 0), ("unpacked", 1)):
+        W.set_launch(cell_packing=packing)
+        ws1 = torch.empty(max(1, W.wecf_workspace_bytes(cx5, 1, g5.T)), dtype=torch.uint8, device="cuda")
+        t1 = timed(lambda: W.wecf_forward(cx5, F1, g5.thr, out=o1, ws=ws1), 5, 1)
+        one[name] = {"fwd_ms": t1 * 1e3, "items_per_s": sum(cx5.counts) / t1}
+        del ws1
+    W.set_launch()
+    one["packing_speedup"] = one["unpacked"]["fwd_ms"] / one["packed"]["fwd_ms"]
+    res["wecf_filter_array_diffbatch_m1"] = one
+    del F5, o5w, ws5w, F1, o1
     thr5 = w5.thr.astype(np.float64)
     lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
     os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device="cuda")

@@ -431,6 +431,13 @@ const char* wect_status_string(wect_status s);
  *   those instead of the voxel's 3^n neighbourhood; automatic turns it on when
  *   a voxel would otherwise be staged more than once (several direction or
  *   threshold tiles).  wect_forward_noalloc never uses records.
+ * cell_packing: 0 = automatic, 1 = off.  With at most 32 directions (or
+ *   filter columns of the general-filter WECF) the simplicial forward packs
+ *   64 / dt cells into each wavefront instruction, dt being the smallest
+ *   power of two >= d: lane l serves direction l mod dt of cell l / dt and
+ *   keeps its own histogram column; the copies are added together before the
+ *   threshold scan, so the output is unchanged (integer and fixed-point sums
+ *   are exact).  Without it, lanes past d idle.
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */
@@ -442,6 +449,7 @@ typedef struct {
   int32_t threshold_tile;
   int32_t directions_per_lane;
   int32_t cubical_records;
+  int32_t cell_packing;
 } wect_launch;
 
 wect_status wect_set_launch(const wect_launch* l);

@@ -60,6 +60,44 @@ __device__ __forceinline__ void filter_hist(ACC* col, const float* stage, int fi
   }
 }
 
+// Packed tiles (at most 32 directions or filter columns, dt of them rounded up
+// to a power of two): lane l serves column l % dt of the entries of lane group
+// g = l / dt, so 64 / dt entries share each instruction.  The wavefront's
+// groups take the pairs (e + 2g, e + 2g + 1) of its block of 2 * cpw entries;
+// entries past ne re-read a valid one and add zero.  Each lane keeps its own
+// histogram column; fold_columns adds the groups' copies together before the
+// scan.  entry(e, b, w) gives entry e's threshold index and signed weight for
+// the lane's column.
+template <typename ACC, typename Entry>
+__device__ __forceinline__ void packed_entries(ACC* col, int first, int step, int ne, int g, Entry entry) {
+  for (int e = first; e < ne; e += step) {
+    const int e0 = e + 2 * g, e1 = e0 + 1;
+    int b0, b1;
+    ACC w0, w1;
+    entry(min(e0, ne - 1), b0, w0);
+    entry(min(e1, ne - 1), b1, w1);
+    if (e0 >= ne) w0 = ACC(0);
+    if (e1 >= ne) w1 = ACC(0);
+    lds_add(&col[b0 * W], w0);
+    lds_add(&col[b1 * W], w1);
+  }
+}
+
+// Column c < dt of every row gets the copies of the other lane groups
+// (columns c + dt, c + 2 dt, ...); the threshold scan then reads columns < dt.
+template <typename ACC>
+__device__ void fold_columns(ACC* hist, int T, int dt) {
+  __syncthreads();
+  const int cpw = W / dt;
+  for (int i = threadIdx.x; i < (T + 1) * dt; i += blockDim.x) {
+    const int q = i / dt, c = i - q * dt;
+    ACC s = ACC(0);
+    for (int g = 1; g < cpw; ++g) s += hist[q * W + g * dt + c];
+    hist[q * W + c] += s;
+  }
+  __syncthreads();
+}
+
 // Forward over the simplices [lo, hi) (local numbering) of dimension DIM of
 // one complex: stage TS simplices at a time, then every wavefront adds its
 // share of them to the LDS histogram.  Indices are prefetched one tile ahead
@@ -118,6 +156,28 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
         h = max_height<N, DIM>(E, sx, sy, sz);
         C = load_weight<ACC>(E + L::WOFF);
       });
+    } else if (p.cpw > 1) {  // packed tile
+      const int g = lane / p.dt;
+      const int first = 2 * p.cpw * wave, step = 2 * p.cpw * nw;
+      if constexpr (N == 0) {
+        auto filt = [&](auto vb) {
+          packed_entries<ACC>(hist + lane, first, step, cnt, g, [&](int e, int& b, ACC& w) {
+            const float* E = stage + e * L::STRIDE;
+            b = 0;
+#pragma unroll
+            for (int j = 0; j < L::NV; ++j) b = max(b, (int)vb[(int64_t)bitcast<int32_t>(E[j]) * p.d + fcol]);
+            w = load_weight<ACC>(E + L::WOFF);
+          });
+        };
+        if (p.vb_bytes == 1) filt((const uint8_t*)p.vbuckets);
+        else filt((const uint16_t*)p.vbuckets);
+      } else {
+        packed_entries<ACC>(hist + lane, first, step, cnt, g, [&](int e, int& b, ACC& w) {
+          const float* E = stage + e * L::STRIDE;
+          b = thr_index<FAST>(max_height<N, DIM>(E, sx, sy, sz), th);
+          w = load_weight<ACC>(E + L::WOFF);
+        });
+      }
     } else if constexpr (N == 0) {
       if (p.vb_bytes == 1)
         filter_hist<DIM, uint8_t, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, (const uint8_t*)p.vbuckets, p.d,
@@ -184,10 +244,12 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
     const int64_t e0 = (pos - base) - (int64_t)t * nb;
     const int64_t e1 = mn64(nb, e0 + (end - pos));
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    // filter column of the lane (N = 0); lanes past the last column read the
-    // last one and their histogram column is never written out
-    const int fcol = min(t * W + lane, p.d - 1);
-    if constexpr (N > 0) load_dir(p, t * W + lane, sx, sy, sz);
+    // the lane's column within the tile (packed tiles: lane l serves column
+    // l % dt); filter column of the lane (N = 0): lanes past the last column
+    // read the last one and their histogram column is never written out
+    const int cl = p.cpw > 1 ? (lane & (p.dt - 1)) : lane;
+    const int fcol = min(t * W + cl, p.d - 1);
+    if constexpr (N > 0) load_dir(p, t * W + cl, sx, sy, sz);
     const int64_t voff = off_or(p.vert_off, b, p.count[0]);
     // dimension ranges within the complex's element numbering
     int64_t dlo = 0;
@@ -207,6 +269,7 @@ __global__ __launch_bounds__(1024) void k_simp_fwd(Params p) {
       }
       dlo = dhi;
     }
+    if (p.cpw > 1) fold_columns<ACC>(hist, T, p.dt);
     end_group<ACC>(p, hist, k, b, t, e0 == 0 && e1 == nb, fexp);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;

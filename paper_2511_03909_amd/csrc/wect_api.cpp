@@ -59,6 +59,7 @@ std::atomic<int> g_decomp{0};  // wect_launch.decomposition
 std::atomic<int> g_ttile{0};   // wect_launch.threshold_tile (0: automatic)
 std::atomic<int> g_dpl{0};     // wect_launch.directions_per_lane (0: automatic)
 std::atomic<int> g_rec{0};     // wect_launch.cubical_records (0: automatic, 1: off, 2: on)
+std::atomic<int> g_pack{0};    // wect_launch.cell_packing (0: automatic, 1: off)
 
 // measurement
 std::atomic<int> g_profile{0};
@@ -301,6 +302,17 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     dpl = (user == 2 || (user == 0 && g->d > kW)) && fits2 ? 2 : 1;
   }
   p.dpl = dpl;
+  // simplicial forward with at most 32 directions (or filter columns): 64 / dt
+  // cells per wavefront instruction instead of lanes past d idling
+  p.cpw = 1;
+  p.dt = kW;
+  if (need_fwd && c->kind == WECT_SIMPLICIAL && !smooth && !ls && g->d > 0 && g->d <= kW / 2 &&
+      g_pack.load() != 1) {
+    int dt = 1;
+    while (dt < g->d) dt *= 2;
+    p.dt = dt;
+    p.cpw = kW / dt;
+  }
   const int ntiles = (int)ceil_div(g->d, kW * dpl);
   DeviceInfo di;
   const bool have_dev = device_info(&di);
@@ -538,6 +550,8 @@ wect_status run_backward(const Plan& pl0, const float* grad_out, float* const gr
   } else {
     for (int i = 0; i < 4; ++i) p.grad_w[i] = grad_w ? grad_w[i] : nullptr;
   }
+  p.cpw = 1;  // the adjoint keeps one cell per instruction
+  p.dt = kW;
   p.dg = pl.dg;
   p.ngroups_dir = pl.ngd;
   p.G = pl.G_bwd;
@@ -912,6 +926,8 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (l->threshold_tile < 0) return WECT_ERR_ARG;
   if (l->directions_per_lane < 0 || l->directions_per_lane > 2) return WECT_ERR_ARG;
   if (l->cubical_records < 0 || l->cubical_records > 2) return WECT_ERR_ARG;
+  if (l->cell_packing < 0 || l->cell_packing > 1) return WECT_ERR_ARG;
+  g_pack.store(l->cell_packing);
   g_rec.store(l->cubical_records);
   g_decomp.store(l->decomposition);
   g_ttile.store(l->threshold_tile);
@@ -931,6 +947,7 @@ wect_status wect_get_launch(wect_launch* l) {
   l->threshold_tile = g_ttile.load();
   l->directions_per_lane = g_dpl.load();
   l->cubical_records = g_rec.load();
+  l->cell_packing = g_pack.load();
   return WECT_OK;
 }
 

@@ -41,6 +41,9 @@ struct Params {
   int32_t ntiles;        // direction tiles of 64 * dpl (forward) / per group (backward)
   int32_t dpl;           // directions per lane: 1, or 2 (cubical forward: a tile of 128 directions, two
                          // histogram columns per lane, so each staged voxel serves both)
+  int32_t cpw, dt;       // simplicial forward with d <= 32: cells per wavefront instruction (64 / dt) and
+                         // the power of two dt >= d of columns per cell; lane l serves column l % dt of
+                         // cell l / dt (cpw = 1, dt = 64: one cell per instruction)
   int32_t G;             // blocks of the main kernel
   int64_t S;             // stream length: sum over groups of the stream elements
   int32_t stage;         // staged entries per tile (<= blockDim.x)

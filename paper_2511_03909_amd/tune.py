@@ -135,7 +135,7 @@ def tune(cx, grid, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES,
     finally:
         api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"],
                        before["decomposition"], before["threshold_tile"], before["directions_per_lane"],
-                       before["cubical_records"])
+                       before["cubical_records"], before["cell_packing"])
     t, block, bpc, mi, dec, tt, dpl = min(results)
     best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "decomposition": dec,
             "threshold_tile": tt, "directions_per_lane": dpl, "ms": t * 1e3,
