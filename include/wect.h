@@ -438,6 +438,11 @@ const char* wect_status_string(wect_status s);
  *   keeps its own histogram column; the copies are added together before the
  *   threshold scan, so the output is unchanged (integer and fixed-point sums
  *   are exact).  Without it, lanes past d idle.
+ * stage_entries: cells (or voxels) staged per tile by the forward's main
+ *   kernel (0 = automatic: one per thread as far as LDS allows; else a
+ *   multiple of 64, at most 1024, lowered to what fits).  A smaller staging
+ *   tile takes less LDS, which can let another block share the compute unit,
+ *   at the price of more block barriers per cell.
  * Changing it changes wect_workspace_bytes().  Not to be called while other
  * threads are inside wect_* calls.
  */
@@ -450,6 +455,7 @@ typedef struct {
   int32_t directions_per_lane;
   int32_t cubical_records;
   int32_t cell_packing;
+  int32_t stage_entries;
 } wect_launch;
 
 wect_status wect_set_launch(const wect_launch* l);

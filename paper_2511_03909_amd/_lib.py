@@ -38,7 +38,8 @@ class WectGrid(ctypes.Structure):
 class WectLaunch(ctypes.Structure):
     _fields_ = [("block", c_int32), ("blocks_per_cu", c_int32), ("min_items_per_block", c_int32),
                 ("decomposition", c_int32), ("threshold_tile", c_int32), ("directions_per_lane", c_int32),
-                ("cubical_records", c_int32), ("cell_packing", c_int32)]
+                ("cubical_records", c_int32), ("cell_packing", c_int32),
+                ("stage_entries", c_int32)]
 
 
 class WectError(RuntimeError):

@@ -445,11 +445,12 @@ DECOMP_AUTO, DECOMP_STREAM, DECOMP_GROUP = 0, 1, 2
 
 def set_launch(block: int = 0, blocks_per_cu: int = 0, min_items_per_block: int = 0,
                decomposition: int = DECOMP_AUTO, threshold_tile: int = 0, directions_per_lane: int = 0,
-               cubical_records: int = 0, cell_packing: int = 0) -> None:
+               cubical_records: int = 0, cell_packing: int = 0, stage_entries: int = 0) -> None:
     """Launch shape of the following calls (0 = automatic for each field); see wect_launch."""
     L.check(L.lib().wect_set_launch(ctypes.byref(L.WectLaunch(block, blocks_per_cu, min_items_per_block,
                                                               decomposition, threshold_tile, directions_per_lane,
-                                                              cubical_records, cell_packing))), "wect_set_launch")
+                                                              cubical_records, cell_packing,
+                                                              stage_entries))), "wect_set_launch")
 
 
 def get_launch() -> dict:
@@ -458,7 +459,7 @@ def get_launch() -> dict:
     return {"block": w.block, "blocks_per_cu": w.blocks_per_cu, "min_items_per_block": w.min_items_per_block,
             "decomposition": w.decomposition, "threshold_tile": w.threshold_tile,
             "directions_per_lane": w.directions_per_lane, "cubical_records": w.cubical_records,
-            "cell_packing": w.cell_packing}
+            "cell_packing": w.cell_packing, "stage_entries": w.stage_entries}
 
 
 def profile_enable(on: bool = True) -> None:

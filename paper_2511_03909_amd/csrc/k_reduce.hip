@@ -172,27 +172,49 @@ __global__ __launch_bounds__(1024) void k_reduce_scan(Params p) {
   }
 }
 
-// Largest |w| over the float32 weights, per block: absmax[dim * 64 + block].
-__global__ __launch_bounds__(256) void k_absmax(Params p) {
-  __shared__ float red[256];
-  const int dim = blockIdx.y;
-  const float* w = nullptr;
-  int64_t n = 0;
-  if (p.wmode == WM_VMAX) {
-    if (dim == 0) { w = (const float*)p.weights[0]; n = p.count[0]; }
-  } else if (dim <= p.top_dim) {
-    w = (const float*)p.weights[dim];
-    n = p.count[dim];
-  }
+// Largest |w| over the float32 weights, one partial per block.  The weight
+// arrays that the request reads (every dimension's, or the vertex weights of
+// vertex-max weights) form one sequence of S values; block k takes the
+// contiguous range [kS/G, (k+1)S/G) and reads it four floats per load between
+// a scalar head (up to the array's next 16-byte boundary) and a scalar tail.
+// fmaxf skips NaN; an infinite weight gives an infinite maximum, for which
+// fixed_exp falls back to e = 0.
+__global__ __launch_bounds__(1024) void k_absmax(Params p) {
+  __shared__ float red[16];
+  const int ndim = p.wmode == WM_VMAX ? 1 : p.top_dim + 1;
+  int64_t S = 0;
+  for (int d = 0; d < ndim; ++d) S += p.count[d];
+  const int64_t lo = S * blockIdx.x / gridDim.x, hi = S * (blockIdx.x + 1) / gridDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   float m = 0.0f;
-  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = fmaxf(m, fabsf(w[i]));
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
+  int64_t base = 0;
+  for (int d = 0; d < ndim; ++d) {
+    const int64_t n = p.count[d];
+    const int64_t a = mx64(lo, base) - base, b = mn64(hi, base + n) - base;
+    base += n;
+    if (a >= b) continue;
+    const float* w = (const float*)p.weights[d];
+    const int64_t head = (int64_t)(((16 - ((uintptr_t)(w + a) & 15)) & 15) >> 2);
+    const int64_t a4 = mn64(a + head, b);
+    const int64_t nv = (b - a4) >> 2;
+    const int64_t b4 = a4 + 4 * nv;
+    if (a + tid < a4) m = fmaxf(m, fabsf(w[a + tid]));
+    if (b4 + tid < b) m = fmaxf(m, fabsf(w[b4 + tid]));
+    const float4* v = (const float4*)(w + a4);
+#pragma unroll 4
+    for (int64_t j = tid; j < nv; j += nt) {
+      const float4 x = v[j];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+    }
   }
-  if (threadIdx.x == 0) p.absmax[dim * gridDim.x + blockIdx.x] = red[0];
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    float r = 0.0f;
+    for (int i = 0; i < (nt >> 6); ++i) r = fmaxf(r, red[i]);
+    p.absmax[blockIdx.x] = r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -353,7 +375,7 @@ hipError_t launch_forward_reduce(const Params& p, hipStream_t s) {
 }
 
 hipError_t launch_absmax(const Params& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_absmax, dim3(p.nabsmax / 4, 4), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_absmax, dim3(p.nabsmax), dim3(1024), 0, s, p);
   return hipGetLastError();
 }
 

@@ -135,7 +135,7 @@ size_t forward_entry_bytes(int kind, int n);
 size_t backward_lds_bytes(int T, int stage, int dg);
 size_t smooth_backward_lds_bytes(int T, int stage);
 
-constexpr int kAbsmaxSlots = 256;  // 64 blocks x 4 weight arrays
+constexpr int kAbsmaxSlots = 256;  // blocks of k_absmax, one partial maximum each
 
 // Records the description returned by wect_last_error() on the calling thread.
 void set_last_error(const char* msg);

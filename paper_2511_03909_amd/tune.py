@@ -10,8 +10,11 @@ per compute unit and a larger staging area, at the price of re-reading the
 cells).  Results are cached in a JSON file keyed by a signature of the request
 (kind, ambient dimension, batch size, total cells rounded to a power of two,
 directions, thresholds, dtype), so a workload of the same shape reuses the
-choice.  Last, for cubical requests with more than 64 directions, it times one
-and two directions per lane (a direction tile of 64 or 128).
+choice.  Then, for cubical requests with more than 64 directions, it times one
+and two directions per lane (a direction tile of 64 or 128).  Last, for
+simplicial requests, it times staging tiles of a half and three quarters of
+the block besides the automatic one (fewer staged cells per tile, the same
+resident blocks).
 
     from paper_2511_03909_amd import tune
     shape = tune.tune(cx, grid)        # times, caches, applies
@@ -72,7 +75,7 @@ def apply(shape: Optional[dict]) -> None:
     if shape:
         api.set_launch(shape["block"], shape["blocks_per_cu"], shape["min_items_per_block"],
                        shape.get("decomposition", 0), shape.get("threshold_tile", 0),
-                       shape.get("directions_per_lane", 0))
+                       shape.get("directions_per_lane", 0), stage_entries=shape.get("stage_entries", 0))
     else:
         api.set_launch()
 
@@ -91,6 +94,15 @@ def lane_candidates(cx, grid) -> Tuple[int, ...]:
     if isinstance(cx, api.CubicalBatch) and grid.d > 64:
         return (1, 2)
     return ()
+
+
+def stage_candidates(cx, block: int) -> Tuple[int, ...]:
+    """Staging tiles tried for simplicial requests after the other choices: a
+    half and three quarters of the block (the automatic one is already timed)."""
+    if isinstance(cx, api.CubicalBatch):
+        return ()
+    b = block or 1024
+    return tuple(sorted({b // 2 // 64 * 64, 3 * b // 4 // 64 * 64} - {0}))
 
 
 def lookup(cx, grid, cache: str = DEFAULT_CACHE) -> Optional[dict]:
@@ -117,31 +129,34 @@ def tune(cx, grid, candidates: Iterable[Tuple[int, int, int, int]] = CANDIDATES,
     before = api.get_launch()
     results = []
 
-    def run(block, bpc, mi, dec, tt, dpl):
-        api.set_launch(block, bpc, mi, dec, tt, dpl)
+    def run(block, bpc, mi, dec, tt, dpl, st):
+        api.set_launch(block, bpc, mi, dec, tt, dpl, stage_entries=st)
         t1 = _time_forward(cx, grid, 1)
         r = reps or max(2, min(50, int(0.05 / max(t1, 1e-6))))
-        results.append((_time_forward(cx, grid, r), block, bpc, mi, dec, tt, dpl))
+        results.append((_time_forward(cx, grid, r), block, bpc, mi, dec, tt, dpl, st))
 
     try:
         for block, bpc, mi, dec in candidates:
-            run(block, bpc, mi, dec, 0, 0)
-        _, block, bpc, mi, dec, _, _ = min(results)
+            run(block, bpc, mi, dec, 0, 0, 0)
+        _, block, bpc, mi, dec, _, _, _ = min(results)
         for tt in tile_candidates(grid.T)[1:]:
-            run(block, bpc, mi, dec, tt, 0)
-        _, block, bpc, mi, dec, tt, _ = min(results)
+            run(block, bpc, mi, dec, tt, 0, 0)
+        _, block, bpc, mi, dec, tt, _, _ = min(results)
         for dpl in lane_candidates(cx, grid):
-            run(block, bpc, mi, dec, tt, dpl)
+            run(block, bpc, mi, dec, tt, dpl, 0)
+        _, block, bpc, mi, dec, tt, dpl, _ = min(results)
+        for st in stage_candidates(cx, block):
+            run(block, bpc, mi, dec, tt, dpl, st)
     finally:
         api.set_launch(before["block"], before["blocks_per_cu"], before["min_items_per_block"],
                        before["decomposition"], before["threshold_tile"], before["directions_per_lane"],
-                       before["cubical_records"], before["cell_packing"])
-    t, block, bpc, mi, dec, tt, dpl = min(results)
+                       before["cubical_records"], before["cell_packing"], before["stage_entries"])
+    t, block, bpc, mi, dec, tt, dpl, st = min(results)
     best = {"block": block, "blocks_per_cu": bpc, "min_items_per_block": mi, "decomposition": dec,
-            "threshold_tile": tt, "directions_per_lane": dpl, "ms": t * 1e3,
+            "threshold_tile": tt, "directions_per_lane": dpl, "stage_entries": st, "ms": t * 1e3,
             "tried": [{"block": b, "blocks_per_cu": c, "min_items_per_block": m, "decomposition": e,
-                       "threshold_tile": x, "directions_per_lane": y, "ms": s * 1e3}
-                      for s, b, c, m, e, x, y in results]}
+                       "threshold_tile": x, "directions_per_lane": y, "stage_entries": z, "ms": s * 1e3}
+                      for s, b, c, m, e, x, y, z in results]}
     if cache:
         data = _load(cache)
         data[signature(cx, grid)] = best

@@ -159,11 +159,14 @@ def test_launch_shape_roundtrip(lib):
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, -1))) == L.WECT_ERR_ARG
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, -5))) == L.WECT_ERR_ARG
     assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77, 3))) == L.WECT_ERR_ARG
-    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77, 2))) == L.WECT_OK
+    for bad_stage in (-64, 100, 1088):
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77, 2, 0, 0, bad_stage))) \
+            == L.WECT_ERR_ARG
+    assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 2, 1024, 2, 77, 2, 0, 0, 192))) == L.WECT_OK
     now = L.WectLaunch()
     lib.wect_get_launch(ctypes.byref(now))
     assert (now.block, now.blocks_per_cu, now.min_items_per_block, now.decomposition,
-            now.threshold_tile, now.directions_per_lane) == (512, 2, 1024, 2, 77, 2)
+            now.threshold_tile, now.directions_per_lane, now.stage_entries) == (512, 2, 1024, 2, 77, 2, 192)
     assert lib.wect_set_launch(ctypes.byref(before)) == L.WECT_OK
 
 

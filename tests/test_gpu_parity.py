@@ -545,6 +545,30 @@ def test_autotuner_caches_and_keeps_results(W, tmp_path):
         W.set_launch()
 
 
+def test_autotuner_simplicial_staging_tiles(W, tmp_path):
+    """Simplicial requests also time staging tiles of a half and three
+    quarters of the block; the chosen shape gives the same bits (64-bit fixed
+    point)."""
+    from paper_2511_03909_amd import tune
+    w = synth.cfg5(n_complexes=5, vmin=3000, vmax=9000)
+    cx = W.SimplicialBatch.from_host(w.complexes)
+    g = W.Grid(w.dirs, w.thr)
+    ref = W.wect_forward(cx, g).cpu().numpy()
+    try:
+        best = tune.tune(cx, g, candidates=((1024, 0, 0, 1), (512, 0, 0, 1)), reps=3, cache=str(tmp_path / "t.json"))
+        tried = best["tried"]
+        assert len(tried) == 2 + len(tune.tile_candidates(g.T)) - 1 + len(tune.stage_candidates(cx, best["block"]))
+        assert {t["stage_entries"] for t in tried} >= set(tune.stage_candidates(cx, best["block"]))
+        assert best["stage_entries"] in (0, *tune.stage_candidates(cx, best["block"]))
+        assert W.get_launch()["stage_entries"] == best["stage_entries"]
+        assert np.array_equal(W.wect_forward(cx, g).cpu().numpy().view(np.int32), ref.view(np.int32))
+        for st in (64, 192, 640):
+            W.set_launch(stage_entries=st)
+            assert np.array_equal(W.wect_forward(cx, g).cpu().numpy().view(np.int32), ref.view(np.int32)), st
+    finally:
+        W.set_launch()
+
+
 @pytest.mark.parametrize("T", [255, 256, 257, 300, 500])
 def test_many_thresholds(W, T):
     """T above 256 takes the two-pass scan (row-group totals, then the scan) and smaller staging tiles."""
