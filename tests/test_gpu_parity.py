@@ -569,6 +569,31 @@ def test_autotuner_simplicial_staging_tiles(W, tmp_path):
         W.set_launch()
 
 
+def test_cubical_staging_tiles_give_identical_integers(W):
+    """wect_launch.stage_entries on the cubical forward: every staging tile (one
+    and two directions per lane, with and without per-voxel records) gives the
+    oracle's integers."""
+    ims = [synth.random_tiny_cubical(s, shp, include_above=60) for s, shp in
+           enumerate(((33, 29), (17, 40), (5, 3), (50, 21)))]
+    vols = [synth.random_tiny_cubical(s, shp, include_above=80) for s, shp in
+            enumerate(((13, 11, 9), (7, 20, 6), (4, 4, 4)))]
+    cases = ((ims, synth.s1_directions(150), synth.uniform_thresholds(67, 1.7)),
+             (vols, synth.fibonacci_directions(140), synth.uniform_thresholds(256, 2.0)))
+    try:
+        for Cs, dirs, thr in cases:
+            refs = [oracle.wect(C, dirs, thr) for C in Cs]
+            for st in (64, 192, 320, 1024):
+                for dpl in (1, 2):
+                    for rec in (1, 2):
+                        _say(f"cubical staging tile {st}, dpl={dpl}, records={rec}, n={Cs[0].n}")
+                        W.set_launch(stage_entries=st, directions_per_lane=dpl, cubical_records=rec)
+                        got = gpu_wect(W, Cs, dirs, thr)
+                        for b, C in enumerate(Cs):
+                            assert_match(got[b], refs[b], C, f"stage={st} dpl={dpl} rec={rec} complex {b}")
+    finally:
+        W.set_launch()
+
+
 @pytest.mark.parametrize("T", [255, 256, 257, 300, 500])
 def test_many_thresholds(W, T):
     """T above 256 takes the two-pass scan (row-group totals, then the scan) and smaller staging tiles."""
