@@ -143,6 +143,43 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+_FLUSH = []
+
+
+def warm_cold(a, fn, reps=11):
+    """Median time of one call with HIP events on the current stream: warm
+    (back to back) and cold (each call after writing a 1 GiB buffer, which
+    evicts the 256 MB Infinity Cache and the L2 caches of earlier calls).
+    Skipped in the single-workload runs behind the profiles, so that their
+    kernel statistics cover warm calls only."""
+    import torch
+    if getattr(a, "only", None):
+        return None
+    if not _FLUSH:
+        _FLUSH.append(torch.empty(1 << 28, dtype=torch.float32, device="cuda"))
+    buf = _FLUSH[0]
+
+    def one(flush):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if flush:
+            buf.fill_(float(len(ts)))
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+
+    res = {}
+    for name, flush in (("warm", False), ("cold", True)):
+        ts = []
+        for _ in range(reps):
+            one(flush)
+        res[f"{name}_median_ms"] = sorted(ts)[reps // 2]
+    res["reps"] = reps
+    res["flush_bytes"] = buf.numel() * 4
+    return res
+
+
 def kernel_ms(W, fn, reps):
     """Average HIP-event duration of the library's main kernels (forward
     histogram, adjoint) per launch, recorded on their own stream."""
@@ -294,7 +331,7 @@ def run_volumes3d(W, a, calib, single=True):
     sec = timed(step, a.steps, a.warmup)
     kf, _, _ = kernel_ms(W, step, max(5, a.steps // 2))
     res = {"workload": w.name, "items": d * cells, "cells": cells, "included_vertices": nverts, "ms": sec * 1e3,
-           "items_per_s": d * cells / sec,
+           "items_per_s": d * cells / sec, "per_call": warm_cold(a, step),
            "roofline": roofline("k_cub_fwd<3, vertex-max>", cubical_ops(nverts, 3, T, d), cubical_bytes(cx, d, T),
                                 kf, calib, "cubical_fwd_3d_16vol_64-192_d512_T256", "cub_fwd", lds_atomics=nverts * d,
                                 step_ms=sec * 1e3)}
@@ -327,6 +364,7 @@ def run_images2d(W, a, calib, single=True):
     sec = timed(step, max(20, a.steps), a.warmup)
     kf, _, _ = kernel_ms(W, step, 20)
     res = {"workload": w.name, "items": d * cells, "ms": sec * 1e3, "items_per_s": d * cells / sec,
+           "per_call": warm_cold(a, step),
            "roofline": roofline("k_cub_fwd<2, vertex-max>", cubical_ops(nverts, 2, T, d), cubical_bytes(cx, d, T),
                                 kf, calib, "cubical_fwd_2d_256x128x128_d64_T128", "cub_fwd", lds_atomics=nverts * d,
                                 step_ms=sec * 1e3)}
@@ -367,6 +405,7 @@ def run_kuhn3d(W, a, calib):
     kf, kb, _ = kernel_ms(W, fwdbwd, 5)
     ops = simplicial_ops(counts, 3, T, d)
     return {"workload": w.name, "items": items, "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3,
+            "per_call_fwd": warm_cold(a, fwd), "per_call_fwd_bwd": warm_cold(a, fwdbwd),
             "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
             "roofline_fwd": roofline("k_simp_fwd<3, explicit, float>", ops,
                                      simplicial_bytes(counts, 3, 1, d, T, "explicit"), kf, calib,
@@ -414,7 +453,9 @@ def run_diffbatch(W, a, calib, single=True):
     t_g = timed(graph.replay, 10, 2)
     ops = simplicial_ops(counts, 2, T, d)
     res = {"workload": w.name, "items": items, "fwd_ms": t_f * 1e3, "fwd_bwd_ms": t_fb * 1e3,
-           "fwd_bwd_graph_ms": t_g * 1e3, "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
+           "fwd_bwd_graph_ms": t_g * 1e3, "per_call_fwd": warm_cold(a, fwd),
+           "per_call_fwd_bwd": warm_cold(a, fwdbwd),
+           "fwd_items_per_s": items / t_f, "fwd_bwd_items_per_s": items / t_fb,
            "roofline_fwd": roofline("k_simp_fwd<2, vertex-max, float>", ops,
                                     simplicial_bytes(counts, 2, B, d, T, "vertex_max"), kf, calib,
                                     "simplicial_fwd_2d_freudenthal_batch64_d128_T128", "simp_fwd", lds_atomics=sum(counts) * d),
@@ -712,6 +753,15 @@ def write_profiles(src: str, bench_log: str) -> None:
               f"{kc:.4g} cycles of the kernel at 2.4 GHz: {100 * cyc / kc:.0f} % busy",
               f"- {64 * sq.get('SQ_INSTS_VALU', 0) / ops:.2f} VALU lane-instructions per algorithmic lane-op "
               f"({ops:.4g} algorithmic lane-ops per launch)"]
+        cal = live.get("calibration", {}).get("lds_add_per_s", {})
+        if sq.get("SQ_WAVE_CYCLES") and cal:
+            per_cc = lambda rate: rate / 64 / 256 / 2.4e9  # wavefront instructions per CU-cycle
+            L.append(f"- LDS: {sq.get('SQ_INSTS_LDS', 0) / 256 / kc:.3f} wavefront instructions per CU-cycle (reads, "
+                     f"writes and atomics); conflict-free atomic adds alone sustain {per_cc(cal['u32']):.3f} (u32) "
+                     f"and {per_cc(cal['u64']):.3f} (u64) per CU-cycle (wect_calib_lds_atomics, same run as the live "
+                     f"line below); wavefronts wait on LDS for "
+                     f"{100 * sq.get('SQ_WAIT_INST_LDS', 0) / sq['SQ_WAVE_CYCLES']:.0f} % of their cycles "
+                     f"(SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES)")
         # the same workload in the default bench run
         lr = live["roofline"] if w == "volumes3d" else live["configs"][w][key]
         step = {"volumes3d": live["ms_per_step"], "images2d": live["configs"]["images2d"]["ms"]}.get(w)
@@ -799,6 +849,7 @@ def main(argv=None):
         "calibration": calib,
         "kernel_sources": kernel_source_hash(),
     }
+    result["per_call"] = head["per_call"]
     if "one_per_launch" in head:
         result["one_per_launch"] = head["one_per_launch"]
     print(json.dumps({"progress": "headline done", "ms_per_step": head["ms"]}), file=sys.stderr, flush=True)
