@@ -22,11 +22,18 @@ namespace {
 // lane then reads the one for its direction's orthant.  With a zero component
 // the heights along that axis are equal, so either corner gives the same index.
 
+// Staged entry of a contributing vertex (8 words): its axis coordinates, then
+// its 2^N combined weights, int32 in 2D and int16 pairs in 3D (|weight| <=
+// 2^(N-1) * 255 < 2^15, the layout of a voxel record).  The 32-byte 3D entry
+// leaves room for a larger staging tile next to the histogram of two
+// directions per lane; a lane extracts its orthant's half with one bitfield
+// extract.
 template <int N>
 struct CubLayout {
   static constexpr int NO = 1 << N;                 // orthants
-  static constexpr int COFF = N == 2 ? 2 : 4;       // first combined weight
-  static constexpr int STRIDE = N == 2 ? 8 : 12;
+  static constexpr bool PACKED = N == 3;            // int16 pairs
+  static constexpr int COFF = N;                    // first weight word
+  static constexpr int STRIDE = 8;
 };
 
 // Raw neighbourhood of one voxel, loaded one tile ahead of its use: the
@@ -164,6 +171,18 @@ struct CubRec {
     cy = ax1[i1];
     cz = N == 3 ? ax2[i2] : 0.0f;
   }
+  // the record's words (int16 pairs); false when all are zero (or the voxel is not staged)
+  __device__ __forceinline__ bool packed(uint32_t* pk) const {
+    if (!valid) return false;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(&r);
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 0; k < NO / 2; ++k) {
+      any |= w[k];
+      pk[k] = w[k];
+    }
+    return any != 0;
+  }
   // combined weights; false when all are zero (or the voxel is not staged)
   __device__ __forceinline__ bool weights(int32_t* cw) const {
     if (!valid) return false;
@@ -260,7 +279,10 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     __syncthreads();
     bool keep = false;
     int32_t cw[L::NO];
-    if constexpr (PRE) {
+    uint32_t pk[L::NO / 2];
+    if constexpr (PRE && L::PACKED) {
+      keep = f.packed(pk);
+    } else if constexpr (PRE) {
       keep = f.weights(cw);
     } else if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
       cub_weights<N, WM>(f, p.include_above, cw);
@@ -268,6 +290,10 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
 #pragma unroll
       for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
       keep = nz;
+    }
+    if constexpr (L::PACKED && !PRE) {
+#pragma unroll
+      for (int k = 0; k < L::NO / 2; ++k) pk[k] = ((uint32_t)cw[2 * k] & 0xffffu) | ((uint32_t)cw[2 * k + 1] << 16);
     }
     // compact the contributing vertices
     const uint64_t bal = __ballot(keep);
@@ -279,9 +305,14 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
       float* E = stage + slot * L::STRIDE;
       E[0] = f.cx;
       E[1] = f.cy;
-      if constexpr (N == 3) { E[2] = f.cz; E[3] = 0.0f; }
+      if constexpr (N == 3) E[2] = f.cz;
+      if constexpr (L::PACKED) {
 #pragma unroll
-      for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
+        for (int k = 0; k < L::NO / 2; ++k) E[L::COFF + k] = bitcast<float>(pk[k]);
+      } else {
+#pragma unroll
+        for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
+      }
     }
     // neighbourhoods of the next tile (in flight during this tile's histogram)
     i0 += (int)s0;
@@ -295,19 +326,31 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     fetch(v < (uint32_t)hi && tid < TS);
     __syncthreads();
     const int ne = uniform(*counter);
+    // the lane's combined weight within an entry: word wo[k], bits sh[k] .. sh[k] + 15 when packed
+    int wo[DPL], sh[DPL];
+#pragma unroll
+    for (int k = 0; k < DPL; ++k) {
+      wo[k] = L::COFF + (L::PACKED ? orth[k] >> 1 : orth[k]);
+      sh[k] = L::PACKED ? (orth[k] & 1) * 16 : 0;
+    }
+    auto weight = [&](const float* E, int k) -> uint32_t {
+      const uint32_t x = bitcast<uint32_t>(E[wo[k]]);
+      if constexpr (L::PACKED) return (uint32_t)__builtin_amdgcn_sbfe((int)x, (unsigned)sh[k], 16u);
+      else return x;
+    };
     if constexpr (DPL == 1) {
-      const float* Wl = stage + L::COFF + orth[0];  // the lane's combined weight within an entry
       hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
                                    [&](int e, float& h, uint32_t& w) {
-                                     h = height<N>(stage + e * L::STRIDE, sx[0], sy[0], sz[0]);
-                                     w = bitcast<uint32_t>(Wl[e * L::STRIDE]);
+                                     const float* E = stage + e * L::STRIDE;
+                                     h = height<N>(E, sx[0], sy[0], sz[0]);
+                                     w = weight(E, 0);
                                    });
     } else {
       hist_entries2<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
                                     [&](int e, int k, float& h, uint32_t& w) {
                                       const float* E = stage + e * L::STRIDE;
                                       h = height<N>(E, sx[k], sy[k], sz[k]);
-                                      w = bitcast<uint32_t>(E[L::COFF + orth[k]]);
+                                      w = weight(E, k);
                                     });
     }
     __syncthreads();

@@ -336,7 +336,7 @@ size_t forward_lds_fixed(int T, int kind, int acc_bytes, int dpl) {
   return hist + pairs + 16;
 }
 
-size_t forward_entry_bytes(int kind, int n) { return (size_t)(kind == 1 ? (n == 2 ? 8 : 12) : kMaxStride) * 4; }
+size_t forward_entry_bytes(int kind, int n) { return (size_t)(kind == 1 ? 8 : kMaxStride) * 4; }
 
 size_t backward_lds_bytes(int T, int stage, int dg) {
   size_t g = (size_t)dg * (T + 1) * W * 4;
