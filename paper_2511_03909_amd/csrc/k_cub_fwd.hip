@@ -24,15 +24,19 @@ namespace {
 
 // Staged entry of a contributing vertex (8 words): its axis coordinates, then
 // its 2^N combined weights, int32 in 2D and int16 pairs in 3D (|weight| <=
-// 2^(N-1) * 255 < 2^15, the layout of a voxel record).  The 32-byte 3D entry
-// leaves room for a larger staging tile next to the histogram of two
-// directions per lane; a lane extracts its orthant's half with one bitfield
-// extract.
+// 2^(N-1) * 255 < 2^15, the layout of a voxel record), and in 3D the index
+// i1 + n1 i2 of its grid row.  The 32-byte 3D entry leaves room for a larger
+// staging tile next to the histogram of two directions per lane; a lane
+// extracts its orthant's half with one bitfield extract.  Entries of one row
+// share y s_y and z s_z, so the histogram keeps them per wavefront and
+// recomputes them only when the row changes: the height ((x s_x) + (y s_y)) +
+// (z s_z) keeps its operations and their order.
 template <int N>
 struct CubLayout {
   static constexpr int NO = 1 << N;                 // orthants
   static constexpr bool PACKED = N == 3;            // int16 pairs
   static constexpr int COFF = N;                    // first weight word
+  static constexpr int ROW = 7;                     // 3D: grid row of the vertex
   static constexpr int STRIDE = 8;
 };
 
@@ -258,6 +262,10 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
   const float* ax1 = ax0 + n0;
   const float* ax2 = ax1 + n1;
   int arith = th.arith;
+  uint32_t row = 0xffffffffu;  // no row yet (row indices are below 2^31)
+  float ysy[DPL], zsz[DPL];
+#pragma unroll
+  for (int k = 0; k < DPL; ++k) ysy[k] = zsz[k] = 0.0f;
   // grid position of the thread's voxel lo + tid, advanced by TS voxels per
   // tile without division (voxel counts of one complex are below 2^31)
   const uint32_t ts = (uint32_t)TS;
@@ -305,7 +313,10 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
       float* E = stage + slot * L::STRIDE;
       E[0] = f.cx;
       E[1] = f.cy;
-      if constexpr (N == 3) E[2] = f.cz;
+      if constexpr (N == 3) {
+        E[2] = f.cz;
+        E[L::ROW] = bitcast<float>((uint32_t)i1 + (uint32_t)n1 * (uint32_t)i2);
+      }
       if constexpr (L::PACKED) {
 #pragma unroll
         for (int k = 0; k < L::NO / 2; ++k) E[L::COFF + k] = bitcast<float>(pk[k]);
@@ -338,18 +349,38 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
       if constexpr (L::PACKED) return (uint32_t)__builtin_amdgcn_sbfe((int)x, (unsigned)sh[k], 16u);
       else return x;
     };
+    // 3D: y s_y and z s_z of the row last seen by this wavefront
+    auto row_terms = [&](const float* E) {
+      if constexpr (N == 3) {
+        const uint32_t r = __builtin_amdgcn_readfirstlane(bitcast<uint32_t>(E[L::ROW]));
+        if (r != row) {
+          row = r;
+#pragma unroll
+          for (int k = 0; k < DPL; ++k) {
+            ysy[k] = E[1] * sy[k];
+            zsz[k] = E[2] * sz[k];
+          }
+        }
+      }
+    };
+    auto hgt = [&](const float* E, int k) -> float {
+      if constexpr (N == 3) return (E[0] * sx[k] + ysy[k]) + zsz[k];
+      else return height<N>(E, sx[k], sy[k], sz[k]);
+    };
     if constexpr (DPL == 1) {
       hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
                                    [&](int e, float& h, uint32_t& w) {
                                      const float* E = stage + e * L::STRIDE;
-                                     h = height<N>(E, sx[0], sy[0], sz[0]);
+                                     row_terms(E);
+                                     h = hgt(E, 0);
                                      w = weight(E, 0);
                                    });
     } else {
       hist_entries2<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
                                     [&](int e, int k, float& h, uint32_t& w) {
                                       const float* E = stage + e * L::STRIDE;
-                                      h = height<N>(E, sx[k], sy[k], sz[k]);
+                                      if (k == 0) row_terms(E);  // k = 1 follows for the same entry
+                                      h = hgt(E, k);
                                       w = weight(E, k);
                                     });
     }

@@ -287,8 +287,9 @@ __device__ __forceinline__ void hist_entries(ACC* col, int first, int step, int 
 // As hist_entries for entries that serve two directions per lane (a tile of
 // 128 directions: column `lane` for the first, `lane + 64` for the second,
 // rows 128 wide).  entry(e, k, h, w) gives the height and weight of entry e
-// for the lane's k-th direction.  The index mode switch is per wavefront as
-// in hist_entries, counted over both directions.
+// for the lane's k-th direction; it is called for k = 0 and then k = 1 of one
+// entry before the next entry.  The index mode switch is per wavefront as in
+// hist_entries, counted over both directions.
 template <bool FAST, typename ACC, typename Entry>
 __device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int ne, const Thr& th, int* arith,
                                               Entry entry) {
@@ -299,49 +300,50 @@ __device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int
       const int stop = min(ne - 1, e + 32 * step);
       int fixes = 0, pairs = 0;
       for (; e < stop; e += step) {
+        float h[2][2];
+        ACC w[2][2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) entry(e + j, k, h[j][k], w[j][k]);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          float h0, h1;
-          ACC w0, w1;
-          entry(e, k, h0, w0);
-          entry(e + 1, k, h1, w1);
           int b0, b1;
-          const bool ok0 = thr_arith(h0, th, b0);
-          const bool ok1 = thr_arith(h1, th, b1);
+          const bool ok0 = thr_arith(h[0][k], th, b0);
+          const bool ok1 = thr_arith(h[1][k], th, b1);
           if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
             ++fixes;
-            if (!ok0) b0 = thr_near(h0, b0, th);
-            if (!ok1) b1 = thr_near(h1, b1, th);
+            if (!ok0) b0 = thr_near(h[0][k], b0, th);
+            if (!ok1) b1 = thr_near(h[1][k], b1, th);
           }
           ++pairs;
-          lds_add(&col[b0 * RW + k * W], w0);
-          lds_add(&col[b1 * RW + k * W], w1);
+          lds_add(&col[b0 * RW + k * W], w[0][k]);
+          lds_add(&col[b1 * RW + k * W], w[1][k]);
         }
       }
       if (4 * fixes > pairs) *arith = 0;
     }
   }
   for (; e + 1 < ne; e += step) {
+    float h[2][2];
+    ACC w[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) entry(e + j, k, h[j][k], w[j][k]);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      float h0, h1;
-      ACC w0, w1;
-      entry(e, k, h0, w0);
-      entry(e + 1, k, h1, w1);
-      const int b0 = thr_index<FAST>(h0, th);
-      const int b1 = thr_index<FAST>(h1, th);
-      lds_add(&col[b0 * RW + k * W], w0);
-      lds_add(&col[b1 * RW + k * W], w1);
+      lds_add(&col[thr_index<FAST>(h[0][k], th) * RW + k * W], w[0][k]);
+      lds_add(&col[thr_index<FAST>(h[1][k], th) * RW + k * W], w[1][k]);
     }
   }
   if (e < ne) {
+    float h[2];
+    ACC w[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      float h0;
-      ACC w0;
-      entry(e, k, h0, w0);
-      lds_add(&col[thr_index<FAST>(h0, th) * RW + k * W], w0);
-    }
+    for (int k = 0; k < 2; ++k) entry(e, k, h[k], w[k]);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) lds_add(&col[thr_index<FAST>(h[k], th) * RW + k * W], w[k]);
   }
 }
 
