@@ -16,9 +16,11 @@ namespace {
 
 constexpr int kMaxDG = 4;
 
-template <int N, int DIM, int WM, bool FAST>
+// DG: direction tiles of the group (compile time, so that the per-tile loop
+// needs no predicates).
+template <int N, int DIM, int WM, bool FAST, int DG>
 __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t lo, int64_t hi, int64_t voff, int64_t soff,
-                               const float* sx, const float* sy, const float* sz, int ntl, int tile0,
+                               const float* sx, const float* sy, const float* sz, int tile0,
                                const float* Gt, float* stage, const Thr& th) {
   using L = SimpLayout<N, DIM, uint64_t>;
   const int tid = threadIdx.x, lane = tid & (W - 1);
@@ -46,11 +48,11 @@ __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t l
       float acc[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const float* E = stage + (e0 + min(j0 + k, ne - 1)) * L::STRIDE;
+        const float* E = stage + uniform(e0 + min(j0 + k, ne - 1)) * L::STRIDE;
         float a = 0.0f;
 #pragma unroll
-        for (int jj = 0; jj < kMaxDG; ++jj) {
-          if (jj < ntl) {
+        for (int jj = 0; jj < DG; ++jj) {
+          {
             int bi;
             if constexpr (N == 0) {
               // general vertex filter: the largest of the vertices' threshold indices
@@ -65,8 +67,9 @@ __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t l
             } else {
               const float h = max_height<N, DIM>(E, sx[jj], sy[jj], sz[jj]);
               if (FAST && th.arith) {
-                // arithmetic index; the one-read fix only where a lane sits on a threshold
-                if (__builtin_amdgcn_ballot_w64(!thr_arith(h, th, bi) ? 1 : 0) != 0) bi = thr_index<FAST>(h, th);
+                // arithmetic index; the one-read fix only on the lanes that sit on a threshold
+                const bool ok = thr_arith(h, th, bi);
+                if (__builtin_amdgcn_ballot_w64(!ok) != 0 && !ok) bi = thr_near(h, bi, th);
               } else {
                 bi = thr_index<FAST>(h, th);
               }
@@ -97,15 +100,27 @@ __device__ __forceinline__ void simp_bwd_range(const Params& p, int b, int64_t l
   }
 }
 
+template <int N, int WM, bool FAST, int DG>
+__device__ __forceinline__ void simp_bwd_dim_g(int dim, const Params& p, int b, int64_t lo, int64_t hi, int64_t voff,
+                                               int64_t soff, const float* sx, const float* sy, const float* sz,
+                                               int tile0, const float* Gt, float* stage, const Thr& th) {
+  switch (dim) {
+    case 0: simp_bwd_range<N, 0, WM, FAST, DG>(p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+    case 1: simp_bwd_range<N, 1, WM, FAST, DG>(p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+    case 2: simp_bwd_range<N, 2, WM, FAST, DG>(p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+    default: simp_bwd_range<N, 3, WM, FAST, DG>(p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+  }
+}
+
 template <int N, int WM, bool FAST>
 __device__ __forceinline__ void simp_bwd_dim(int dim, const Params& p, int b, int64_t lo, int64_t hi, int64_t voff,
                                              int64_t soff, const float* sx, const float* sy, const float* sz, int ntl,
                                              int tile0, const float* Gt, float* stage, const Thr& th) {
-  switch (dim) {
-    case 0: simp_bwd_range<N, 0, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
-    case 1: simp_bwd_range<N, 1, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
-    case 2: simp_bwd_range<N, 2, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
-    default: simp_bwd_range<N, 3, WM, FAST>(p, b, lo, hi, voff, soff, sx, sy, sz, ntl, tile0, Gt, stage, th); break;
+  switch (ntl) {
+    case 1: simp_bwd_dim_g<N, WM, FAST, 1>(dim, p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+    case 2: simp_bwd_dim_g<N, WM, FAST, 2>(dim, p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+    case 3: simp_bwd_dim_g<N, WM, FAST, 3>(dim, p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
+    default: simp_bwd_dim_g<N, WM, FAST, kMaxDG>(dim, p, b, lo, hi, voff, soff, sx, sy, sz, tile0, Gt, stage, th); break;
   }
 }
 
