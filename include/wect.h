@@ -439,8 +439,9 @@ const char* wect_status_string(wect_status s);
  *   threshold scan, so the output is unchanged (integer and fixed-point sums
  *   are exact).  Without it, lanes past d idle.
  * stage_entries: cells (or voxels) staged per tile by the forward's main
- *   kernel (0 = automatic: one per thread as far as LDS allows; else a
- *   multiple of 64, at most 1024, lowered to what fits).  A smaller staging
+ *   kernel (0 = automatic: one per thread as far as LDS allows, except 768
+ *   for 1024-thread simplicial blocks, which measured faster than 1024; else
+ *   a multiple of 64, at most 1024, lowered to what fits).  A smaller staging
  *   tile takes less LDS, which can let another block share the compute unit,
  *   at the price of more block barriers per cell.
  * Changing it changes wect_workspace_bytes().  Not to be called while other
