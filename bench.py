@@ -693,17 +693,18 @@ SQ_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU SQ_WAVE_CYCLES
 
 
 def profile_commands(w: str) -> dict:
-    """The rocprofv3 runs behind a workload's profiles (REPO = repository root
-    on the GPU machine; outputs under REPO/gpurun_out)."""
+    """The rocprofv3 runs behind a workload's profiles (REPO = repository
+    root, OUT = the folder that receives the profiler output; write_profiles
+    reads that folder)."""
     run = f"python3 -u $REPO/bench.py --only {w}"
     return {
-        "stats": f"cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d $REPO/gpurun_out/prof_{w} "
+        "stats": f"cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/prof_{w} "
                  f"-o {w} -- {run} --steps 10 --warmup 2",
         "FETCH_SIZE": f"cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d "
-                      f"$REPO/gpurun_out/pmc_FETCH_SIZE_{w} -o pmc -- {run} --steps 3 --warmup 1 --copy-calibration",
+                      f"$OUT/pmc_FETCH_SIZE_{w} -o pmc -- {run} --steps 3 --warmup 1 --copy-calibration",
         "WRITE_SIZE": f"cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d "
-                      f"$REPO/gpurun_out/pmc_WRITE_SIZE_{w} -o pmc -- {run} --steps 3 --warmup 1 --copy-calibration",
-        "sq": f"cd /tmp && rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d $REPO/gpurun_out/pmc_sq_{w} -o pmc "
+                      f"$OUT/pmc_WRITE_SIZE_{w} -o pmc -- {run} --steps 3 --warmup 1 --copy-calibration",
+        "sq": f"cd /tmp && rocprofv3 --pmc {SQ_COUNTERS} --output-format csv -d $OUT/pmc_sq_{w} -o pmc "
               f"-- {run} --steps 3 --warmup 1",
     }
 
@@ -781,7 +782,7 @@ def write_profiles(src: str, bench_log: str) -> None:
         with open(os.path.join(out_dir, name + ".json"), "w") as f:
             json.dump(rec, f, indent=1)
         tot = sum(float(r["TotalDurationNs"]) for r in stats)
-        L = [f"# rocprofv3: {name} (MI355X)", "", "Kernel statistics, command (REPO = repository root on the GPU box):",
+        L = [f"# rocprofv3: {name} (MI355X)", "", "Kernel statistics, command (REPO = repository root, OUT = profiler output folder):",
              "", "    " + cmds["stats"], "", "| kernel | calls | average (us) | min (us) | max (us) | share |",
              "|---|---|---|---|---|---|"]
         for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]:
