@@ -547,8 +547,8 @@ def run_mesh2d(W, a, calib):
 
 def run_more(W, a, res, diff):
     """Workloads beyond the scope rows: the general-filter WECF of the
-    differentiation batch, the Freudenthal builder, the image ECF, and the
-    sigmoid relaxation."""
+    differentiation batch, a batch of small images, the Freudenthal builder,
+    the image ECF, and the sigmoid relaxation."""
     import numpy as np
     import torch
     import synth
@@ -574,6 +574,23 @@ def run_more(W, a, res, diff):
     one["packing_speedup"] = one["unpacked"]["fwd_ms"] / one["packed"]["fwd_ms"]
     res["wecf_filter_array_diffbatch_m1"] = one
     del F5, o5w, ws5w, F1, o1
+    # a batch of small images (1024 of 28^2, the images' recipe otherwise):
+    # one block per image, against one call per image
+    ws_ = synth.cfg2(n_images=1024, side=28)
+    cxs = W.CubicalBatch.from_host(ws_.complexes, device="cuda")
+    gs = W.Grid(ws_.dirs, ws_.thr, device="cuda")
+    its = gs.d * sum(cubical_cell_count(C) for C in ws_.complexes)
+    outs = torch.empty((cxs.B, gs.d, gs.T), dtype=torch.int32, device="cuda")
+    wss = torch.empty(max(1, W.wect_workspace_bytes(cxs, gs)), dtype=torch.uint8, device="cuda")
+    t_b = timed(lambda: W.wect_forward(cxs, gs, out=outs, ws=wss), 20, 3)
+    singles = [W.CubicalBatch.from_host([C], device="cuda") for C in ws_.complexes]
+    o1s = [torch.empty((1, gs.d, gs.T), dtype=torch.int32, device="cuda") for _ in singles]
+    ws1s = torch.empty(max(1, max(W.wect_workspace_bytes(c, gs) for c in singles)), dtype=torch.uint8,
+                       device="cuda")
+    t_s = timed(lambda: [W.wect_forward(c, gs, out=o, ws=ws1s) for c, o in zip(singles, o1s)], 2, 1)
+    res["images2d_1024x28x28_d64_T128"] = {"ms": t_b * 1e3, "items_per_s": its / t_b,
+                                           "one_per_launch_ms": t_s * 1e3, "batched_speedup": t_s / t_b}
+    del cxs, singles, o1s, ws1s, outs, wss
     thr5 = w5.thr.astype(np.float64)
     lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
     os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device="cuda")
