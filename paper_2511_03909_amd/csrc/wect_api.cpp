@@ -349,18 +349,19 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
   pl->tt_fwd = tt_fwd;
   // Automatic one block per group (complex, direction tile) when there is at
   // least one group per compute unit: every block finishes its own groups, so
-  // there are no partial histograms and no reduction kernel.  1024-thread
-  // blocks for groups of 2048 cells or more on average, else 512.  Measured on
-  // MI355X (64 directions, T = 128): 256 images of 128^2 102 us (1024-thread
-  // groups) against 118-145 us split over blocks; 256 images of 2^2 ... 64^2,
-  // 1024 of 28^2 and 4096 of 8^2 take 15 / 16 / 17 / 22 / 37 / 45 / 101 us in
-  // groups against 332 / 35 / 21 / 41 / 54 / 74 / 179 us when a few blocks
-  // share many small groups.
+  // there are no partial histograms and no reduction kernel.  Cubical groups
+  // take 1024-thread blocks for 2048 voxels or more on average, else 512;
+  // simplicial groups the block that auto_block picks (occupancy by LDS).
+  // Measured on MI355X (64 directions, T = 128): 256 images of 128^2 102 us
+  // (1024-thread groups) against 118-145 us split over blocks; 256 images of
+  // 2^2 ... 64^2, 1024 of 28^2 and 4096 of 8^2 take 15 / 16 / 17 / 22 / 37 /
+  // 45 / 101 us in groups against 332 / 35 / 21 / 41 / 54 / 74 / 179 us when a
+  // few blocks share many small groups.
   const int64_t groups_fwd = (int64_t)c->B * ntiles;
   const int64_t S_fwd = (int64_t)ntiles * elems;
   const int decomp = g_decomp.load();
   const bool auto_group = need_fwd && decomp == 0 && g->T > 0 && S_fwd > 0 && groups_fwd >= cus;
-  const int group_block = S_fwd >= groups_fwd * 2048 ? 1024 : 512;
+  const int group_block = c->kind == WECT_CUBICAL ? (S_fwd >= groups_fwd * 2048 ? 1024 : 512) : 0;
   int block = g_block.load();
   if (ls) {
     // the coface rows of the vertex-centric kernels grow with the block:
@@ -369,7 +370,7 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     block = block ? std::min(block, fit) : fit;
     if (block == 0) block = 256;
   } else if (!block) {
-    block = auto_group ? group_block : auto_block(c, &gt, need_bwd && !need_fwd, smooth, dpl);
+    block = auto_group && group_block ? group_block : auto_block(c, &gt, need_bwd && !need_fwd, smooth, dpl);
   }
   pl->block = block;
   pl->elems = elems;
