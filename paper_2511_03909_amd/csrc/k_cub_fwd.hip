@@ -202,44 +202,50 @@ struct CubRec {
   }
 };
 
-// One thread per voxel of the batch: its complex (binary search over the
-// voxel offsets), its grid position, its neighbourhood and its records.
+// q = floor(v / n) and v - q n for v, n < 2^32, n > 0: the double-precision
+// quotient is within 2^-20 of v / n, so one correction step in either
+// direction makes it exact.
+__device__ __forceinline__ uint32_t divmod_u32(uint32_t v, uint32_t n, double inv, uint32_t& r) {
+  int64_t q = (int64_t)((double)v * inv);
+  int64_t rr = (int64_t)v - q * (int64_t)n;
+  if (rr >= (int64_t)n) { ++q; rr -= n; }
+  if (rr < 0) { --q; rr += n; }
+  r = (uint32_t)rr;
+  return (uint32_t)q;
+}
+
+// One thread per voxel: block (x, y) takes the voxels x * 256 + t,
+// + gridDim.x * 256, ... of complexes y, y + gridDim.y, ...; the grid
+// position comes from two exact double-precision divisions.
 template <int N, int WM>
 __global__ __launch_bounds__(256) void k_cub_records(Params p) {
   using RT = typename CubRec<N>::R;
   constexpr int NO = 1 << N;
-  RT* rec = (RT*)p.cub_rec;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < p.total_voxels; g += stride) {
-    int b = 0;
-    if (p.grid_off) {
-      int lo = 0, hi = p.B - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (p.grid_off[mid] <= g) lo = mid;
-        else hi = mid - 1;
-      }
-      b = lo;
-    }
+  for (int b = blockIdx.y; b < p.B; b += gridDim.y) {
     const int n0 = p.shape[3 * b], n1 = p.shape[3 * b + 1], n2 = N == 3 ? p.shape[3 * b + 2] : 1;
     const int64_t goff = off_or(p.grid_off, b, p.total_voxels);
     const int64_t aoff = p.axis_off ? p.axis_off[b] : 0;
-    const uint32_t v = (uint32_t)(g - goff);
-    const int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
-    const int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
+    const uint32_t nvox = (uint32_t)n0 * (uint32_t)n1 * (uint32_t)n2;
+    const double inv0 = 1.0 / (double)n0, inv1 = 1.0 / (double)n1;
     const float* ax0 = p.axis + aoff;
-    CubFetch<N> f;
-    f.load(p.intensity + goff, ax0, ax0 + n0, ax0 + n0 + n1, n0, n1, n2, i0, i1, i2, true);
-    int32_t cw[NO];
+    RT* rec = (RT*)p.cub_rec + goff;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += gridDim.x * blockDim.x) {
+      uint32_t i0, i1;
+      const uint32_t row = divmod_u32(v, (uint32_t)n0, inv0, i0);
+      const uint32_t i2 = divmod_u32(row, (uint32_t)n1, inv1, i1);
+      CubFetch<N> f;
+      f.load(p.intensity + goff, ax0, ax0 + n0, ax0 + n0 + n1, n0, n1, n2, (int)i0, (int)i1, (int)i2, true);
+      int32_t cw[NO];
 #pragma unroll
-    for (int o = 0; o < NO; ++o) cw[o] = 0;
-    if (f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) cub_weights<N, WM>(f, p.include_above, cw);
-    uint32_t w[NO / 2];
+      for (int o = 0; o < NO; ++o) cw[o] = 0;
+      if (f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) cub_weights<N, WM>(f, p.include_above, cw);
+      uint32_t w[NO / 2];
 #pragma unroll
-    for (int k = 0; k < NO / 2; ++k) w[k] = ((uint32_t)cw[2 * k] & 0xffffu) | ((uint32_t)cw[2 * k + 1] << 16);
-    RT out;
-    __builtin_memcpy(&out, w, sizeof(RT));
-    rec[g] = out;
+      for (int k = 0; k < NO / 2; ++k) w[k] = ((uint32_t)cw[2 * k] & 0xffffu) | ((uint32_t)cw[2 * k + 1] << 16);
+      RT out;
+      __builtin_memcpy(&out, w, sizeof(RT));
+      rec[v] = out;
+    }
   }
 }
 
@@ -458,15 +464,16 @@ static hipError_t launch_cub_fwd_d(const Params& p, int block, size_t lds, hipSt
 }
 
 hipError_t launch_cub_records(const Params& p, hipStream_t s) {
-  if (p.total_voxels <= 0) return hipSuccess;
-  int64_t blocks = (p.total_voxels + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
+  if (p.total_voxels <= 0 || p.B <= 0) return hipSuccess;
+  // blocks per complex for one voxel per thread in a complex of average size
+  const int64_t per = std::max<int64_t>(1, (p.total_voxels / p.B + 255) / 256);
+  const dim3 grid((unsigned)std::min<int64_t>(per, 65535), (unsigned)std::min(p.B, 65535));
   if (p.n == 2) {
-    if (p.wmode == WM_ONES) hipLaunchKernelGGL((k_cub_records<2, WM_ONES>), dim3((unsigned)blocks), dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((k_cub_records<2, WM_VMAX>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+    if (p.wmode == WM_ONES) hipLaunchKernelGGL((k_cub_records<2, WM_ONES>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_cub_records<2, WM_VMAX>), grid, dim3(256), 0, s, p);
   } else {
-    if (p.wmode == WM_ONES) hipLaunchKernelGGL((k_cub_records<3, WM_ONES>), dim3((unsigned)blocks), dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((k_cub_records<3, WM_VMAX>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+    if (p.wmode == WM_ONES) hipLaunchKernelGGL((k_cub_records<3, WM_ONES>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_cub_records<3, WM_VMAX>), grid, dim3(256), 0, s, p);
   }
   return hipGetLastError();
 }
