@@ -870,7 +870,7 @@ def main(argv=None):
         write_profiles(*a.write_profiles)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (sharding across GPUs is not implemented); --gpus must be 1",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
 
