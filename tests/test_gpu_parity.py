@@ -594,6 +594,34 @@ def test_cubical_staging_tiles_give_identical_integers(W):
         W.set_launch()
 
 
+def test_many_small_complexes_one_block_per_group(W):
+    """Batches with more groups than compute units run one block per group
+    (512-thread blocks for small groups): hundreds of tiny images of uneven
+    shapes, some without any vertex, and hundreds of tiny simplicial complexes
+    with two direction tiles, each against the oracle."""
+    g = np.random.default_rng(91)
+    ims = []
+    for i in range(600):
+        nx, ny = (int(v) for v in g.integers(1, 7, size=2))
+        if i % 97 == 0:
+            ims.append(synth.Cubical(np.zeros((ny, nx), np.uint8), [synth.cubical_axis(nx), synth.cubical_axis(ny)],
+                                     50, True))
+        else:
+            ims.append(synth.random_tiny_cubical(1000 + i, (nx, ny), include_above=50))
+    dirs, thr = synth.s1_directions(64), synth.uniform_thresholds(40, 1.6)
+    _say("600 tiny images, one block per group")
+    got = gpu_wect(W, ims, dirs, thr)
+    for b, C in enumerate(ims):
+        assert_match(got[b], oracle.wect(C, dirs, thr), C, f"image {b}")
+    Ks = [synth.random_tiny_complex(2000 + i, n=2, nv=7, top_dim=2, wmode="explicit", wdtype=np.int32)
+          for i in range(300)]
+    dirs2, thr2 = synth.s1_directions(70), synth.uniform_thresholds(33, 1.8)
+    _say("300 tiny complexes, d = 70, one block per group")
+    got = gpu_wect(W, Ks, dirs2, thr2)
+    for b, K in enumerate(Ks):
+        assert_match(got[b], oracle.wect(K, dirs2, thr2), K, f"complex {b}")
+
+
 @pytest.mark.parametrize("T", [255, 256, 257, 300, 500])
 def test_many_thresholds(W, T):
     """T above 256 takes the two-pass scan (row-group totals, then the scan) and smaller staging tiles."""
