@@ -60,6 +60,46 @@ __device__ __forceinline__ void filter_hist(ACC* col, const float* stage, int fi
   }
 }
 
+// As hist_entries (arithmetic index with the per-wavefront switch to the
+// guess), two pairs of entries per step: the four entries' staged words are
+// read before any of their histogram adds, so the LDS reads of the second
+// pair are in flight while the first pair's heights are formed.
+template <bool FAST, typename ACC, typename Entry>
+__device__ __forceinline__ void hist_entries_x2(ACC* col, int first, int step, int ne, const Thr& th, int* arith,
+                                                Entry entry) {
+  int e = first;
+  if constexpr (FAST) {
+    while (*arith && e + step + 1 < ne) {
+      const int stop = min(ne - 1 - step, e + 32 * step);
+      int fixes = 0, pairs = 0;
+      for (; e < stop; e += 2 * step) {
+        float h[4];
+        ACC w[4];
+        entry(e, h[0], w[0]);
+        entry(e + 1, h[1], w[1]);
+        entry(e + step, h[2], w[2]);
+        entry(e + step + 1, h[3], w[3]);
+#pragma unroll
+        for (int q = 0; q < 4; q += 2) {
+          int b0, b1;
+          const bool ok0 = thr_arith(h[q], th, b0);
+          const bool ok1 = thr_arith(h[q + 1], th, b1);
+          if (__builtin_amdgcn_ballot_w64(!(ok0 && ok1)) != 0) {
+            ++fixes;
+            if (!ok0) b0 = thr_near(h[q], b0, th);
+            if (!ok1) b1 = thr_near(h[q + 1], b1, th);
+          }
+          ++pairs;
+          lds_add(&col[b0 * W], w[q]);
+          lds_add(&col[b1 * W], w[q + 1]);
+        }
+      }
+      if (4 * fixes > pairs) *arith = 0;
+    }
+  }
+  hist_entries<FAST, ACC>(col, e, step, ne, th, arith, entry);
+}
+
 // Packed tiles (at most 32 directions or filter columns, dt of them rounded up
 // to a power of two): lane l serves column l % dt of the entries of lane group
 // g = l / dt, so 64 / dt entries share each instruction.  The wavefront's
@@ -186,7 +226,7 @@ __device__ void simp_fwd_range(const Params& p, int64_t lo, int64_t hi, int64_t 
         filter_hist<DIM, uint16_t, ACC, L>(hist + lane, stage, 2 * wave, 2 * nw, cnt, (const uint16_t*)p.vbuckets,
                                            p.d, fcol);
     } else {
-      hist_entries<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
+      hist_entries_x2<FAST, ACC>(hist + lane, 2 * wave, 2 * nw, cnt, th, &arith,
                               [&](int e, float& h, ACC& w) {
                                 const float* E = stage + e * L::STRIDE;
                                 h = max_height<N, DIM>(E, sx, sy, sz);
