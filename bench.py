@@ -591,6 +591,21 @@ def run_more(W, a, res, diff):
     res["images2d_1024x28x28_d64_T128"] = {"ms": t_b * 1e3, "items_per_s": its / t_b,
                                            "one_per_launch_ms": t_s * 1e3, "batched_speedup": t_s / t_b}
     del cxs, singles, o1s, ws1s, outs, wss
+    # the 256 images of 128^2 at 1000 and 4096 thresholds (threshold tiles: one
+    # pass over the voxels per tile of thresholds that fits LDS)
+    wi = synth.cfg2()
+    cxi = W.CubicalBatch.from_host(wi.complexes, device="cuda")
+    iti = 64 * sum(cubical_cell_count(C) for C in wi.complexes)
+    many = {}
+    for T in (1000, 4096):
+        gi = W.Grid(wi.dirs, synth.uniform_thresholds(T, 1.45), device="cuda")
+        oi = torch.empty((cxi.B, gi.d, T), dtype=torch.int32, device="cuda")
+        wsi = torch.empty(max(1, W.wect_workspace_bytes(cxi, gi)), dtype=torch.uint8, device="cuda")
+        ti = timed(lambda: W.wect_forward(cxi, gi, out=oi, ws=wsi), 10, 2)
+        many[f"T{T}"] = {"ms": ti * 1e3, "items_per_s": iti / ti}
+        del oi, wsi
+    res["images2d_256x128x128_d64_many_thresholds"] = many
+    del cxi
     thr5 = w5.thr.astype(np.float64)
     lam5 = float(np.float32(2.0 * (thr5.size - 1) / (thr5[-1] - thr5[0])))
     os5 = torch.empty((cx5.B, g5.d, g5.T), dtype=torch.float32, device="cuda")
