@@ -341,7 +341,12 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
       return ls ? wect::smooth_ls_forward_lds_bytes(t, 256) <= kLdsLimit
                 : wect::forward_lds_fixed(t, c->kind, acc_bytes, dpl) + nst * entry <= kLdsLimit;
     };
-    tt_fwd = choose_tile(g->T, [&](int t) { return fits_stage(t, 64); }, [&](int t) { return fits_stage(t, 256); });
+    // one tile when all T thresholds fit next to a wavefront's staging area;
+    // else the fewest balanced tiles that leave 448 staged cells (measured on
+    // MI355X: with several passes anyway, one more pass for a larger staging
+    // tile pays, e.g. 256 images of 128^2 at T = 4096: 8 tiles 0.89 ms
+    // against 7 tiles 1.06 ms)
+    tt_fwd = choose_tile(g->T, [&](int t) { return fits_stage(t, 64); }, [&](int t) { return fits_stage(t, 448); });
     if (tt_fwd == 0) return WECT_ERR_UNSUPPORTED;
   }
   wect_grid gt = *g;  // the grid of one forward launch: its threshold tile
