@@ -331,6 +331,42 @@ def test_launch_shapes_give_identical_integers(W):
         W.set_launch()
 
 
+def test_random_launch_knobs_give_identical_bits(W):
+    """Forty random combinations of every launch knob (block, blocks per
+    CU, minimum items, decomposition, threshold tile, directions per lane,
+    voxel records, cell packing, staging tile) on a 3D volume batch, a 2D
+    image batch and simplicial batches with integer and float32 weights: the
+    same bits as the automatic plan (integer and 64-bit fixed-point sums are
+    exact), which matches the oracle."""
+    g = np.random.default_rng(2024)
+    vols = [synth.random_tiny_cubical(s, shp, include_above=70) for s, shp in
+            enumerate(((9, 7, 5), (4, 11, 3), (6, 6, 6)))]
+    ims, Ks = _uneven_batches()
+    Kf = [synth.random_tiny_complex(40 + s, n=3, nv=10, top_dim=3, wdtype=np.float32) for s in range(4)]
+    cases = [(vols, synth.fibonacci_directions(150), synth.uniform_thresholds(100, 2.0)),
+             (ims, synth.s1_directions(20), synth.uniform_thresholds(61, 1.7)),
+             (Ks, synth.s1_directions(90), synth.uniform_thresholds(100, 1.8)),
+             (Kf, synth.fibonacci_directions(30), synth.uniform_thresholds(300, 2.2))]
+    try:
+        for ci, (Cs, dirs, thr) in enumerate(cases):
+            W.set_launch()
+            ref = gpu_wect(W, Cs, dirs, thr)
+            for b, C in enumerate(Cs):
+                assert_match(ref[b], oracle.wect(C, dirs, thr), C, f"case {ci} complex {b}")
+            for trial in range(10):
+                knobs = dict(block=int(g.choice([0, 256, 512, 1024])), blocks_per_cu=int(g.choice([0, 1, 2])),
+                             min_items_per_block=int(g.choice([0, 64, 5000])), decomposition=int(g.choice([0, 1, 2])),
+                             threshold_tile=int(g.choice([0, 7, 33, 64])),
+                             directions_per_lane=int(g.choice([0, 1, 2])), cubical_records=int(g.choice([0, 1, 2])),
+                             cell_packing=int(g.choice([0, 1])), stage_entries=int(g.choice([0, 64, 192, 448, 1024])))
+                _say(f"case {ci} trial {trial}: {knobs}")
+                W.set_launch(**knobs)
+                got = gpu_wect(W, Cs, dirs, thr)
+                assert np.array_equal(got.view(np.int32), ref.view(np.int32)), f"case {ci}: {knobs}"
+    finally:
+        W.set_launch()
+
+
 def _uneven_batches():
     ims = [synth.random_tiny_cubical(s, shp, include_above=80) for s, shp in
            enumerate(((12, 9), (3, 17), (20, 1), (7, 7), (16, 11), (9, 30), (2, 2), (25, 13)))]
