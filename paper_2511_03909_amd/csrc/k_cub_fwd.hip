@@ -28,9 +28,11 @@ namespace {
 // i1 + n1 i2 of its grid row.  The 32-byte 3D entry leaves room for a larger
 // staging tile next to the histogram of two directions per lane; a lane
 // extracts its orthant's half with one bitfield extract.  Entries of one row
-// share y s_y and z s_z, so the histogram keeps them per wavefront and
-// recomputes them only when the row changes: the height ((x s_x) + (y s_y)) +
-// (z s_z) keeps its operations and their order.
+// share y s_y and z s_z, so each wavefront walks a contiguous run of entries,
+// two at a time, keeps the row terms once for the first and once for the
+// second entry of its pairs, and recomputes them only when the row changes:
+// the height ((x s_x) + (y s_y)) + (z s_z) keeps its operations and their
+// order.
 template <int N>
 struct CubLayout {
   static constexpr int NO = 1 << N;                 // orthants
@@ -268,10 +270,14 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
   const float* ax1 = ax0 + n0;
   const float* ax2 = ax1 + n1;
   int arith = th.arith;
-  uint32_t row = 0xffffffffu;  // no row yet (row indices are below 2^31)
-  float ysy[DPL], zsz[DPL];
+  // 3D: y s_y and z s_z of the row last seen, one cache per entry slot of a
+  // pair (no row yet: row indices are below 2^31)
+  uint32_t row[2] = {0xffffffffu, 0xffffffffu};
+  float ysy[2][DPL], zsz[2][DPL];
 #pragma unroll
-  for (int k = 0; k < DPL; ++k) ysy[k] = zsz[k] = 0.0f;
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int k = 0; k < DPL; ++k) ysy[j][k] = zsz[j][k] = 0.0f;
   // grid position of the thread's voxel lo + tid, advanced by TS voxels per
   // tile without division (voxel counts of one complex are below 2^31)
   const uint32_t ts = (uint32_t)TS;
@@ -350,43 +356,56 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
       wo[k] = L::COFF + (L::PACKED ? orth[k] >> 1 : orth[k]);
       sh[k] = L::PACKED ? (orth[k] & 1) * 16 : 0;
     }
+    // the stage's address held in a vector register, so that the entry reads
+    // of one step share one address register instead of copying a scalar one
+    uint32_t vz;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+    const float* vstage = stage + vz;
     auto weight = [&](const float* E, int k) -> uint32_t {
       const uint32_t x = bitcast<uint32_t>(E[wo[k]]);
       if constexpr (L::PACKED) return (uint32_t)__builtin_amdgcn_sbfe((int)x, (unsigned)sh[k], 16u);
       else return x;
     };
-    // 3D: y s_y and z s_z of the row last seen by this wavefront
-    auto row_terms = [&](const float* E) {
+    auto row_terms = [&](const float* E, int j) {
       if constexpr (N == 3) {
         const uint32_t r = __builtin_amdgcn_readfirstlane(bitcast<uint32_t>(E[L::ROW]));
-        if (r != row) {
-          row = r;
+        if (r != row[j]) {
+          row[j] = r;
 #pragma unroll
           for (int k = 0; k < DPL; ++k) {
-            ysy[k] = E[1] * sy[k];
-            zsz[k] = E[2] * sz[k];
+            ysy[j][k] = E[1] * sy[k];
+            zsz[j][k] = E[2] * sz[k];
           }
         }
       }
     };
-    auto hgt = [&](const float* E, int k) -> float {
-      if constexpr (N == 3) return (E[0] * sx[k] + ysy[k]) + zsz[k];
+    auto hgt = [&](const float* E, int j, int k) -> float {
+      if constexpr (N == 3) return (E[0] * sx[k] + ysy[j][k]) + zsz[j][k];
       else return height<N>(E, sx[k], sy[k], sz[k]);
     };
     if constexpr (DPL == 1) {
       hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
                                    [&](int e, float& h, uint32_t& w) {
                                      const float* E = stage + e * L::STRIDE;
-                                     row_terms(E);
-                                     h = hgt(E, 0);
+                                     row_terms(E, 0);
+                                     h = hgt(E, 0, 0);
                                      w = weight(E, 0);
                                    });
     } else {
-      hist_entries2<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
-                                    [&](int e, int k, float& h, uint32_t& w) {
-                                      const float* E = stage + e * L::STRIDE;
-                                      if (k == 0) row_terms(E);  // k = 1 follows for the same entry
-                                      h = hgt(E, k);
+      // 3D: every wavefront takes a contiguous run of entries, so that its
+      // row terms change only where the run crosses a grid row
+      int first = 2 * wave, step = 2 * nw, last = ne;
+      if constexpr (N == 3) {
+        const int run = 2 * ((ne + 2 * nw - 1) / (2 * nw));
+        first = min(ne, wave * run);
+        last = min(ne, first + run);
+        step = 2;
+      }
+      hist_entries2<FAST, uint32_t>(hist + lane, first, step, last, th, &arith,
+                                    [&](int e, int j, int k, float& h, uint32_t& w) {
+                                      const float* E = vstage + e * L::STRIDE;
+                                      if (k == 0) row_terms(E, j);  // k = 1 follows for the same entry
+                                      h = hgt(E, j, k);
                                       w = weight(E, k);
                                     });
     }

@@ -286,9 +286,10 @@ __device__ __forceinline__ void hist_entries(ACC* col, int first, int step, int 
 
 // As hist_entries for entries that serve two directions per lane (a tile of
 // 128 directions: column `lane` for the first, `lane + 64` for the second,
-// rows 128 wide).  entry(e, k, h, w) gives the height and weight of entry e
-// for the lane's k-th direction; it is called for k = 0 and then k = 1 of one
-// entry before the next entry.  The index mode switch is per wavefront as in
+// rows 128 wide).  entry(e, j, k, h, w) gives the height and weight of entry
+// e for the lane's k-th direction; it is called for k = 0 and then k = 1 of one
+// entry before the next entry, with j = 0 for the first entry of a pair and
+// j = 1 for the second (j = 0 for a lone last entry).  The index mode switch is per wavefront as in
 // hist_entries, counted over both directions.
 template <bool FAST, typename ACC, typename Entry>
 __device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int ne, const Thr& th, int* arith,
@@ -305,7 +306,7 @@ __device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-          for (int k = 0; k < 2; ++k) entry(e + j, k, h[j][k], w[j][k]);
+          for (int k = 0; k < 2; ++k) entry(e + j, j, k, h[j][k], w[j][k]);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           int b0, b1;
@@ -330,7 +331,7 @@ __device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int k = 0; k < 2; ++k) entry(e + j, k, h[j][k], w[j][k]);
+      for (int k = 0; k < 2; ++k) entry(e + j, j, k, h[j][k], w[j][k]);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       lds_add(&col[thr_index<FAST>(h[0][k], th) * RW + k * W], w[0][k]);
@@ -341,7 +342,7 @@ __device__ __forceinline__ void hist_entries2(ACC* col, int first, int step, int
     float h[2];
     ACC w[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) entry(e, k, h[k], w[k]);
+    for (int k = 0; k < 2; ++k) entry(e, 0, k, h[k], w[k]);
 #pragma unroll
     for (int k = 0; k < 2; ++k) lds_add(&col[thr_index<FAST>(h[k], th) * RW + k * W], w[k]);
   }
