@@ -294,9 +294,13 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     else f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, active);
   };
   fetch(v < (uint32_t)hi && tid < TS);
-  for (int64_t t0 = lo; t0 < hi; t0 += TS) {
-    if (tid == 0) *counter = 0;
-    __syncthreads();
+  // two compaction counters take turns: the one of the next tile is cleared
+  // once every wavefront has read this tile's count, so a tile needs two block
+  // barriers instead of three
+  if (tid == 0) counter[0] = counter[1] = 0;
+  __syncthreads();
+  int par = 0;
+  for (int64_t t0 = lo; t0 < hi; t0 += TS, par ^= 1) {
     bool keep = false;
     int32_t cw[L::NO];
     uint32_t pk[L::NO / 2];
@@ -318,7 +322,7 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     // compact the contributing vertices
     const uint64_t bal = __ballot(keep);
     int base = 0;
-    if (lane == 0 && bal) base = atomicAdd(counter, __popcll(bal));
+    if (lane == 0 && bal) base = atomicAdd(counter + par, __popcll(bal));
     base = __shfl(base, 0);
     if (keep) {
       const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
@@ -348,7 +352,10 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     v += ts;
     fetch(v < (uint32_t)hi && tid < TS);
     __syncthreads();
-    const int ne = uniform(*counter);
+    const int ne = uniform(counter[par]);
+    // the other counter was last read before this barrier; the barrier that
+    // ends this tile orders the clearing before the next tile's additions
+    if (tid == 0) counter[par ^ 1] = 0;
     // the lane's combined weight within an entry: word wo[k], bits sh[k] .. sh[k] + 15 when packed
     int wo[DPL], sh[DPL];
 #pragma unroll
