@@ -294,9 +294,9 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     else f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, active);
   };
   fetch(v < (uint32_t)hi && tid < TS);
-  // two compaction counters take turns: the one of the next tile is cleared
-  // once every wavefront has read this tile's count, so a tile needs two block
-  // barriers instead of three
+  // two compaction counters take turns, so that clearing one needs no block
+  // barrier of its own: a tile has two, after its staging and after its
+  // histogram
   if (tid == 0) counter[0] = counter[1] = 0;
   __syncthreads();
   int par = 0;
@@ -351,11 +351,13 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
     i2 += (int)s2 + carry;
     v += ts;
     fetch(v < (uint32_t)hi && tid < TS);
+    // the next tile's counter: its last readers read it before the barrier
+    // that ended the previous tile, and the barrier below (which waits for the
+    // wavefront's LDS writes) orders the clearing before the next tile's
+    // additions
+    if (tid == 0) counter[par ^ 1] = 0;
     __syncthreads();
     const int ne = uniform(counter[par]);
-    // the other counter was last read before this barrier; the barrier that
-    // ends this tile orders the clearing before the next tile's additions
-    if (tid == 0) counter[par ^ 1] = 0;
     // the lane's combined weight within an entry: word wo[k], bits sh[k] .. sh[k] + 15 when packed
     int wo[DPL], sh[DPL];
 #pragma unroll
@@ -416,8 +418,14 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
                                       w = weight(E, k);
                                     });
     }
-    __syncthreads();
+    // end of the tile: every wavefront has used the values of all its reads of
+    // the stage (they fed its atomics), so the next tile may overwrite it once
+    // all have arrived; the histogram additions still in flight need no wait
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
   }
+  __syncthreads();  // every addition has landed before the caller reads the histogram
 }
 
 template <int N, int WM, int DPL, bool PRE>
