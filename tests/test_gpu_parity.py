@@ -367,6 +367,36 @@ def test_random_launch_knobs_give_identical_bits(W):
         W.set_launch()
 
 
+def test_cubical_sparse_volumes_empty_staging_tiles(W):
+    """Volumes whose included voxels sit in three small blobs, so that most
+    staging tiles stage nothing: the alternating compaction counters and the
+    tile barriers meet empty tiles, in stream mode with several blocks per
+    group, with and without voxel records and with small staging and
+    threshold tiles; against the oracle."""
+    g = np.random.default_rng(77)
+    vols = []
+    for n2, n1, n0 in ((30, 24, 40), (12, 50, 33)):
+        a = np.zeros((n2, n1, n0), np.uint8)
+        for _ in range(3):
+            c = [int(g.integers(0, n)) for n in (n2, n1, n0)]
+            sl = tuple(slice(max(0, ci - 2), ci + 3) for ci in c)
+            a[sl] = g.integers(1, 256, size=a[sl].shape)
+        vols.append(synth.Cubical(a, [synth.cubical_axis(n0), synth.cubical_axis(n1), synth.cubical_axis(n2)], 0, True))
+    dirs, thr = synth.fibonacci_directions(200), synth.uniform_thresholds(50, 2.0)
+    refs = [oracle.wect(C, dirs, thr) for C in vols]
+    try:
+        for knobs in (dict(), dict(decomposition=W.DECOMP_STREAM, min_items_per_block=64),
+                      dict(decomposition=W.DECOMP_STREAM, min_items_per_block=64, cubical_records=1),
+                      dict(cubical_records=2, stage_entries=64, threshold_tile=17)):
+            _say(f"sparse volumes {knobs}")
+            W.set_launch(**knobs)
+            got = gpu_wect(W, vols, dirs, thr)
+            for b, C in enumerate(vols):
+                assert_match(got[b], refs[b], C, f"{knobs} volume {b}")
+    finally:
+        W.set_launch()
+
+
 def _uneven_batches():
     ims = [synth.random_tiny_cubical(s, shp, include_above=80) for s, shp in
            enumerate(((12, 9), (3, 17), (20, 1), (7, 7), (16, 11), (9, 30), (2, 2), (25, 13)))]
