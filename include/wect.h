@@ -425,12 +425,17 @@ const char* wect_status_string(wect_status s);
  *   LDS, else 1; 1 or 2 to choose).  With 2, every staged voxel (its 3^n
  *   neighbourhood and combined weights) serves two directions per lane.
  *   Simplicial complexes always use 1.
- * cubical_records: 0 = automatic, 1 = off, 2 = on.  When on, the cubical
- *   forward first forms every voxel's 2^n combined weights once into records
- *   (8 bytes per voxel in 2D, 16 in 3D, part of the workspace) and stages
- *   those instead of the voxel's 3^n neighbourhood; automatic turns it on when
- *   a voxel would otherwise be staged more than once (several direction or
- *   threshold tiles).  wect_forward_noalloc never uses records.
+ * cubical_records: 0 = automatic, 1 = off, 2 = on, 3 = on with two voxels
+ *   per thread.  When on, the cubical forward first forms every voxel's 2^n
+ *   combined weights once into records (8 bytes per voxel in 2D, 16 in 3D,
+ *   part of the workspace) and stages those instead of the voxel's 3^n
+ *   neighbourhood; automatic turns it on when a voxel would otherwise be
+ *   staged more than once (several direction or threshold tiles).  With 3, a
+ *   tile covers 1.5 staging tiles of voxels, two per thread, and the
+ *   contributing ones that do not fit the stage go in a second round of the
+ *   same tile (fewer tiles and block barriers per voxel); automatic does this
+ *   when every block walks at least 16 tiles.  wect_forward_noalloc never uses
+ *   records.
  * cell_packing: 0 = automatic, 1 = off.  With at most 32 directions (or
  *   filter columns of the general-filter WECF) the simplicial forward packs
  *   64 / dt cells into each wavefront instruction, dt being the smallest

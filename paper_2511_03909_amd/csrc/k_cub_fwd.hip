@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_cub_records(Params p) {
 // Forward over the voxels [lo, hi) of complex b for one direction tile (DPL
 // directions per lane): the neighbourhoods (or records, PRE) of tile t+1 are
 // loaded while the histogram of tile t runs.
-template <int N, int WM, bool FAST, int DPL, bool PRE>
+template <int N, int WM, bool FAST, int DPL, bool PRE, bool TWO>
 __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, const float (&sx)[DPL],
                               const float (&sy)[DPL], const float (&sz)[DPL], const int (&orth)[DPL],
                               uint32_t* hist, float* stage, int* counter, const Thr& th) {
@@ -278,120 +278,92 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
   for (int j = 0; j < 2; ++j)
 #pragma unroll
     for (int k = 0; k < DPL; ++k) ysy[j][k] = zsz[j][k] = 0.0f;
-  // grid position of the thread's voxel lo + tid, advanced by TS voxels per
+  // voxels per tile: TS (one per thread), or with TWO up to two per thread
+  // (lo + tid and lo + blockDim + tid); the contributing vertices past the
+  // stage's TS entries then go in a second round of the same tile
+  const int BD = blockDim.x;
+  const int TV = TWO ? min(p.stage_vox, min(2 * TS, 2 * BD)) : TS;
+  const int TV0 = min(TV, BD);
+  // grid position of the thread's voxel lo + tid, advanced by TV voxels per
   // tile without division (voxel counts of one complex are below 2^31)
-  const uint32_t ts = (uint32_t)TS;
+  const uint32_t ts = (uint32_t)TV;
   const uint32_t s0 = ts % (uint32_t)n0, s1 = (ts / (uint32_t)n0) % (uint32_t)n1;
   const uint32_t s2 = ts / ((uint32_t)n0 * (uint32_t)n1);
   uint32_t v = (uint32_t)(lo + tid);
   int i0 = (int)(v % (uint32_t)n0), i1 = (int)((v / (uint32_t)n0) % (uint32_t)n1);
   int i2 = (int)(v / ((uint32_t)n0 * (uint32_t)n1));
+  // TWO: the second voxel v + BD
+  uint32_t v2 = v + (uint32_t)BD;
+  int j0 = 0, j1 = 0, j2 = 0;
+  if constexpr (TWO) {
+    j0 = (int)(v2 % (uint32_t)n0);
+    j1 = (int)((v2 / (uint32_t)n0) % (uint32_t)n1);
+    j2 = (int)(v2 / ((uint32_t)n0 * (uint32_t)n1));
+  }
   using Fetch = typename std::conditional<PRE, CubRec<N>, CubFetch<N>>::type;
   const typename CubRec<N>::R* rec = (const typename CubRec<N>::R*)p.cub_rec + goff;
-  Fetch f;
-  auto fetch = [&](bool active) {
+  Fetch f, f2;
+  auto fetch = [&]() {
+    const bool active = v < (uint32_t)hi && tid < TV0;
     if constexpr (PRE) f.load(rec, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, v, active);
     else f.load(vol, ax0, ax1, ax2, n0, n1, n2, i0, i1, i2, active);
+    if constexpr (TWO) f2.load(rec, ax0, ax1, ax2, n0, n1, n2, j0, j1, j2, v2, v2 < (uint32_t)hi && BD + tid < TV);
   };
-  fetch(v < (uint32_t)hi && tid < TS);
-  // two compaction counters take turns, so that clearing one needs no block
-  // barrier of its own: a tile has two, after its staging and after its
-  // histogram
-  if (tid == 0) counter[0] = counter[1] = 0;
-  __syncthreads();
-  int par = 0;
-  for (int64_t t0 = lo; t0 < hi; t0 += TS, par ^= 1) {
-    bool keep = false;
-    int32_t cw[L::NO];
-    uint32_t pk[L::NO / 2];
-    if constexpr (PRE && L::PACKED) {
-      keep = f.packed(pk);
-    } else if constexpr (PRE) {
-      keep = f.weights(cw);
-    } else if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
-      cub_weights<N, WM>(f, p.include_above, cw);
-      bool nz = false;
-#pragma unroll
-      for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
-      keep = nz;
+  fetch();
+  // the staged entry of a contributing vertex: coordinates, grid row and
+  // combined weights (packed int16 pairs in 3D, int32 in 2D)
+  auto put = [&](int slot, float cx, float cy, float cz, int a1, int a2, const uint32_t* pk, const int32_t* cw) {
+    float* E = stage + slot * L::STRIDE;
+    E[0] = cx;
+    E[1] = cy;
+    if constexpr (N == 3) {
+      E[2] = cz;
+      E[L::ROW] = bitcast<float>((uint32_t)a1 + (uint32_t)n1 * (uint32_t)a2);
     }
-    if constexpr (L::PACKED && !PRE) {
+    if constexpr (L::PACKED) {
 #pragma unroll
-      for (int k = 0; k < L::NO / 2; ++k) pk[k] = ((uint32_t)cw[2 * k] & 0xffffu) | ((uint32_t)cw[2 * k + 1] << 16);
+      for (int k = 0; k < L::NO / 2; ++k) E[L::COFF + k] = bitcast<float>(pk[k]);
+    } else {
+#pragma unroll
+      for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
     }
-    // compact the contributing vertices
-    const uint64_t bal = __ballot(keep);
-    int base = 0;
-    if (lane == 0 && bal) base = atomicAdd(counter + par, __popcll(bal));
-    base = __shfl(base, 0);
-    if (keep) {
-      const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
-      float* E = stage + slot * L::STRIDE;
-      E[0] = f.cx;
-      E[1] = f.cy;
-      if constexpr (N == 3) {
-        E[2] = f.cz;
-        E[L::ROW] = bitcast<float>((uint32_t)i1 + (uint32_t)n1 * (uint32_t)i2);
-      }
-      if constexpr (L::PACKED) {
+  };
+  // the lane's combined weight within an entry: word wo[k], bits sh[k] .. sh[k] + 15 when packed
+  int wo[DPL], sh[DPL];
 #pragma unroll
-        for (int k = 0; k < L::NO / 2; ++k) E[L::COFF + k] = bitcast<float>(pk[k]);
-      } else {
+  for (int k = 0; k < DPL; ++k) {
+    wo[k] = L::COFF + (L::PACKED ? orth[k] >> 1 : orth[k]);
+    sh[k] = L::PACKED ? (orth[k] & 1) * 16 : 0;
+  }
+  auto weight = [&](const float* E, int k) -> uint32_t {
+    const uint32_t x = bitcast<uint32_t>(E[wo[k]]);
+    if constexpr (L::PACKED) return (uint32_t)__builtin_amdgcn_sbfe((int)x, (unsigned)sh[k], 16u);
+    else return x;
+  };
+  auto row_terms = [&](const float* E, int j) {
+    if constexpr (N == 3) {
+      const uint32_t r = __builtin_amdgcn_readfirstlane(bitcast<uint32_t>(E[L::ROW]));
+      if (r != row[j]) {
+        row[j] = r;
 #pragma unroll
-        for (int o = 0; o < L::NO; ++o) E[L::COFF + o] = bitcast<float>(cw[o]);
+        for (int k = 0; k < DPL; ++k) {
+          ysy[j][k] = E[1] * sy[k];
+          zsz[j][k] = E[2] * sz[k];
+        }
       }
     }
-    // neighbourhoods of the next tile (in flight during this tile's histogram)
-    i0 += (int)s0;
-    int carry = i0 >= n0;
-    i0 -= carry ? n0 : 0;
-    i1 += (int)s1 + carry;
-    carry = i1 >= n1;
-    i1 -= carry ? n1 : 0;
-    i2 += (int)s2 + carry;
-    v += ts;
-    fetch(v < (uint32_t)hi && tid < TS);
-    // the next tile's counter: its last readers read it before the barrier
-    // that ended the previous tile, and the barrier below (which waits for the
-    // wavefront's LDS writes) orders the clearing before the next tile's
-    // additions
-    if (tid == 0) counter[par ^ 1] = 0;
-    __syncthreads();
-    const int ne = uniform(counter[par]);
-    // the lane's combined weight within an entry: word wo[k], bits sh[k] .. sh[k] + 15 when packed
-    int wo[DPL], sh[DPL];
-#pragma unroll
-    for (int k = 0; k < DPL; ++k) {
-      wo[k] = L::COFF + (L::PACKED ? orth[k] >> 1 : orth[k]);
-      sh[k] = L::PACKED ? (orth[k] & 1) * 16 : 0;
-    }
+  };
+  auto hgt = [&](const float* E, int j, int k) -> float {
+    if constexpr (N == 3) return (E[0] * sx[k] + ysy[j][k]) + zsz[j][k];
+    else return height<N>(E, sx[k], sy[k], sz[k]);
+  };
+  // the histogram of the ne entries in the stage
+  auto histogram = [&](int ne) {
     // the stage's address held in a vector register, so that the entry reads
     // of one step share one address register instead of copying a scalar one
     uint32_t vz;
     asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
     const float* vstage = stage + vz;
-    auto weight = [&](const float* E, int k) -> uint32_t {
-      const uint32_t x = bitcast<uint32_t>(E[wo[k]]);
-      if constexpr (L::PACKED) return (uint32_t)__builtin_amdgcn_sbfe((int)x, (unsigned)sh[k], 16u);
-      else return x;
-    };
-    auto row_terms = [&](const float* E, int j) {
-      if constexpr (N == 3) {
-        const uint32_t r = __builtin_amdgcn_readfirstlane(bitcast<uint32_t>(E[L::ROW]));
-        if (r != row[j]) {
-          row[j] = r;
-#pragma unroll
-          for (int k = 0; k < DPL; ++k) {
-            ysy[j][k] = E[1] * sy[k];
-            zsz[j][k] = E[2] * sz[k];
-          }
-        }
-      }
-    };
-    auto hgt = [&](const float* E, int j, int k) -> float {
-      if constexpr (N == 3) return (E[0] * sx[k] + ysy[j][k]) + zsz[j][k];
-      else return height<N>(E, sx[k], sy[k], sz[k]);
-    };
     if constexpr (DPL == 1) {
       hist_entries<FAST, uint32_t>(hist + lane, 2 * wave, 2 * nw, ne, th, &arith,
                                    [&](int e, float& h, uint32_t& w) {
@@ -418,12 +390,118 @@ __device__ void cub_fwd_range(const Params& p, int b, int64_t lo, int64_t hi, co
                                       w = weight(E, k);
                                     });
     }
-    // end of the tile: every wavefront has used the values of all its reads of
-    // the stage (they fed its atomics), so the next tile may overwrite it once
-    // all have arrived; the histogram additions still in flight need no wait
+  };
+  // every wavefront has used the values of all its reads of the stage (they
+  // fed its atomics), so the stage may be overwritten once all have arrived;
+  // the histogram additions still in flight need no wait
+  auto stage_free = [&]() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
+  };
+  const double inv0 = 1.0 / (double)n0, inv1 = 1.0 / (double)n1;
+  // two compaction counters take turns, so that clearing one needs no block
+  // barrier of its own: a tile has two, after its staging and after its
+  // histogram
+  if (tid == 0) counter[0] = counter[1] = 0;
+  __syncthreads();
+  int par = 0;
+  for (int64_t t0 = lo; t0 < hi; t0 += TV, par ^= 1) {
+    bool keep = false, keep2 = false;
+    int32_t cw[L::NO], cw2[L::NO];
+    uint32_t pk[L::NO / 2], pk2[L::NO / 2];
+    if constexpr (PRE && L::PACKED) {
+      keep = f.packed(pk);
+      if constexpr (TWO) keep2 = f2.packed(pk2);
+    } else if constexpr (PRE) {
+      keep = f.weights(cw);
+      if constexpr (TWO) keep2 = f2.weights(cw2);
+    } else if (f.valid && f.nb[(CubFetch<N>::M - 1) / 2] > p.include_above) {
+      cub_weights<N, WM>(f, p.include_above, cw);
+      bool nz = false;
+#pragma unroll
+      for (int o = 0; o < L::NO; ++o) nz = nz || (cw[o] != 0);
+      keep = nz;
+    }
+    if constexpr (L::PACKED && !PRE) {
+#pragma unroll
+      for (int k = 0; k < L::NO / 2; ++k) pk[k] = ((uint32_t)cw[2 * k] & 0xffffu) | ((uint32_t)cw[2 * k + 1] << 16);
+    }
+    // compact the contributing vertices: this thread's first voxel, then (TWO)
+    // its second, each wavefront reserving one range for both
+    const uint64_t bal = __ballot(keep);
+    const uint64_t bal2 = TWO ? __ballot(keep2) : 0ull;
+    int base = 0;
+    if (lane == 0 && (bal | bal2)) base = atomicAdd(counter + par, __popcll(bal) + __popcll(bal2));
+    base = __shfl(base, 0);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int slot = base + __popcll(bal & below);
+    const int slot2 = base + __popcll(bal) + __popcll(bal2 & below);
+    // TWO: entries past the stage wait for the second round (slot - TS)
+    uint32_t dv = 0, dv2 = 0;
+    int dslot = -1, dslot2 = -1;
+    if (keep) {
+      if (!TWO || slot < TS) put(slot, f.cx, f.cy, f.cz, i1, i2, pk, cw);
+      else dslot = slot - TS, dv = v;
+    }
+    if constexpr (TWO) {
+      if (keep2) {
+        if (slot2 < TS) put(slot2, f2.cx, f2.cy, f2.cz, j1, j2, pk2, cw2);
+        else dslot2 = slot2 - TS, dv2 = v2;
+      }
+    }
+    // neighbourhoods of the next tile (in flight during this tile's histogram)
+    i0 += (int)s0;
+    int carry = i0 >= n0;
+    i0 -= carry ? n0 : 0;
+    i1 += (int)s1 + carry;
+    carry = i1 >= n1;
+    i1 -= carry ? n1 : 0;
+    i2 += (int)s2 + carry;
+    v += ts;
+    if constexpr (TWO) {
+      j0 += (int)s0;
+      carry = j0 >= n0;
+      j0 -= carry ? n0 : 0;
+      j1 += (int)s1 + carry;
+      carry = j1 >= n1;
+      j1 -= carry ? n1 : 0;
+      j2 += (int)s2 + carry;
+      v2 += ts;
+    }
+    fetch();
+    // the next tile's counter: its last readers read it before the barrier
+    // that ended the previous tile, and the barrier below (which waits for the
+    // wavefront's LDS writes) orders the clearing before the next tile's
+    // additions
+    if (tid == 0) counter[par ^ 1] = 0;
+    __syncthreads();
+    const int ne = uniform(counter[par]);
+    histogram(min(ne, TS));
+    if constexpr (TWO) {
+      if (ne > TS) {  // the same for every thread: the stage overflowed
+        stage_free();
+        // the deferred vertices: their records again (from cache), their
+        // grid positions by division
+        auto refetch = [&](int ds, uint32_t u) {
+          uint32_t a0, a1;
+          const uint32_t r = divmod_u32(u, (uint32_t)n0, inv0, a0);
+          const uint32_t a2 = divmod_u32(r, (uint32_t)n1, inv1, a1);
+          CubRec<N> g;
+          g.load(rec, ax0, ax1, ax2, n0, n1, n2, (int)a0, (int)a1, (int)a2, u, true);
+          int32_t gw[L::NO];
+          uint32_t gp[L::NO / 2];
+          if constexpr (L::PACKED) g.packed(gp);
+          else g.weights(gw);
+          put(ds, g.cx, g.cy, g.cz, (int)a1, (int)a2, gp, gw);
+        };
+        if (dslot >= 0) refetch(dslot, dv);
+        if (dslot2 >= 0) refetch(dslot2, dv2);
+        __syncthreads();
+        histogram(ne - TS);
+      }
+    }
+    stage_free();
   }
   __syncthreads();  // every addition has landed before the caller reads the histogram
 }
@@ -465,8 +543,13 @@ __global__ __launch_bounds__(1024) void k_cub_fwd(Params p) {
       load_dir(p, t * W * DPL + j * W + lane, sx[j], sy[j], sz[j]);
       orth[j] = (sx[j] < 0.0f ? 1 : 0) | (sy[j] < 0.0f ? 2 : 0) | (sz[j] < 0.0f ? 4 : 0);
     }
-    if (th.fast) cub_fwd_range<N, WM, true, DPL, PRE>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
-    else cub_fwd_range<N, WM, false, DPL, PRE>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    if (PRE && p.stage_vox > p.stage) {
+      if (th.fast) cub_fwd_range<N, WM, true, DPL, PRE, PRE>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+      else cub_fwd_range<N, WM, false, DPL, PRE, PRE>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    } else {
+      if (th.fast) cub_fwd_range<N, WM, true, DPL, PRE, false>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+      else cub_fwd_range<N, WM, false, DPL, PRE, false>(p, b, e0, e1, sx, sy, sz, orth, hist, stage, counter, th);
+    }
     end_group<uint32_t>(p, hist, k, b, t, e0 == 0 && e1 == nb, 0);
     pos += e1 - e0;
     if (e1 == nb && t == gpc - 1) ++b;

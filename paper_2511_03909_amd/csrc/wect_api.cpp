@@ -58,7 +58,7 @@ std::atomic<int> g_min_items{256};
 std::atomic<int> g_decomp{0};  // wect_launch.decomposition
 std::atomic<int> g_ttile{0};   // wect_launch.threshold_tile (0: automatic)
 std::atomic<int> g_dpl{0};     // wect_launch.directions_per_lane (0: automatic)
-std::atomic<int> g_rec{0};     // wect_launch.cubical_records (0: automatic, 1: off, 2: on)
+std::atomic<int> g_rec{0};     // wect_launch.cubical_records (0: automatic, 1: off, 2: on, 3: on, two voxels per thread)
 std::atomic<int> g_pack{0};    // wect_launch.cell_packing (0: automatic, 1: off)
 std::atomic<int> g_stage{0};   // wect_launch.stage_entries (0: automatic)
 
@@ -91,6 +91,7 @@ struct Plan {
   size_t partial_bytes = 0, dsum_bytes = 0, absmax_bytes = 0;
   size_t vb_bytes = 0;        // general-filter WECF: threshold indices of the filter values
   size_t rec_bytes = 0;       // cubical: per-voxel records of combined weights
+  bool two_vox = false;       // cubical with records: two voxels per thread and tile
   bool split = false;
   bool group_mode = false;
   size_t ws_fwd = 0, ws_bwd = 0;
@@ -438,8 +439,15 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
     // (the workspace then stays at the partial histograms).
     const int64_t reuse = (int64_t)ntiles * ceil_div(g->T, tt_fwd);
     const int rec_knob = g_rec.load();
-    if (c->kind == WECT_CUBICAL && !lean && rec_knob != 1 && (reuse >= 2 || rec_knob == 2))
+    if (c->kind == WECT_CUBICAL && !lean && rec_knob != 1 && (reuse >= 2 || rec_knob >= 2))
       pl->rec_bytes = align256((size_t)c->total_voxels * (c->n == 3 ? 16 : 8));
+    // With records, a tile of 1.5 stages of voxels (two per thread, the
+    // contributing ones past the stage in a second round) means fewer tiles
+    // and block barriers per voxel; automatic when every block walks many
+    // tiles (measured on MI355X: 16 volumes 64^3 - 192^3 at d = 512, 3.31 ->
+    // 3.27 ms; 3 volumes of sides 9 - 40, 34 -> 36 us, hence the bound)
+    if (pl->rec_bytes)
+      pl->two_vox = rec_knob == 3 || (rec_knob == 0 && pl->S_fwd >= 16 * (int64_t)pl->stage_fwd * std::max(1, pl->G_fwd));
     pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes + pl->rec_bytes;
     p.nabsmax = absmax ? wect::kAbsmaxSlots : 0;
     p.cells_total = (double)std::max<int64_t>(cells, 1);
@@ -518,6 +526,10 @@ wect_status run_forward(const Plan& pl0, void* out, void* ws, size_t ws_bytes, h
   p.G = pl.G_fwd;
   p.S = pl.S_fwd;
   p.stage = pl.stage_fwd;
+  // 1.5 stages of voxels per tile: about 55 % of the voxels of a volume contribute, so the stage rarely
+  // overflows into the second round
+  p.stage_vox = pl.two_vox ? std::min(2 * pl.block, (3 * pl.stage_fwd / 2) / 64 * 64) : 0;
+  if (p.stage_vox <= p.stage) p.stage_vox = 0;
   p.ldo = Tfull;
   const bool prof = g_profile.load() != 0;
   if (p.nabsmax > 0) {
@@ -944,7 +956,7 @@ wect_status wect_set_launch(const wect_launch* l) {
   if (l->decomposition < 0 || l->decomposition > 2) return WECT_ERR_ARG;
   if (l->threshold_tile < 0) return WECT_ERR_ARG;
   if (l->directions_per_lane < 0 || l->directions_per_lane > 2) return WECT_ERR_ARG;
-  if (l->cubical_records < 0 || l->cubical_records > 2) return WECT_ERR_ARG;
+  if (l->cubical_records < 0 || l->cubical_records > 3) return WECT_ERR_ARG;
   if (l->cell_packing < 0 || l->cell_packing > 1) return WECT_ERR_ARG;
   if (l->stage_entries < 0 || l->stage_entries > 1024 || l->stage_entries % 64 != 0) return WECT_ERR_ARG;
   g_stage.store(l->stage_entries);

@@ -47,6 +47,9 @@ struct Params {
   int32_t G;             // blocks of the main kernel
   int64_t S;             // stream length: sum over groups of the stream elements
   int32_t stage;         // staged entries per tile (<= blockDim.x)
+  int32_t stage_vox;     // cubical forward with voxel records: voxels per tile, stage < stage_vox <=
+                         // min(2 stage, 2 blockDim.x) (two per thread; the contributing ones past the
+                         // stage go in a second round); otherwise 0 (one voxel per thread, stage of them)
   int32_t dg;            // backward: direction tiles held in LDS at once
   int32_t ngroups_dir;   // backward: number of direction groups ( = ceil(ntiles / dg) )
   void* partial;         // forward: [slots][T][64] uint32 (integer weights) / uint64 (fixed point)

@@ -241,15 +241,15 @@ def test_cubical_records_add_16_bytes_per_voxel(lib):
     c.shape, c.axis, c.intensity, c.total_voxels = FAKE, FAKE, FAKE, 5000
     try:
         ws = {}
-        for rec in (0, 1, 2):
+        for rec in (0, 1, 2, 3):
             assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, rec))) == L.WECT_OK
             ws[rec] = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(_grid(d=130, T=40)), 0)
-        assert ws[0] == ws[2] == ws[1] + (5000 * 16 + 255) // 256 * 256
+        assert ws[0] == ws[2] == ws[3] == ws[1] + (5000 * 16 + 255) // 256 * 256
         assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 0))) == L.WECT_OK
         one = lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(_grid(d=64, T=40)), 0)
         assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 1))) == L.WECT_OK
         assert lib.wect_workspace_bytes(ctypes.byref(c), ctypes.byref(_grid(d=64, T=40)), 0) == one
-        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 3))) == L.WECT_ERR_ARG
+        assert lib.wect_set_launch(ctypes.byref(L.WectLaunch(512, 1, 64, 1, 0, 0, 4))) == L.WECT_ERR_ARG
     finally:
         lib.wect_set_launch(ctypes.byref(before))
 

@@ -357,7 +357,7 @@ def test_random_launch_knobs_give_identical_bits(W):
                 knobs = dict(block=int(g.choice([0, 256, 512, 1024])), blocks_per_cu=int(g.choice([0, 1, 2])),
                              min_items_per_block=int(g.choice([0, 64, 5000])), decomposition=int(g.choice([0, 1, 2])),
                              threshold_tile=int(g.choice([0, 7, 33, 64])),
-                             directions_per_lane=int(g.choice([0, 1, 2])), cubical_records=int(g.choice([0, 1, 2])),
+                             directions_per_lane=int(g.choice([0, 1, 2])), cubical_records=int(g.choice([0, 1, 2, 3])),
                              cell_packing=int(g.choice([0, 1])), stage_entries=int(g.choice([0, 64, 192, 448, 1024])))
                 _say(f"case {ci} trial {trial}: {knobs}")
                 W.set_launch(**knobs)
@@ -387,12 +387,38 @@ def test_cubical_sparse_volumes_empty_staging_tiles(W):
     try:
         for knobs in (dict(), dict(decomposition=W.DECOMP_STREAM, min_items_per_block=64),
                       dict(decomposition=W.DECOMP_STREAM, min_items_per_block=64, cubical_records=1),
-                      dict(cubical_records=2, stage_entries=64, threshold_tile=17)):
+                      dict(cubical_records=2, stage_entries=64, threshold_tile=17),
+                      dict(cubical_records=3, decomposition=W.DECOMP_STREAM, min_items_per_block=64)):
             _say(f"sparse volumes {knobs}")
             W.set_launch(**knobs)
             got = gpu_wect(W, vols, dirs, thr)
             for b, C in enumerate(vols):
                 assert_match(got[b], refs[b], C, f"{knobs} volume {b}")
+    finally:
+        W.set_launch()
+
+
+def test_cubical_two_voxels_per_thread_overflow(W):
+    """Records with two voxels per thread (cubical_records = 3) on dense
+    volumes and images, where nearly every voxel contributes, so that the
+    stage overflows in every tile and the second round carries the rest: the
+    oracle's values, at the automatic stage and at a small one, in group and
+    stream mode."""
+    vols = [synth.random_tiny_cubical(40 + s, shp, include_above=-1) for s, shp in
+            enumerate(((20, 18, 23), (31, 7, 12), (9, 40, 10)))]
+    ims = [synth.random_tiny_cubical(50 + s, shp, include_above=-1) for s, shp in enumerate(((45, 38), (60, 29)))]
+    cases = ((vols, synth.fibonacci_directions(200), synth.uniform_thresholds(60, 2.0)),
+             (ims, synth.s1_directions(150), synth.uniform_thresholds(40, 1.7)))
+    try:
+        for ci, (Cs, dirs, thr) in enumerate(cases):
+            refs = [oracle.wect(C, dirs, thr) for C in Cs]
+            for knobs in (dict(cubical_records=3), dict(cubical_records=3, stage_entries=128),
+                          dict(cubical_records=3, decomposition=W.DECOMP_STREAM, min_items_per_block=64)):
+                _say(f"two voxels per thread, case {ci}: {knobs}")
+                W.set_launch(**knobs)
+                got = gpu_wect(W, Cs, dirs, thr)
+                for b, C in enumerate(Cs):
+                    assert_match(got[b], refs[b], C, f"case {ci} {knobs} complex {b}")
     finally:
         W.set_launch()
 
