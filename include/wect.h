@@ -434,8 +434,8 @@ const char* wect_status_string(wect_status s);
  *   tile covers 1.5 staging tiles of voxels, two per thread, and the
  *   contributing ones that do not fit the stage go in a second round of the
  *   same tile (fewer tiles and block barriers per voxel); automatic does this
- *   when every block walks at least 16 tiles.  wect_forward_noalloc never uses
- *   records.
+ *   for volumes (n = 3) when every block walks at least 16 tiles.
+ *   wect_forward_noalloc never uses records.
  * cell_packing: 0 = automatic, 1 = off.  With at most 32 directions (or
  *   filter columns of the general-filter WECF) the simplicial forward packs
  *   64 / dt cells into each wavefront instruction, dt being the smallest

@@ -443,11 +443,13 @@ wect_status make_plan(const wect_complex* c, const wect_grid* g, bool need_fwd, 
       pl->rec_bytes = align256((size_t)c->total_voxels * (c->n == 3 ? 16 : 8));
     // With records, a tile of 1.5 stages of voxels (two per thread, the
     // contributing ones past the stage in a second round) means fewer tiles
-    // and block barriers per voxel; automatic when every block walks many
-    // tiles (measured on MI355X: 16 volumes 64^3 - 192^3 at d = 512, 3.31 ->
-    // 3.27 ms; 3 volumes of sides 9 - 40, 34 -> 36 us, hence the bound)
+    // and block barriers per voxel; automatic for volumes whose blocks walk
+    // many tiles (measured on MI355X: 16 volumes 64^3 - 192^3 at d = 512, 3.31
+    // -> 3.27 ms; 3 volumes of sides 9 - 40, 34 -> 36 us, hence the bound; 256
+    // images 128^2 at T = 1000, 0.23 -> 0.25 ms, hence volumes only)
     if (pl->rec_bytes)
-      pl->two_vox = rec_knob == 3 || (rec_knob == 0 && pl->S_fwd >= 16 * (int64_t)pl->stage_fwd * std::max(1, pl->G_fwd));
+      pl->two_vox = rec_knob == 3 || (rec_knob == 0 && c->n == 3 &&
+                                       pl->S_fwd >= 16 * (int64_t)pl->stage_fwd * std::max(1, pl->G_fwd));
     pl->ws_fwd = pl->partial_bytes + pl->dsum_bytes + pl->absmax_bytes + pl->rec_bytes;
     p.nabsmax = absmax ? wect::kAbsmaxSlots : 0;
     p.cells_total = (double)std::max<int64_t>(cells, 1);
